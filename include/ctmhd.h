@@ -1,0 +1,160 @@
+/* ctmhd.h -- C ABI of libctmhd: one second-order constrained-transport MHD
+ * time step on periodic Cartesian boxes, on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Kriel et al., "Magnetising the Quokka code with fast,
+ * second-order accurate, error-correcting schemes for MHD on GPUs":
+ *   - state: cell-centred (rho, rho u, e_tot) and the face-centred normal
+ *     magnetic field (Sec. 2.1, eq. state:conserved);
+ *   - fluxes: PC / PLM / PPM reconstruction of the primitives and the HLLD
+ *     Riemann solver with an HLL fallback, or LLF (Sec. 2.2);
+ *   - edge EMFs: the Q26 scheme (eqs. emf:q26-facevel, emf:q26) or the B25a /
+ *     FS18 schemes (eqs. emf:b25a-*, emf:fs18*), combined by LD04 averaging
+ *     (eq. emf:ld04) with edge wavespeeds (eq. emf:alpha-edge);
+ *   - constant Ohmic resistivity: eta j added to the EMF and the Joule energy
+ *     flux (Sec. 2.4, eqs. resistivity:*);
+ *   - RK2-SSP with first-order flux correction (Sec. 2.5, eqs.
+ *     rk:increment-state, rk:increment-bfield, rk1:update, rk2:update).
+ *
+ * Data layout (every array is caller-owned DEVICE memory, float64):
+ *   A box has n[3] interior cells and ng ghost layers on every side; each of
+ *   the 8 fields is a contiguous (n2+2ng)(n1+2ng)(n0+2ng) array with x0
+ *   fastest.  Cell fields: rho, m0, m1, m2, e_tot.  Face field b_a[i,j,k] is
+ *   the x_a-face on the LOWER side of cell (i,j,k).  Boundaries are periodic;
+ *   ghost layers are library scratch and hold the periodic copy on return.
+ *
+ * Streams and ownership: every call is enqueued on `stream` (a hipStream_t,
+ * NULL for the default stream) and returns without synchronising.  The
+ * library allocates and frees nothing: all scratch lives in the caller's
+ * `workspace` of at least ctmhd_workspace_bytes() bytes (256-byte aligned).
+ * dt values and diagnostic counters stay on the device.
+ *
+ * Errors: calls return CTMHD_OK (0) or a negative code; ctmhd_last_error()
+ * gives a static description of the last failure on the calling thread.
+ * Numerical faults are reported asynchronously through `diag`.
+ */
+#ifndef CTMHD_H_
+#define CTMHD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* reconstruction (Sec. 2.2) */
+#define CTMHD_RECON_PC 0
+#define CTMHD_RECON_PLM_MC 1
+#define CTMHD_RECON_PLM_MINMOD 2
+#define CTMHD_RECON_PPM 3
+/* Riemann solver (Sec. 2.2) */
+#define CTMHD_RIEMANN_HLLD 0
+#define CTMHD_RIEMANN_LLF 1
+/* EMF compute scheme (Sec. 2.3.1) */
+#define CTMHD_EMF_Q26 0
+#define CTMHD_EMF_B25A 1
+#define CTMHD_EMF_FS18 2
+/* EMF averaging scheme (Sec. 2.3.2) */
+#define CTMHD_AVG_LD04 0
+/* invalid-state criteria for first-order flux correction (Sec. 2.5) */
+#define CTMHD_FLAG_RHO 1       /* rho <= 0 */
+#define CTMHD_FLAG_P 2         /* p <= 0 */
+#define CTMHD_FLAG_NONFINITE 4 /* any non-finite value */
+/* arithmetic form */
+#define CTMHD_FP64 0           /* everything in float64 */
+#define CTMHD_FP32 1           /* stencil in float32; pressure recovery, dt and
+                                  the state / face-b accumulation in float64 */
+/* dt mode of the batched call */
+#define CTMHD_DT_GLOBAL 0
+#define CTMHD_DT_PER_BOX 1
+
+/* status codes */
+#define CTMHD_OK 0
+#define CTMHD_EARG (-1)        /* bad argument (sizes, ghosts, CFL, pointers) */
+#define CTMHD_EUNSUPPORTED (-2)/* scheme combination not built */
+#define CTMHD_EHIP (-3)        /* a HIP launch or runtime call failed */
+
+typedef struct ctmhd_params {
+  double gamma;          /* adiabatic index, > 1 */
+  double eta;            /* constant Ohmic resistivity, >= 0 */
+  double cfl;            /* CFL number in (0, 1); < 1/3 when eta > 0 (eq. resistivity:cfl) */
+  int32_t recon;         /* CTMHD_RECON_* */
+  int32_t riemann;       /* CTMHD_RIEMANN_* */
+  int32_t emf_compute;   /* CTMHD_EMF_* */
+  int32_t emf_average;   /* CTMHD_AVG_LD04 */
+  int32_t fofc;          /* 1: first-order flux correction on, 0: off */
+  int32_t flag_criteria; /* OR of CTMHD_FLAG_* */
+  int32_t precision;     /* CTMHD_FP64 or CTMHD_FP32 */
+  int32_t reserved;      /* must be 0 */
+  /* Test hook: NULL, or a DEVICE mask of 2 * n0*n1*n2 bytes (stage-1 mask then
+   * stage-2 mask, interior cells, x0 fastest) OR-ed into the invalid-cell
+   * flags of every step.  Single-box call only. */
+  const uint8_t* force_flags;
+} ctmhd_params;
+
+typedef struct ctmhd_box {
+  int32_t n[3];    /* interior cells per axis, >= 1 */
+  int32_t ng;      /* ghost layers, >= ctmhd_required_ghosts() */
+  double dx[3];    /* cell widths, > 0 */
+  int64_t offset;  /* element offset of this box in the packed arrays (batched call) */
+} ctmhd_box;
+
+/* Ghost layers the scheme needs: reconstruction half-width + 2 (PC 2, PLM 3,
+ * PPM 4).  Returns a negative code for bad parameters. */
+int ctmhd_required_ghosts(const ctmhd_params* p);
+
+/* Elements (not bytes) of one field array of a box: prod(n_d + 2 ng). */
+int64_t ctmhd_box_elems(const ctmhd_box* box);
+
+/* Workspace bytes for ctmhd_step (nbox = 1) or ctmhd_step_batched. */
+size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox);
+
+/* Advance one box by `nsteps` RK2 steps (Sec. 2.5).
+ *   cons[5]  : host array of 5 device pointers (rho, m0, m1, m2, e_tot), in/out
+ *   bface[3] : host array of 3 device pointers (b0, b1, b2), in/out
+ *   dt_fixed : device, nsteps values used as dt, or NULL for the CFL dt
+ *              computed from each step's starting state (eq. resistivity:cfl)
+ *   dt_out   : device, nsteps values written, or NULL
+ *   diag     : device, 4*nsteps int64 written per step: [cells flagged in
+ *              stage 1, cells flagged in stage 2, HLL fallbacks, non-finite
+ *              dt (1: the step and all later steps were skipped)], or NULL
+ * The discrete divergence of the face field is preserved to round-off. */
+int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
+               double* const bface[3], int nsteps, const double* dt_fixed, double* dt_out,
+               int64_t* diag, void* workspace, size_t ws_bytes, void* stream);
+
+/* Advance `nbox` independent periodic boxes of different sizes by `nsteps`
+ * steps in one persistent launch per step.  Box b's 8 fields start at element
+ * boxes[b].offset of the packed arrays cons[m] / bface[a] (each box is laid
+ * out as in ctmhd_step).  `boxes` is a HOST array.  dt_mode CTMHD_DT_GLOBAL:
+ * one dt = min over boxes (every box must share dx); CTMHD_DT_PER_BOX: each
+ * box its own CFL dt.  dt_fixed / dt_out hold nsteps values (global) or
+ * nsteps*nbox values (per box, step-major).  diag as in ctmhd_step, summed
+ * over boxes. */
+int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes,
+                       double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
+                       const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
+                       size_t ws_bytes, void* stream);
+
+/* Reverse-mode derivative (vector-Jacobian product) of ONE step of
+ * ctmhd_step with a frozen dt and no flux correction taken:
+ * given S^n (cons_n, bface_n; ghosts need not be filled) and dL/dS^{n+1}
+ * (g_cons, g_bface, interior values; ghosts ignored), writes dL/dS^n into
+ * g_cons_out / g_bface_out (interior; ghosts zeroed).  dt: device scalar.
+ * Supports FP64 and FP32 forms with PC / PLM reconstruction, HLLD or LLF,
+ * Q26, LD04 and eta >= 0. */
+int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,
+                       const double* const cons_n[5], const double* const bface_n[3],
+                       const double* dt, const double* const g_cons[5],
+                       const double* const g_bface[3], double* const g_cons_out[5],
+                       double* const g_bface_out[3], void* workspace, size_t ws_bytes,
+                       void* stream);
+
+/* Static description of the last error on this thread ("" if none). */
+const char* ctmhd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTMHD_H_ */

@@ -1,0 +1,242 @@
+"""Python binding of libctmhd (ctypes).  Argument marshalling only: every step
+of the method runs in the HIP kernels of the library.  PyTorch provides the
+device memory and the stream.
+
+The library must have been built (``python -m paper_2609_10816_amd.build`` or
+``__graft_entry__.build()``); without it every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctmhd.so")
+
+RECON = {"pc": 0, "plm": 1, "plm_mc": 1, "plm_minmod": 2, "ppm": 3}
+RIEMANN = {"hlld": 0, "llf": 1}
+EMF = {"q26": 0, "b25a": 1, "fs18": 2}
+PRECISION = {"fp64": 0, "fp32": 1}
+DT_GLOBAL, DT_PER_BOX = 0, 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("eta", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("recon", ctypes.c_int32), ("riemann", ctypes.c_int32),
+                ("emf_compute", ctypes.c_int32), ("emf_average", ctypes.c_int32),
+                ("fofc", ctypes.c_int32), ("flag_criteria", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("force_flags", ctypes.c_void_p)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ng", ctypes.c_int32), ("dx", ctypes.c_double * 3),
+                ("offset", ctypes.c_int64)]
+
+
+_lib = None
+_P = ctypes.POINTER(Params)
+_B = ctypes.POINTER(Box)
+_vp = ctypes.c_void_p
+_PTR5 = ctypes.c_void_p * 5
+_PTR3 = ctypes.c_void_p * 3
+
+
+class CtmhdError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libctmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CtmhdError(f"{LIB_PATH} is missing: build it first (paper_2609_10816_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ctmhd_required_ghosts.argtypes = [_P]
+        L.ctmhd_required_ghosts.restype = ctypes.c_int
+        L.ctmhd_box_elems.argtypes = [_B]
+        L.ctmhd_box_elems.restype = ctypes.c_int64
+        L.ctmhd_workspace_bytes.argtypes = [_P, _B, ctypes.c_int]
+        L.ctmhd_workspace_bytes.restype = ctypes.c_size_t
+        L.ctmhd_step.argtypes = [_P, _B, _PTR5, _PTR3, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                 ctypes.c_size_t, _vp]
+        L.ctmhd_step.restype = ctypes.c_int
+        L.ctmhd_step_batched.argtypes = [_P, ctypes.c_int, _B, _PTR5, _PTR3, ctypes.c_int,
+                                         ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.ctmhd_step_batched.restype = ctypes.c_int
+        L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
+                                         _vp, ctypes.c_size_t, _vp]
+        L.ctmhd_step_adjoint.restype = ctypes.c_int
+        L.ctmhd_last_error.argtypes = []
+        L.ctmhd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
+            "ctmhd_step_batched", "ctmhd_step_adjoint", "ctmhd_last_error")
+
+
+def _check(rc):
+    if rc != 0:
+        raise CtmhdError(f"libctmhd error {rc}: {lib().ctmhd_last_error().decode()}")
+    return rc
+
+
+def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", emf="q26",
+                fofc=True, flag_mask=7, precision="fp64", force_flags=None) -> Params:
+    ff = None
+    if force_flags is not None:
+        ff = force_flags.data_ptr()
+    return Params(float(gamma), float(eta), float(cfl), RECON[recon], RIEMANN[riemann], EMF[emf],
+                  0, int(bool(fofc)), int(flag_mask), PRECISION[precision], 0, ff)
+
+
+def make_box(n, ng, dx, offset=0) -> Box:
+    return Box((ctypes.c_int32 * 3)(*[int(v) for v in n]), int(ng),
+               (ctypes.c_double * 3)(*[float(v) for v in dx]), int(offset))
+
+
+def required_ghosts(params: Params) -> int:
+    r = lib().ctmhd_required_ghosts(ctypes.byref(params))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def workspace_bytes(params: Params, boxes) -> int:
+    if isinstance(boxes, Box):
+        boxes = [boxes]
+    arr = (Box * len(boxes))(*boxes)
+    return int(lib().ctmhd_workspace_bytes(ctypes.byref(params), arr, len(boxes)))
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def ctmhd_step(params: Params, box: Box, cons, bface, nsteps, dt_fixed=None, dt_out=None,
+               diag=None, workspace=None, stream=None):
+    """Direct binding of ctmhd_step; tensors are device tensors (float64 /
+    int64 / uint8 workspace)."""
+    ws = workspace
+    rc = lib().ctmhd_step(ctypes.byref(params), ctypes.byref(box),
+                          _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
+                          int(nsteps), _p(dt_fixed), _p(dt_out), _p(diag), _p(ws),
+                          ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+def ctmhd_step_batched(params: Params, boxes, cons, bface, nsteps, dt_mode=DT_GLOBAL,
+                       dt_fixed=None, dt_out=None, diag=None, workspace=None, stream=None):
+    arr = (Box * len(boxes))(*boxes)
+    ws = workspace
+    rc = lib().ctmhd_step_batched(ctypes.byref(params), len(boxes), arr,
+                                  _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
+                                  int(nsteps), int(dt_mode), _p(dt_fixed), _p(dt_out), _p(diag),
+                                  _p(ws), ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+def ctmhd_step_adjoint(params: Params, box: Box, cons_n, bface_n, dt, g_cons, g_bface,
+                       g_cons_out, g_bface_out, workspace=None, stream=None):
+    ws = workspace
+    rc = lib().ctmhd_step_adjoint(ctypes.byref(params), ctypes.byref(box),
+                                  _PTR5(*[_p(t) for t in cons_n]), _PTR3(*[_p(t) for t in bface_n]),
+                                  _p(dt), _PTR5(*[_p(t) for t in g_cons]),
+                                  _PTR3(*[_p(t) for t in g_bface]),
+                                  _PTR5(*[_p(t) for t in g_cons_out]),
+                                  _PTR3(*[_p(t) for t in g_bface_out]), _p(ws),
+                                  ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+# ---------------------------------------------------------------------------
+# Device state of one box and convenience wrappers.
+# ---------------------------------------------------------------------------
+class BoxState:
+    """The 8 float64 fields of one ghosted box as device tensors."""
+
+    def __init__(self, n, ng, dx, device="cuda"):
+        import torch
+        self.n = tuple(int(v) for v in n)
+        self.ng = int(ng)
+        self.dx = tuple(float(v) for v in dx)
+        shape = tuple(v + 2 * self.ng for v in self.n[::-1])
+        self.cons = [torch.zeros(shape, dtype=torch.float64, device=device) for _ in range(5)]
+        self.bface = [torch.zeros(shape, dtype=torch.float64, device=device) for _ in range(3)]
+        self.box = make_box(self.n, self.ng, self.dx)
+
+    @classmethod
+    def from_numpy(cls, cons, bface, ng, dx, device="cuda"):
+        """Interior arrays (5|3, n2, n1, n0) -> ghosted device box (ghosts are
+        filled by the library at the start of each step)."""
+        import torch
+        n2, n1, n0 = cons.shape[1:]
+        st = cls((n0, n1, n2), ng, dx, device)
+        g = st.ng
+        sl = (slice(g, g + n2), slice(g, g + n1), slice(g, g + n0))
+        for m in range(5):
+            st.cons[m][sl] = torch.from_numpy(np.ascontiguousarray(cons[m])).to(device)
+        for a in range(3):
+            st.bface[a][sl] = torch.from_numpy(np.ascontiguousarray(bface[a])).to(device)
+        return st
+
+    def interior(self):
+        g = self.ng
+        n0, n1, n2 = self.n
+        return (slice(g, g + n2), slice(g, g + n1), slice(g, g + n0))
+
+    def to_numpy(self):
+        sl = self.interior()
+        c = np.stack([t[sl].cpu().numpy() for t in self.cons])
+        b = np.stack([t[sl].cpu().numpy() for t in self.bface])
+        return c, b
+
+
+class Stepper:
+    """Holds the workspace for one box and one parameter set."""
+
+    def __init__(self, params: Params, state: BoxState):
+        import torch
+        self.params = params
+        self.state = state
+        nbytes = workspace_bytes(params, state.box)
+        if nbytes == 0:
+            raise CtmhdError("workspace size query failed")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=state.cons[0].device)
+        if self.workspace.data_ptr() % 256:
+            raise CtmhdError("workspace allocation is not 256-byte aligned")
+
+    def step(self, nsteps=1, dt_fixed=None, dt_out=None, diag=None, stream=None):
+        ctmhd_step(self.params, self.state.box, self.state.cons, self.state.bface, nsteps,
+                   dt_fixed, dt_out, diag, self.workspace, stream)
+
+
+def run(params: Params, cons, bface, dx, nsteps=1, dt_fixed=None, ng=None, device="cuda"):
+    """Convenience: numpy interior state in, numpy interior state out, with
+    the per-step dt values and diagnostics."""
+    import torch
+    if ng is None:
+        ng = required_ghosts(params)
+    st = BoxState.from_numpy(cons, bface, ng, dx, device)
+    S = Stepper(params, st)
+    dts = torch.zeros(nsteps, dtype=torch.float64, device=device)
+    diag = torch.zeros(4 * nsteps, dtype=torch.int64, device=device)
+    dtf = None
+    if dt_fixed is not None:
+        dtf = torch.as_tensor(np.broadcast_to(np.asarray(dt_fixed, np.float64), (nsteps,)).copy(),
+                              device=device)
+    S.step(nsteps, dtf, dts, diag)
+    torch.cuda.synchronize()
+    c, b = st.to_numpy()
+    return c, b, dts.cpu().numpy(), diag.cpu().numpy().reshape(nsteps, 4)

@@ -1,0 +1,78 @@
+"""The C-ABI library loads on the host and exports every symbol that
+include/ctmhd.h declares; argument validation happens before any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2609_10816_amd import ctmhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ctmhd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctmhd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert "ctmhd_step" in names and "ctmhd_step_batched" in names and "ctmhd_step_adjoint" in names
+    L = ctypes.CDLL(ctmhd.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(ctmhd.EXPORTED) == set(names)
+
+
+def test_required_ghosts():
+    for recon, g in [("pc", 2), ("plm", 3), ("plm_minmod", 3), ("ppm", 4)]:
+        assert ctmhd.required_ghosts(ctmhd.make_params(recon=recon)) == g
+
+
+def test_box_elems_and_workspace():
+    p = ctmhd.make_params(recon="ppm")
+    b = ctmhd.make_box((10, 7, 3), 4, (0.1, 0.2, 0.3))
+    assert ctmhd.lib().ctmhd_box_elems(ctypes.byref(b)) == 18 * 15 * 11
+    ws64 = ctmhd.workspace_bytes(p, b)
+    ws32 = ctmhd.workspace_bytes(ctmhd.make_params(recon="ppm", precision="fp32"), b)
+    assert ws64 > ws32 > 0
+
+
+def _call_step(p, b, nsteps=1):
+    L = ctmhd.lib()
+    dummy = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    cons = ctmhd._PTR5(*([dummy.value] * 5))
+    bf = ctmhd._PTR3(*([dummy.value] * 3))
+    return L.ctmhd_step(ctypes.byref(p), ctypes.byref(b), cons, bf, nsteps, None, None, None,
+                        None, 0, None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(gamma=1.0), dict(eta=-1.0), dict(cfl=0.0), dict(cfl=1.2), dict(eta=1e-3, cfl=0.4),
+])
+def test_bad_params_rejected(bad):
+    kw = dict(recon="plm")
+    kw.update(bad)
+    p = ctmhd.make_params(**kw)
+    b = ctmhd.make_box((8, 8, 8), 3, (0.1, 0.1, 0.1))
+    assert _call_step(p, b) == -1
+    assert ctmhd.lib().ctmhd_last_error()
+
+
+def test_bad_box_rejected():
+    p = ctmhd.make_params(recon="ppm")
+    assert _call_step(p, ctmhd.make_box((8, 8, 8), 3, (0.1, 0.1, 0.1))) == -1  # ng < 4
+    assert b"ghost" in ctmhd.lib().ctmhd_last_error()
+    assert _call_step(p, ctmhd.make_box((8, 0, 8), 4, (0.1, 0.1, 0.1))) == -1
+    assert _call_step(p, ctmhd.make_box((8, 8, 8), 4, (0.1, -1.0, 0.1))) == -1
+    # workspace missing
+    assert _call_step(p, ctmhd.make_box((8, 8, 8), 4, (0.1, 0.1, 0.1))) == -1
+    assert b"workspace" in ctmhd.lib().ctmhd_last_error()
+
+
+def test_unsupported_averaging():
+    p = ctmhd.make_params()
+    p.emf_average = 1
+    assert _call_step(p, ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3)) == -2
