@@ -1,17 +1,30 @@
 """Throughput of the CT-MHD step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb128|turb256|turb512]
-                [--precision fp64|fp32] [--emf q26|b25a] [--no-cpu-baseline]
+                [--precision fp64|fp32] [--emf q26|b25a|fs18] [--no-cpu-baseline]
+                [--no-fp32] [--copy-calibration]
 
-Prints one JSON line.  A step is one full RK2-SSP step with first-order flux
-correction (dt reduction, ghost wrap, both stages: primitives,
-reconstruction, Riemann fluxes, edge EMFs, LD04, Ohmic terms, CT and
-conserved updates, invalid-state flagging) on a seeded synthetic state
-resident in HBM.
+Prints ONE JSON line.  A step is one full RK2-SSP step with first-order flux
+correction on a seeded synthetic state already resident in HBM: CFL dt
+reduction, ghost wrap, and for both stages primitives, reconstruction, HLLD
+fluxes, edge EMFs, LD04 averaging, Ohmic terms, CT and conserved updates and
+invalid-state flagging.  `value` is FP64 cell-updates per second of the
+default workload (the 128^3 Mach-5 turbulent box, PPM + HLLD + Q26 + LD04).
+
+roofline: the dominant kernel is the face kernel (reconstruction + HLLD at
+every x_a face of one stage).  Its algorithmic work is face_flops (from
+tests/golden/flops_per_unit.json, the oracle's operation count with each
+reconstruction charged once) times the n^3 interior faces one launch
+resolves; its duration is measured with HIP events recorded by the library
+around every launch inside the timed region.  The path is bound by FP64
+vector ALU throughput (peak 78.6 TFLOP/s on MI355X), not by HBM.
+traffic: HBM bytes per launch from the committed rocprofv3 counter summary
+of the same kernel source, or null if the kernel source has changed since.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,13 +36,116 @@ sys.path.insert(0, ROOT)
 CONFIGS = {
     # the 128^3 driven-free turbulent box: rms Mach 5, b = (0.1,0,0) + curl A, PPM
     "turb128": dict(n=128, recipe="turbulent_mach5", recon="ppm", eta=0.0,
-                    name="turbulent-box-128^3-mach5"),
+                    name="turbulent-box-128^3-mach5-ppm"),
     # the throughput sweep: rms Mach 2, beta 1, eta 1e-3, PPM
     "turb256": dict(n=256, recipe="turbulent_mach2_beta1", recon="ppm", eta=1e-3,
-                    name="turbulent-box-256^3-mach2-beta1-eta1e-3"),
+                    name="turbulent-box-256^3-mach2-beta1-eta1e-3-ppm"),
     "turb512": dict(n=512, recipe="turbulent_mach2_beta1", recon="ppm", eta=1e-3,
-                    name="turbulent-box-512^3-mach2-beta1-eta1e-3"),
+                    name="turbulent-box-512^3-mach2-beta1-eta1e-3-ppm"),
 }
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+ALG_BYTES_PER_CELL_UPDATE = 128.0  # 8 float64 fields read + written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_face_kernel.txt")
+FLOPS_FILE = os.path.join(ROOT, "tests", "golden", "flops_per_unit.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_10816_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(config, precision, emf):
+    """Per-launch HBM bytes of the face kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    key = f"{config}/{precision}/{emf}"
+    v = kv.get(f"bytes_per_launch[{key}]")
+    return float(v) if v else None
+
+
+def run_gpu(cfg, precision, emf, K, W, timer_pairs=0, copy_calibration=False):
+    import torch
+
+    from paper_2609_10816_amd import ctmhd, inputs
+
+    t0 = time.time()
+    cons, bf, info = getattr(inputs, cfg["recipe"])(cfg["n"])
+    log(f"input {cfg['name']} generated in {time.time() - t0:.1f}s")
+    P = ctmhd.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3,
+                          precision=precision)
+    ng = ctmhd.required_ghosts(P)
+    st = ctmhd.BoxState.from_numpy(cons, bf, ng, info["dx"])
+    S = ctmhd.Stepper(P, st)
+    dev = st.cons[0].device
+    if copy_calibration:
+        # a plain copy of known size (1 GiB read + 1 GiB written) for scaling
+        # the HBM byte counters of a profiler run
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    dts = torch.zeros(max(K, W, 1), dtype=torch.float64, device=dev)
+    diag = torch.zeros(4 * max(K, W, 1), dtype=torch.int64, device=dev)
+    if W:
+        S.step(W, None, dts, diag)
+    torch.cuda.synchronize()
+    timer = ctmhd.KernelTimer(timer_pairs) if timer_pairs else None
+    if timer:
+        timer.start()
+    t1 = time.perf_counter()
+    S.step(K, None, dts, diag)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    kernel_ms = None
+    nlaunch = 0
+    if timer:
+        nlaunch = timer.stop()
+        d = timer.durations_ms(nlaunch)
+        kernel_ms = sum(d) / len(d) if d else None
+        timer.close()
+    dg = diag[: 4 * K].view(K, 4).cpu().numpy()
+    res = dict(elapsed=el, kernel_ms=kernel_ms, nlaunch=nlaunch,
+               flagged=int(dg[:, :2].sum()), hll=int(dg[:, 2].sum()),
+               dt_first=float(dts[0].item()))
+    del S, st
+    torch.cuda.empty_cache()
+    return res, (cons, bf, info)
+
+
+def cpu_baseline(cfg, emf, state):
+    """The oracle (plain FP64 C++, OpenMP over z-planes) on one step of the
+    same state."""
+    import oracle
+    cons, bf, info = state
+    Q = oracle.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3)
+    t0 = time.perf_counter()
+    oracle.step(Q, cons, bf, info["dx"], nsteps=1)
+    el = time.perf_counter() - t0
+    n3 = cfg["n"] ** 3
+    return {"value": n3 / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 step of the full {cfg['n']}^3 box ({n3 / 1e6:.2f} M cell-updates), "
+                      f"{el:.1f} s"}
 
 
 def main():
@@ -41,42 +157,30 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--emf", default="q26", choices=["q26", "b25a", "fs18"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+              "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_2609_10816_amd import ctmhd, inputs
+    rank = int(os.environ.get("RANK", "0"))
 
     cfg = CONFIGS[args.config]
-    t0 = time.time()
-    cons, bf, info = getattr(inputs, cfg["recipe"])(cfg["n"])
-    print(f"[bench] input {cfg['name']} generated in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-    P = ctmhd.make_params(recon=cfg["recon"], emf=args.emf, eta=cfg["eta"], cfl=0.3,
-                          precision=args.precision)
-    ng = ctmhd.required_ghosts(P)
-    st = ctmhd.BoxState.from_numpy(cons, bf, ng, info["dx"])
-    del cons, bf
-    S = ctmhd.Stepper(P, st)
-    dev = st.cons[0].device
     K, W = args.steps, args.warmup
-    dts = torch.zeros(max(K, W, 1), dtype=torch.float64, device=dev)
-    diag = torch.zeros(4 * max(K, W, 1), dtype=torch.int64, device=dev)
-    if W:
-        S.step(W, None, dts, diag)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    S.step(K, None, dts, diag)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
-    ncell = cfg["n"] ** 3
-    value = ncell * K / el / 1e6
-    dg = diag[: 4 * K].view(K, 4).cpu().numpy()
+    n3 = cfg["n"] ** 3
+    res, state = run_gpu(cfg, args.precision, args.emf, K, W, timer_pairs=64 * K,
+                         copy_calibration=args.copy_calibration)
+    value = n3 * K / res["elapsed"] / 1e6
+    log(f"{args.precision}: {value:.1f} Mcell-updates/s, face kernel "
+        f"{res['kernel_ms']:.4f} ms avg over {res['nlaunch']} launches")
+
+    flops_tab = json.load(open(FLOPS_FILE))["entries"]
+    fkey = f"{cfg['recon']}/{args.emf}/eta{'>0' if cfg['eta'] > 0 else '=0'}"
+    face_flops = flops_tab[fkey]["face_flops"]
+    cell_update_flops = flops_tab[fkey]["cell_update_flops"]
+    achieved = face_flops * n3 / (res["kernel_ms"] * 1e-3) / 1e12
+    traffic = read_traffic(args.config, args.precision, args.emf)
     out = {
         "metric": "Mcell-updates/s on 1 MI355X",
         "value": value,
@@ -84,18 +188,33 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": el / K * 1e3,
+        "ms_per_step": res["elapsed"] / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "recon": cfg["recon"], "riemann": "hlld",
-                   "emf": args.emf, "averaging": "ld04", "fofc": True, "cfl": 0.3,
-                   "eta": cfg["eta"], "precision": args.precision},
-        "fofc_flagged_cells": int(dg[:, :2].sum()),
-        "hll_fallbacks": int(dg[:, 2].sum()),
+        "config": {"workload": cfg["name"], "cells": n3, "recon": cfg["recon"],
+                   "riemann": "hlld", "emf": args.emf, "averaging": "ld04", "fofc": True,
+                   "cfl": 0.3, "eta": cfg["eta"], "precision": args.precision},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "face (reconstruction + Riemann, one direction, one stage)",
+                     "kernel_ms": res["kernel_ms"], "flops_per_face": face_flops,
+                     "faces_per_launch": n3},
+        "step_alu_frac": value * 1e6 * cell_update_flops / (PEAK_FP64_TFLOPS * 1e12),
+        "hbm_frac_algorithmic": value * 1e6 * ALG_BYTES_PER_CELL_UPDATE / (PEAK_HBM_GBS * 1e9),
+        "fofc_flagged_cells": res["flagged"],
+        "hll_fallbacks": res["hll"],
+        "paper_context": ">50 M cell-updates/s per GPU (one MI250X GCD, PPM-EP + HLLD + Q26, "
+                         "512^3 on 4 GCDs); context, not the target",
     }
+    if args.precision == "fp64" and not args.no_fp32:
+        r32, _ = run_gpu(cfg, "fp32", args.emf, K, W)
+        v32 = n3 * K / r32["elapsed"] / 1e6
+        out["fp32_form"] = {"value": v32, "unit": "Mcell-updates/s", "speedup": v32 / value}
+    if rank == 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.emf, state)
     print(json.dumps(out), flush=True)
 
 

@@ -150,6 +150,16 @@ int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,
                        double* const g_bface_out[3], void* workspace, size_t ws_bytes,
                        void* stream);
 
+/* Kernel timing hook (for benchmarks).  `events` holds 2*npairs hipEvent_t
+ * handles created by the caller (timing enabled).  During subsequent
+ * ctmhd_step calls in this process the library records pair i
+ * (events[2i] before, events[2i+1] after) around the i-th launch of its face
+ * kernel (reconstruction + Riemann solve, the dominant kernel), for
+ * i < npairs.  ctmhd_profile_recorded() returns the pairs recorded so far.
+ * npairs = 0 (or events = NULL) switches the hook off.  Not thread-safe. */
+int ctmhd_profile_events(void* const* events, int npairs);
+int ctmhd_profile_recorded(void);
+
 /* Static description of the last error on this thread ("" if none). */
 const char* ctmhd_last_error(void);
 

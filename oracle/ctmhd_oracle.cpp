@@ -23,6 +23,8 @@
 //
 // Readings of points the paper leaves open are marked "reading:" below.
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -61,9 +63,10 @@ inline Dual rsqrt_(Dual a) {
 
 // Flop counter.  Counts go to per-phase tallies; phase set by the caller.
 enum { OP_ADD = 0, OP_MUL, OP_DIV, OP_SQRT, OP_CMP, OP_N };
-enum { PH_DT = 0, PH_PRIM, PH_FACE, PH_EMF, PH_UPDATE, PH_FOFC, PH_N };
+enum { PH_DT = 0, PH_PRIM, PH_FACE, PH_EMF, PH_UPDATE, PH_FOFC, PH_RECON, PH_N };
 static int64_t g_count[PH_N][OP_N];
 static int g_phase = 0;
+static int64_t g_recon_calls = 0;  // 1D reconstructions (each gives both faces of a cell)
 struct Count {
   double v = 0.0;
   Count() = default;
@@ -262,7 +265,24 @@ R ppm_interface(R qa, R qb, R qc, R qd) {
 }
 
 template <class R>
+void recon1d_(int method, const R q[5], R& qm, R& qp);
+
+// Counting type: tally reconstruction arithmetic under its own phase.
+template <class R>
 void recon1d(int method, const R q[5], R& qm, R& qp) {
+  if (std::is_same<R, Count>::value) {
+    int save = g_phase;
+    g_phase = PH_RECON;
+    ++g_recon_calls;
+    recon1d_(method, q, qm, qp);
+    g_phase = save;
+  } else {
+    recon1d_(method, q, qm, qp);
+  }
+}
+
+template <class R>
+void recon1d_(int method, const R q[5], R& qm, R& qp) {
   if (method == RECON_PC) { qm = q[2]; qp = q[2]; return; }
   if (method == RECON_PLM_MC || method == RECON_PLM_MINMOD) {
     R s = plm_slope(method, q[1], q[2], q[3]);
@@ -962,12 +982,14 @@ int oracle_step_dual(const Params* P, const int n[3], const double dx[3], double
 }
 
 // Count the arithmetic of one step (dt from the CFL condition included).
-// counts: PH_N x OP_N int64, phases (dt, prim, face, emf, update, fofc) and
-// ops (add/sub, mul, div, sqrt, compare).
+// counts: PH_N x OP_N int64, phases (dt, prim, face, emf, update, fofc,
+// recon) and ops (add/sub, mul, div, sqrt, compare); recon_calls: number of
+// 1D reconstructions performed.
 int oracle_count_step(const Params* P, const int n[3], const double dx[3], const double* cons,
-                      const double* bface, int64_t* counts) {
+                      const double* bface, int64_t* counts, int64_t* recon_calls) {
   Grid g{{n[0], n[1], n[2]}, {dx[0], dx[1], dx[2]}};
   std::memset(g_count, 0, sizeof(g_count));
+  g_recon_calls = 0;
   State<Count> S;
   load_state(g, cons, bface, S);
   g_phase = PH_PRIM;
@@ -980,8 +1002,12 @@ int oracle_count_step(const Params* P, const int n[3], const double dx[3], const
   int64_t dg[4] = {0, 0, 0, 0};
   step(g, *P, S, dt, nullptr, nullptr, dg);
   std::memcpy(counts, g_count, sizeof(g_count));
+  if (recon_calls) *recon_calls = g_recon_calls;
   return 0;
 }
+
+// Threads the parallel loops use.
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 // ---- unit-level entry points used by the pinning tests -------------------
 void oracle_recon1d(int method, const double q[5], double* qm, double* qp) {

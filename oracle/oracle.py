@@ -60,7 +60,7 @@ def lib():
         P = ctypes.POINTER(_Params)
         L.oracle_step.argtypes = [P, _ip, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _lp, _up]
         L.oracle_step_dual.argtypes = [P, _ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
-        L.oracle_count_step.argtypes = [P, _ip, _dp, _dp, _dp, _lp]
+        L.oracle_count_step.argtypes = [P, _ip, _dp, _dp, _dp, _lp, _lp]
         L.oracle_recon1d.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.oracle_hlld.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
         L.oracle_hlld_fan.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
@@ -72,8 +72,14 @@ def lib():
         L.oracle_dt.argtypes = [P, _ip, _dp, _dp, _dp]
         L.oracle_dt.restype = ctypes.c_double
         L.oracle_fluxes.argtypes = [P, _ip, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
 
 
 def _ptr(a, t=_dp):
@@ -139,19 +145,24 @@ def step_dual(params, cons, bface, tcons, tbface, dx, dts):
     return c, b, tc, tb
 
 
-PHASES = ("dt", "prim", "face", "emf", "update", "fofc")
+PHASES = ("dt", "prim", "face", "emf", "update", "fofc", "recon")
 OPS = ("add", "mul", "div", "sqrt", "cmp")
 
 
 def count_step(params, cons, bface, dx):
-    """Arithmetic of one step, as a dict phase -> dict op -> count (whole box)."""
+    """Arithmetic of one step, as a dict phase -> dict op -> count (whole box),
+    plus "recon_calls": the number of 1D reconstructions performed."""
     P = _params(params)
     c = np.ascontiguousarray(cons, dtype=np.float64)
     b = np.ascontiguousarray(bface, dtype=np.float64)
     out = np.zeros((len(PHASES), len(OPS)), np.int64)
     dxa = (ctypes.c_double * 3)(*[float(v) for v in dx])
-    lib().oracle_count_step(ctypes.byref(P), _dims(c), dxa, _ptr(c), _ptr(b), _ptr(out, _lp))
-    return {ph: {op: int(out[i, j]) for j, op in enumerate(OPS)} for i, ph in enumerate(PHASES)}
+    calls = np.zeros(1, np.int64)
+    lib().oracle_count_step(ctypes.byref(P), _dims(c), dxa, _ptr(c), _ptr(b), _ptr(out, _lp),
+                            _ptr(calls, _lp))
+    res = {ph: {op: int(out[i, j]) for j, op in enumerate(OPS)} for i, ph in enumerate(PHASES)}
+    res["recon_calls"] = int(calls[0])
+    return res
 
 
 def recon1d(method, q5):

@@ -860,6 +860,22 @@ int build_work(void* ws, size_t ws_bytes, const ctmhd_box& b, Work<T>& W, State&
   return CTMHD_OK;
 }
 
+// Timing hook state (host only).
+void* const* g_prof_events = nullptr;
+int g_prof_pairs = 0;
+int g_prof_used = 0;
+
+inline void prof_begin(hipStream_t st) {
+  if (g_prof_events && g_prof_used < g_prof_pairs)
+    hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used], st);
+}
+inline void prof_end(hipStream_t st) {
+  if (g_prof_events && g_prof_used < g_prof_pairs) {
+    hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used + 1], st);
+    ++g_prof_used;
+  }
+}
+
 #define LAUNCH(kern, blocks, ...)                                                  \
   do {                                                                             \
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, st, __VA_ARGS__);      \
@@ -871,12 +887,14 @@ template <typename T, int RECON>
 int launch_face(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
                 Range R, int a, int stage, Range upd, long long* diag) {
   if (R.count() <= 0) return CTMHD_OK;
+  prof_begin(st);
   if (p->riemann == CTMHD_RIEMANN_HLLD)
     LAUNCH((k_face<T, RECON, kHLLD>), nblocks(R.count()), S, G, W, R, a, stage, p->gamma, p->eta, upd,
            diag, W.stop);
   else
     LAUNCH((k_face<T, RECON, kLLF>), nblocks(R.count()), S, G, W, R, a, stage, p->gamma, p->eta, upd,
            diag, W.stop);
+  prof_end(st);
   return CTMHD_OK;
 }
 
@@ -1082,6 +1100,16 @@ int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double
   (void)g_cons_out; (void)g_bface_out; (void)workspace; (void)ws_bytes; (void)stream;
   return fail(CTMHD_EUNSUPPORTED, "ctmhd_step_adjoint is not built yet");
 }
+
+int ctmhd_profile_events(void* const* events, int npairs) {
+  if (npairs < 0) return fail(CTMHD_EARG, "npairs must be >= 0");
+  g_prof_events = npairs > 0 ? events : nullptr;
+  g_prof_pairs = events ? npairs : 0;
+  g_prof_used = 0;
+  return CTMHD_OK;
+}
+
+int ctmhd_profile_recorded(void) { return g_prof_used; }
 
 const char* ctmhd_last_error(void) { return g_err; }
 

@@ -70,6 +70,10 @@ def lib():
         L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
                                          _vp, ctypes.c_size_t, _vp]
         L.ctmhd_step_adjoint.restype = ctypes.c_int
+        L.ctmhd_profile_events.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+        L.ctmhd_profile_events.restype = ctypes.c_int
+        L.ctmhd_profile_recorded.argtypes = []
+        L.ctmhd_profile_recorded.restype = ctypes.c_int
         L.ctmhd_last_error.argtypes = []
         L.ctmhd_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -77,7 +81,8 @@ def lib():
 
 
 EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
-            "ctmhd_step_batched", "ctmhd_step_adjoint", "ctmhd_last_error")
+            "ctmhd_step_batched", "ctmhd_step_adjoint", "ctmhd_profile_events",
+            "ctmhd_profile_recorded", "ctmhd_last_error")
 
 
 def _check(rc):
@@ -240,3 +245,49 @@ def run(params: Params, cons, bface, dx, nsteps=1, dt_fixed=None, ng=None, devic
     torch.cuda.synchronize()
     c, b = st.to_numpy()
     return c, b, dts.cpu().numpy(), diag.cpu().numpy().reshape(nsteps, 4)
+
+
+# ---------------------------------------------------------------------------
+# HIP event timing of the library's face kernel (benchmarks).
+# ---------------------------------------------------------------------------
+class KernelTimer:
+    """Creates HIP events through the HIP runtime and hands them to
+    ctmhd_profile_events; mean_ms() gives the average duration of the
+    recorded face-kernel launches (after a synchronisation)."""
+
+    def __init__(self, npairs):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.events = (ctypes.c_void_p * (2 * npairs))()
+        for i in range(2 * npairs):
+            ev = ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                raise CtmhdError("hipEventCreate failed")
+            self.events[i] = ev
+        self.npairs = npairs
+
+    def start(self):
+        _check(lib().ctmhd_profile_events(self.events, self.npairs))
+
+    def stop(self):
+        n = lib().ctmhd_profile_recorded()
+        _check(lib().ctmhd_profile_events(None, 0))
+        return n
+
+    def durations_ms(self, n):
+        out = []
+        for i in range(n):
+            ms = ctypes.c_float()
+            rc = self.hip.hipEventElapsedTime(ctypes.byref(ms), self.events[2 * i],
+                                              self.events[2 * i + 1])
+            if rc != 0:
+                raise CtmhdError(f"hipEventElapsedTime failed ({rc})")
+            out.append(ms.value)
+        return out
+
+    def close(self):
+        for i in range(2 * self.npairs):
+            self.hip.hipEventDestroy(self.events[i])
