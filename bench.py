@@ -179,7 +179,7 @@ def main():
     fkey = f"{cfg['recon']}/{args.emf}/eta{'>0' if cfg['eta'] > 0 else '=0'}"
     face_flops = flops_tab[fkey]["face_flops"]
     cell_update_flops = flops_tab[fkey]["cell_update_flops"]
-    achieved = face_flops * n3 / (res["kernel_ms"] * 1e-3) / 1e12
+    achieved = face_flops * 3 * n3 / (res["kernel_ms"] * 1e-3) / 1e12
     traffic = read_traffic(args.config, args.precision, args.emf)
     out = {
         "metric": "Mcell-updates/s on 1 MI355X",
@@ -201,7 +201,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "face (reconstruction + Riemann, one direction, one stage)",
                      "kernel_ms": res["kernel_ms"], "flops_per_face": face_flops,
-                     "faces_per_launch": n3},
+                     "faces_per_launch": 3 * n3},
         "step_alu_frac": value * 1e6 * cell_update_flops / (PEAK_FP64_TFLOPS * 1e12),
         "hbm_frac_algorithmic": value * 1e6 * ALG_BYTES_PER_CELL_UPDATE / (PEAK_HBM_GBS * 1e9),
         "fofc_flagged_cells": res["flagged"],

@@ -2,18 +2,22 @@
 //
 // One RK2-SSP step with first-order flux correction (Sec. 2.5 of Kriel et al.)
 // is a short sequence of stream-ordered kernels on a ghosted box:
-//   k_begin      zero the per-step reduction slots
-//   k_wrap       periodic ghost fill of the 8 fields
-//   k_dt         CFL signal speed per cell -> wavefront max -> device max
-//   k_dt_final   dt = CFL / max (or the caller's dt); non-finite dt stops
+//   k_dt_final   dt from the CFL maximum of the step's starting state (or the
+//                caller's dt); a non-finite dt stops the call
 //   per stage:
-//   k_prim       conserved -> primitive (pressure recovery in FP64)
-//   k_face<a>    reconstruction + Riemann solve at x_a faces (flux, alpha, u*)
-//   k_emf<c>     edge EMFs (Q26 / B25a / FS18) + LD04 + eta j
-//   k_update     flux divergence and CT curl; RK combination
-//   k_flag       invalid-state flags (FOFC)
-//   k_fo_face/k_fo_edge  first-order fluxes / EMFs from S^n where flagged
-//   k_update     again, only when something was flagged
+//   k_faces      reconstruction + Riemann solve at every face of all three
+//                directions in one launch: x faces inside a wavefront (cross-
+//                lane shuffles), y and z faces by marching along the face
+//                normal with a register window, so that every cell is loaded
+//                and reconstructed once per direction; primitives are formed
+//                on the fly (pressure recovery in FP64)
+//   k_emf3       edge EMFs of the three edge directions (Q26 / B25a / FS18),
+//                LD04 averaging and eta j
+//   k_update     flux divergence and CT curl, RK combination, periodic ghost
+//                images, invalid-state flags and (second stage) the CFL
+//                maximum of the new state for the next step
+//   k_fo         first-order fluxes / EMFs from S^n around flagged cells
+//   k_update     again (fix-up mode), only when something was flagged
 // Face arrays hold the x_a face on the lower side of each cell, edge arrays
 // the edge at the lower corner in the two transverse directions.
 #include <hip/hip_runtime.h>
@@ -58,25 +62,6 @@ Geom make_geom(const ctmhd_box& b) {
   return G;
 }
 
-// A 3D index range [lo, lo+len) mapped onto a 1D grid, x fastest.
-struct Range {
-  int lo[3];
-  int len[3];
-  int count() const { return len[0] * len[1] * len[2]; }
-};
-
-__device__ __forceinline__ bool range_pos(const Range& r, int t, int s[3]) {
-  if (t >= r.len[0] * r.len[1] * r.len[2]) return false;
-  int i = t % r.len[0];
-  int q = t / r.len[0];
-  int j = q % r.len[1];
-  int k = q / r.len[1];
-  s[0] = r.lo[0] + i;
-  s[1] = r.lo[1] + j;
-  s[2] = r.lo[2] + k;
-  return true;
-}
-
 __device__ __forceinline__ int gidx() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
 struct State {
@@ -84,9 +69,12 @@ struct State {
   double* b[3];
 };
 
+constexpr int kBlock = 256;
+constexpr int kMaxSlots = 64;  // spread of the CFL maximum over atomics
+
 template <typename T>
 struct Work {
-  T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2
+  T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2 (B25a / FS18 only)
   T* ecell[3];      // cell-centred ideal EMF (B25a)
   T* F[2][3][5];    // per stage, direction, component (global momentum order)
   T* ap[3];
@@ -94,40 +82,27 @@ struct Work {
   T* us[3];
   T* E[2][3];       // per stage, edge EMFs
   uint8_t* flag;    // interior cells
-  unsigned long long* smax;  // CFL signal-speed maximum (bits of a non-negative double)
+  // CFL maxima (bits of non-negative doubles), kMaxSlots each: [0] fused into
+  // the stage-2 update, [1] recomputed by a stage-2 fix-up
+  unsigned long long* smax;
   double* dt;       // the step's dt
   int* stop;        // 1 once a non-finite dt was seen
-  int* nflag;       // flagged cells of the current stage
+  int* nflag;       // flagged cells of stage 0 / 1; nflag[2]: stage-2 fix-up ran
 };
-
-// Per-step diagnostic slot pointer (may be null).
-struct Diag {
-  long long* d;  // 4 counters of this step or null
-};
-
-constexpr int kBlock = 256;
 
 inline int nblocks(long long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
-__global__ void k_init(int* stop) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *stop = 0;
-}
-
-__global__ void k_begin(unsigned long long* smax, int* nflag, long long* diag, const int* stop) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *smax = 0ull;
-    nflag[0] = 0;
-    nflag[1] = 0;
-    if (diag) {
-      diag[0] = 0;
-      diag[1] = 0;
-      diag[2] = 0;
-      diag[3] = *stop ? 1 : 0;
-    }
+__global__ void k_init(int* stop, unsigned long long* smax, int* nflag) {
+  int t = threadIdx.x;
+  if (blockIdx.x != 0) return;
+  if (t == 0) {
+    *stop = 0;
+    nflag[0] = nflag[1] = nflag[2] = 0;
   }
+  if (t < 2 * kMaxSlots) smax[t] = 0ull;
 }
 
 __device__ __forceinline__ int pwrap(int s, int g, int n) {
@@ -137,7 +112,8 @@ __device__ __forceinline__ int pwrap(int s, int g, int n) {
 }
 
 // Periodic ghost fill of all 8 fields (faces follow the same rule: the face at
-// storage index s is the lower face of cell s).
+// storage index s is the lower face of cell s).  Used on the caller's state at
+// the start of a call; later states get their ghost images from k_update.
 __global__ void k_wrap(State S, Geom G, const int* stop) {
   if (*stop) return;
   int t = gidx();
@@ -167,51 +143,42 @@ __global__ void k_copy(State dst, State src, int elems, const int* only_if_stop)
 }
 
 // ---------------------------------------------------------------------------
-// CFL time step (eq. resistivity:cfl and the signal-speed treatment of the
-// resistive term): max over cells of max_d (|u_d| + c_f,d) / dx_d and
-// 2 eta / dx_min^2, reduced across the wavefront, the block and the grid.
+// Cell primitives from the conserved state (eq. state:primitive), FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v) {
+__device__ __forceinline__ void cell_prim(const State& S, const Geom& G, int s, double gamma,
+                                          double& rho, double u[3], double& p, double bc[3]) {
+  rho = S.c[0][s];
+  double ir = 1.0 / rho;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  for (int d = 0; d < 3; ++d) {
+    u[d] = S.c[1 + d][s] * ir;
+    bc[d] = 0.5 * (S.b[d][s] + S.b[d][s + G.st[d]]);
+  }
+  p = (gamma - 1.0) * (S.c[4][s] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
+                       0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
 }
 
-__global__ void __launch_bounds__(kBlock) k_dt(State S, Geom G, double gamma, double sres,
-                                               unsigned long long* smax, const int* stop) {
-  if (*stop) return;
-  __shared__ double red[kBlock / 64];
-  int t = gidx();
-  double s = 0.0;
-  int ninter = G.n[0] * G.n[1] * G.n[2];
-  if (t < ninter) {
-    int i = t % G.n[0] + G.g;
-    int q = t / G.n[0];
-    int j = q % G.n[1] + G.g;
-    int k = q / G.n[1] + G.g;
-    int c = i + G.st[1] * j + G.st[2] * k;
-    double rho = S.c[0][c];
-    double ir = 1.0 / rho;
-    double u[3], b[3];
+// CFL signal speed of one cell (eq. resistivity:cfl; the resistive term
+// enters as the speed 2 eta / dx_min, i.e. 2 eta / dx_min^2 per unit length).
+// NaN propagates.
+__device__ __forceinline__ double cfl_signal(double rho, const double u[3], double p,
+                                             const double bc[3], const Geom& G, double gamma,
+                                             double sres) {
+  double s = sres;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      u[d] = S.c[1 + d][c] * ir;
-      b[d] = 0.5 * (S.b[d][c] + S.b[d][c + G.st[d]]);
-    }
-    double p = (gamma - 1.0) *
-               (S.c[4][c] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
-                0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
-    s = sres;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double cf = fast_speed<double>(rho, p, b[d], b[(d + 1) % 3], b[(d + 2) % 3], gamma);
-      double sd = (fabs(u[d]) + cf) * G.idx[d];
-      // NaN-propagating max: a NaN signal speed must surface as a NaN dt
-      s = (sd > s || sd != sd) ? sd : s;
-    }
+  for (int d = 0; d < 3; ++d) {
+    double cf = fast_speed<double>(rho, p, bc[d], bc[(d + 1) % 3], bc[(d + 2) % 3], gamma);
+    double sd = (fabs(u[d]) + cf) * G.idx[d];
+    s = (sd > s || sd != sd) ? sd : s;
   }
-  // NaN-aware: fmax drops NaN, so reduce bit patterns instead for the final
-  // atomic (a NaN has larger bits than +inf as an unsigned integer).
+  return s;
+}
+
+// Block maximum of a non-negative (or NaN) double, folded into one of
+// kMaxSlots device slots by an atomic max on its bit pattern (a NaN has
+// larger bits than +inf as an unsigned integer).  All threads must call.
+__device__ __forceinline__ void block_max_to_slots(double s, unsigned long long* slots) {
+  __shared__ unsigned long long red[kBlock / 64];
   unsigned long long bits = (unsigned long long)__double_as_longlong(s);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -219,33 +186,64 @@ __global__ void __launch_bounds__(kBlock) k_dt(State S, Geom G, double gamma, do
     bits = ob > bits ? ob : bits;
   }
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = __longlong_as_double((long long)bits);
+  if (lane == 0) red[w] = bits;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long m = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-      unsigned long long v = (unsigned long long)__double_as_longlong(red[q]);
-      m = v > m ? v : m;
-    }
-    atomicMax(smax, m);
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = red[q] > m ? red[q] : m;
+    atomicMax(&slots[blockIdx.x % kMaxSlots], m);
   }
 }
 
-__global__ void k_dt_final(const unsigned long long* smax, double cfl, const double* dt_fixed,
-                           double* dt, double* dt_out, int* stop, long long* diag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// CFL maximum of a whole state (start of a call).
+__global__ void __launch_bounds__(kBlock) k_dt(State S, Geom G, double gamma, double sres,
+                                               unsigned long long* slots, const int* stop) {
+  if (*stop) return;
+  int ninter = G.n[0] * G.n[1] * G.n[2];
+  double s = 0.0;
+  for (int t = gidx(); t < ninter; t += gridDim.x * blockDim.x) {
+    int i = t % G.n[0] + G.g;
+    int q = t / G.n[0];
+    int j = q % G.n[1] + G.g;
+    int k = q / G.n[1] + G.g;
+    int c = i + G.st[1] * j + G.st[2] * k;
+    double rho, u[3], p, bc[3];
+    cell_prim(S, G, c, gamma, rho, u, p, bc);
+    double v = cfl_signal(rho, u, p, bc, G, gamma, sres);
+    s = (v > s || v != v) ? v : s;
+  }
+  block_max_to_slots(s, slots);
+}
+
+// dt of a step.  smax[0..kMaxSlots) holds the CFL maximum of the step's
+// starting state unless the previous step's second stage was fixed up
+// (nflag[2]), whose recomputed maximum is in smax[kMaxSlots..).  Resets the
+// slots, the flag counters and this step's diagnostics.
+__global__ void k_dt_final(unsigned long long* smax, int* nflag, double cfl,
+                           const double* dt_fixed, double* dt, double* dt_out, int* stop,
+                           long long* diag) {
+  int t = threadIdx.x;
+  __shared__ unsigned long long m;
+  if (t == 0) {
+    const unsigned long long* src = nflag[2] ? smax + kMaxSlots : smax;
+    unsigned long long v = 0;
+    for (int q = 0; q < kMaxSlots; ++q) v = src[q] > v ? src[q] : v;
+    m = v;
+  }
+  __syncthreads();
+  if (t < 2 * kMaxSlots) smax[t] = 0ull;
+  if (t != 0) return;
+  nflag[0] = nflag[1] = nflag[2] = 0;
+  if (diag) {
+    diag[0] = diag[1] = diag[2] = 0;
+    diag[3] = *stop ? 1 : 0;
+  }
   if (*stop) {
     *dt = 0.0;
     if (dt_out) *dt_out = 0.0;
     return;
   }
-  double v;
-  if (dt_fixed) {
-    v = *dt_fixed;
-  } else {
-    double s = __longlong_as_double((long long)*smax);
-    v = cfl / s;
-  }
+  double v = dt_fixed ? *dt_fixed : cfl / __longlong_as_double((long long)m);
   if (!(v > 0.0) || !__builtin_isfinite(v)) {
     *stop = 1;
     if (diag) diag[3] = 1;
@@ -255,9 +253,8 @@ __global__ void k_dt_final(const unsigned long long* smax, double cfl, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Conserved -> primitive (eq. state:primitive).  Pressure recovery is always
-// FP64; results are rounded to the stencil type T.  Cells whose upper faces
-// are stored (index < N-1 on every axis).
+// Cell-centred fields for the two-step EMF schemes (B25a: ideal EMF; FS18:
+// velocity), over cells whose upper faces are stored.
 // ---------------------------------------------------------------------------
 template <typename T, int EMF>
 __global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, double gamma,
@@ -270,24 +267,8 @@ __global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, dou
   int j = q % G.N[1];
   int k = q / G.N[1];
   if (i >= G.N[0] - 1 || j >= G.N[1] - 1 || k >= G.N[2] - 1) return;
-  double rho = S.c[0][t];
-  double ir = 1.0 / rho;
-  double u[3], b[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    u[d] = S.c[1 + d][t] * ir;
-    b[d] = 0.5 * (S.b[d][t] + S.b[d][t + G.st[d]]);
-  }
-  double p = (gamma - 1.0) * (S.c[4][t] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
-                              0.5 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
-  W.prim[0][t] = (T)rho;
-  W.prim[1][t] = (T)u[0];
-  W.prim[2][t] = (T)u[1];
-  W.prim[3][t] = (T)u[2];
-  W.prim[4][t] = (T)p;
-  W.prim[5][t] = (T)b[0];
-  W.prim[6][t] = (T)b[1];
-  W.prim[7][t] = (T)b[2];
+  double rho, u[3], p, b[3];
+  cell_prim(S, G, t, gamma, rho, u, p, b);
   if (EMF == kB25A) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -295,6 +276,10 @@ __global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, dou
       // eq. emf:b25a-emf-centre in the stencil type
       W.ecell[c][t] = -(T)u[a] * (T)b[bb] + (T)u[bb] * (T)b[a];
     }
+  } else {
+    W.prim[1][t] = (T)u[0];
+    W.prim[2][t] = (T)u[1];
+    W.prim[3][t] = (T)u[2];
   }
 }
 
@@ -311,72 +296,212 @@ __device__ __forceinline__ T eta_j(const State& S, const Geom& G, int s, int c, 
 // with eta j averaged over the face's bounding edges and b the mean of the two
 // adjacent cells' cell-averaged field.
 template <typename T>
-__device__ __forceinline__ T joule(const State& S, const Geom& G, const T* const* prim, int s,
-                                   int a, T eta) {
+__device__ __forceinline__ T joule(const State& S, const Geom& G, int s, int a, T eta) {
   int b = (a + 1) % 3, c = (a + 2) % 3;
   T eb = T(0.5) * (eta_j<T>(S, G, s, b, eta) + eta_j<T>(S, G, s + G.st[c], b, eta));
   T ec = T(0.5) * (eta_j<T>(S, G, s, c, eta) + eta_j<T>(S, G, s + G.st[b], c, eta));
   int l = s - G.st[a];
-  T bb = T(0.5) * (prim[5 + b][l] + prim[5 + b][s]);
-  T bc = T(0.5) * (prim[5 + c][l] + prim[5 + c][s]);
-  return eb * bc - ec * bb;
+  T bbl = (T)(0.5 * (S.b[b][l] + S.b[b][l + G.st[b]]));
+  T bbr = (T)(0.5 * (S.b[b][s] + S.b[b][s + G.st[b]]));
+  T bcl = (T)(0.5 * (S.b[c][l] + S.b[c][l + G.st[c]]));
+  T bcr = (T)(0.5 * (S.b[c][s] + S.b[c][s + G.st[c]]));
+  return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
 }
 
 // ---------------------------------------------------------------------------
-// Face pass (Sec. 2.2, eqs. emf:alpha-pm, emf:q26-facevel): reconstruct the
-// seven face-local primitives from both sides, solve the Riemann problem with
-// the stored normal field, store the flux, alpha^{+/-} and u_a^*.
+// Face pass (Sec. 2.2, eqs. emf:alpha-pm, emf:q26-facevel).
 // ---------------------------------------------------------------------------
+// Face ranges of one stage.  Faces of direction a: s_a in [lo_a, lo_a +
+// nf_a), transverse coordinates in [tlo, tlo + tlen) on both axes.
+struct FacePlan {
+  int lo[3], nf[3];   // along the face normal
+  int tlo, tlen[3];   // transverse range start (same on every axis) and length per axis
+  int ulo[3], ulen[3];  // faces read by the update (Joule flux only there)
+  // x part: one wavefront per (row, segment)
+  int xseg, xnseg, xwaves, xblocks;
+  // y and z parts: lane blocks x chunks
+  int chunk[3], nchunk[3], lanes[3], lblocks[3], blocks[3];
+  int total_blocks;
+};
+
+// Face-local primitive of cell s for the face normal a (FP64 recovery, then T).
+template <typename T>
+__device__ __forceinline__ void face_local(const State& S, const Geom& G, int s, int a, double gamma,
+                                           T v[7]) {
+  double rho, u[3], p, bc[3];
+  cell_prim(S, G, s, gamma, rho, u, p, bc);
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  v[0] = (T)rho;
+  v[1] = (T)u[a];
+  v[2] = (T)u[b];
+  v[3] = (T)u[c];
+  v[4] = (T)p;
+  v[5] = (T)bc[b];
+  v[6] = (T)bc[c];
+}
+
+template <typename T, int RIEMANN>
+__device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, const Work<T>& W,
+                                               const FacePlan& FP, int s, const int s3[3], int a,
+                                               int stage, const T qL[7], const T qR[7],
+                                               double gamma_d, double eta_d) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  FState<T> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
+  FState<T> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
+  T bn = (T)S.b[a][s];
+  T F[5], ap, am;
+  int fb = 0;
+  if (RIEMANN == kHLLD) {
+    T SL, SR;
+    fb = hlld_flux(L, R, bn, (T)gamma_d, F, SL, SR);
+    ap = tmax(T(0), SR);
+    am = tmax(T(0), -SL);
+  } else {
+    ap = am = llf_flux(L, R, bn, (T)gamma_d, F);
+  }
+  if (eta_d > 0.0) {
+    // faces read by the update: [g, g+n] along the normal, [g, g+n) across
+    bool in_upd = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      in_upd = in_upd && s3[d] >= FP.ulo[d] && s3[d] < FP.ulo[d] + FP.ulen[d] + (d == a ? 1 : 0);
+    if (in_upd) F[4] += joule<T>(S, G, s, a, (T)eta_d);
+  }
+  W.F[stage][a][0][s] = F[0];
+  W.F[stage][a][1 + a][s] = F[1];
+  W.F[stage][a][1 + b][s] = F[2];
+  W.F[stage][a][1 + c][s] = F[3];
+  W.F[stage][a][4][s] = F[4];
+  W.ap[a][s] = ap;
+  W.am[a][s] = am;
+  W.us[a][s] = (ap * L.un + am * R.un) / (ap + am);
+  return fb;
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_shfl(T v, int src) {
+  return __shfl(v, src, 64);
+}
+
+// x faces: one wavefront holds 64 consecutive cells of a row; lane l forms
+// the primitives, the limited slope and the upper interface value of its own
+// cell, neighbours come from cross-lane shuffles, and the face at lane l takes
+// the upper value of lane l-1.  Faces at lanes [r+1, 63-r] are resolved
+// (overlapping segments).
+template <int RECON, typename T>
+__device__ __forceinline__ void recon_lanes(T q, int lane, T& qm, T& qp) {
+  if constexpr (RECON == kPC) {
+    qm = q;
+    qp = q;
+  } else if constexpr (RECON == kPLM_MC || RECON == kPLM_MM) {
+    T s = T(0.5) * plm_slope<RECON>(lane_shfl(q, lane - 1), q, lane_shfl(q, lane + 1));
+    qm = q - s;
+    qp = q + s;
+  } else {
+    T qr = lane_shfl(q, lane + 1);
+    T dm = ppm_slope(lane_shfl(q, lane - 1), q, qr);
+    T ihi = ppm_iface(q, qr, dm, lane_shfl(dm, lane + 1));
+    T ilo = lane_shfl(ihi, lane - 1);
+    ppm_constrain(q, ilo, ihi);
+    qm = ilo;
+    qp = ihi;
+  }
+}
+
+template <typename T, int RECON, int RIEMANN>
+__device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const FacePlan& FP,
+                        int wave, int stage, double gamma, double eta, int& nfb) {
+  constexpr int r = recon_halfwidth(RECON);
+  const int lane = threadIdx.x & 63;
+  const int row = wave / FP.xnseg, seg = wave % FP.xnseg;
+  const int y = FP.tlo + row % FP.tlen[1];
+  const int z = FP.tlo + row / FP.tlen[1];
+  const int x = FP.lo[0] - (r + 1) + seg * FP.xseg + lane;
+  const int xc = x < 0 ? 0 : (x > G.N[0] - 2 ? G.N[0] - 2 : x);  // loads stay in the box
+  const int s = xc + G.st[1] * y + G.st[2] * z;
+  T v[7];
+  face_local<T>(S, G, s, 0, gamma, v);
+  T qm[7], qp[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], lane, qm[k], qp[k]);
+  T qL[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) qL[k] = lane_shfl(qp[k], lane - 1);
+  const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
+  if (face) {
+    const int s3[3] = {x, y, z};
+    nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, 0, stage, qL, qm, gamma, eta);
+  }
+}
+
+// y / z faces: lanes over the transverse plane (x fastest), each thread
+// marches along the face normal A through a chunk of faces, streaming the
+// cells through a reconstruction pipeline (one slope and one interface value
+// per cell); each cell is loaded and reconstructed once.
+template <typename T, int RECON, int RIEMANN, int A>
+__device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, const FacePlan& FP,
+                            int lblock, int chunk, int stage, double gamma, double eta, int& nfb) {
+  constexpr int r = recon_halfwidth(RECON);
+  const int lane = lblock * kBlock + threadIdx.x;
+  if (lane >= FP.lanes[A]) return;
+  const int C = A == 1 ? 2 : 1;  // transverse axes: x (fastest) and C
+  int s3[3];
+  s3[0] = FP.tlo + lane % FP.tlen[0];
+  s3[C] = FP.tlo + lane / FP.tlen[0];
+  const int f0 = FP.lo[A] + chunk * FP.chunk[A];
+  int f1 = f0 + FP.chunk[A];
+  if (f1 > FP.lo[A] + FP.nf[A]) f1 = FP.lo[A] + FP.nf[A];
+  const int sa = G.st[A];
+  const int base = s3[0] + G.st[C] * s3[C];
+  ReconStream<RECON, T> rs[7];
+  T qprev[7];
+  // warm-up: cells f0-1-r .. f0-2+r (outputs not yet complete)
+  for (int q = f0 - 1 - r; q < f0 - 1 + r; ++q) {
+    T v[7];
+    face_local<T>(S, G, base + q * sa, A, gamma, v);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      T a0, a1;
+      rs[k].push(v[k], a0, a1);
+    }
+  }
+  for (int q = f0 - 1 + r; q <= f1 - 1 + r; ++q) {
+    T v[7];
+    face_local<T>(S, G, base + q * sa, A, gamma, v);
+    const int cell = q - r;  // completed by this push
+    T qm[7], qp[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) rs[k].push(v[k], qm[k], qp[k]);
+    if (cell >= f0) {
+      s3[A] = cell;
+      const int s = base + cell * sa;
+      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, A, stage, qprev, qm, gamma, eta);
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) qprev[k] = qp[k];
+  }
+}
+
 template <typename T, int RECON, int RIEMANN>
 __global__ void __launch_bounds__(kBlock)
-    k_face(State S, Geom G, Work<T> W, Range R, int a, int stage, double gamma_d, double eta_d,
-           Range upd, long long* diag, const int* stop) {
+    k_faces(State S, Geom G, Work<T> W, FacePlan FP, int stage, double gamma, double eta,
+            long long* diag, const int* stop) {
   if (*stop) return;
-  int s3[3];
-  int fb = 0;
-  if (range_pos(R, gidx(), s3)) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    const int sa = G.st[a];
-    const int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-    const T gamma = (T)gamma_d;
-    const int var[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
-    T lo[7], hi[7];
-#pragma unroll
-    for (int v = 0; v < 7; ++v) {
-      const T* P = W.prim[var[v]];
-      T q[6];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) q[m] = stencil_uses<RECON>(m) ? P[s + (m - 3) * sa] : T(0);
-      recon_iface<RECON>(q, lo[v], hi[v]);
-    }
-    FState<T> L{lo[0], lo[1], lo[2], lo[3], lo[4], lo[5], lo[6]};
-    FState<T> Rr{hi[0], hi[1], hi[2], hi[3], hi[4], hi[5], hi[6]};
-    T bn = (T)S.b[a][s];
-    T F[5], ap, am;
-    if (RIEMANN == kHLLD) {
-      T SL, SR;
-      fb = hlld_flux(L, Rr, bn, gamma, F, SL, SR);
-      ap = tmax(T(0), SR);
-      am = tmax(T(0), -SL);
-    } else {
-      ap = am = llf_flux(L, Rr, bn, gamma, F);
-    }
-    bool in_upd = s3[0] >= upd.lo[0] && s3[0] < upd.lo[0] + upd.len[0] && s3[1] >= upd.lo[1] &&
-                  s3[1] < upd.lo[1] + upd.len[1] && s3[2] >= upd.lo[2] && s3[2] < upd.lo[2] + upd.len[2];
-    if (eta_d > 0.0 && in_upd) F[4] += joule<T>(S, G, W.prim, s, a, (T)eta_d);
-    W.F[stage][a][0][s] = F[0];
-    W.F[stage][a][1 + a][s] = F[1];
-    W.F[stage][a][1 + b][s] = F[2];
-    W.F[stage][a][1 + c][s] = F[3];
-    W.F[stage][a][4][s] = F[4];
-    W.ap[a][s] = ap;
-    W.am[a][s] = am;
-    W.us[a][s] = (ap * L.un + am * Rr.un) / (ap + am);
+  int nfb = 0;
+  int b = blockIdx.x;
+  // long-running marching blocks first, the short x-face wavefronts fill in
+  if (b < FP.blocks[2]) {
+    faces_march<T, RECON, RIEMANN, 2>(S, G, W, FP, b / FP.nchunk[2], b % FP.nchunk[2], stage,
+                                      gamma, eta, nfb);
+  } else if ((b -= FP.blocks[2]) < FP.blocks[1]) {
+    faces_march<T, RECON, RIEMANN, 1>(S, G, W, FP, b / FP.nchunk[1], b % FP.nchunk[1], stage,
+                                      gamma, eta, nfb);
+  } else {
+    b -= FP.blocks[1];
+    const int wave = b * (kBlock / 64) + (threadIdx.x >> 6);
+    if (wave < FP.xwaves) faces_x<T, RECON, RIEMANN>(S, G, W, FP, wave, stage, gamma, eta, nfb);
   }
-  if (diag) {
-    unsigned long long m = __ballot(fb);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd((unsigned long long*)&diag[2], (unsigned long long)__popcll(m));
-  }
+  if (diag && nfb) atomicAdd((unsigned long long*)&diag[2], (unsigned long long)nfb);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,14 +548,10 @@ __device__ __forceinline__ void two_step(const T* A, int s, int st1, int st2, T 
 }
 
 template <typename T, int RECON, int EMF>
-__global__ void __launch_bounds__(kBlock)
-    k_emf(State S, Geom G, Work<T> W, Range R, int c, int stage, double eta_d, const int* stop) {
-  if (*stop) return;
-  int s3[3];
-  if (!range_pos(R, gidx(), s3)) return;
+__device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
+                                      double eta_d) {
   const int a = (c + 1) % 3, b = (c + 2) % 3;
   const int sa = G.st[a], sb = G.st[b];
-  const int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
   T baB, baT, bbL, bbR;
   iface_along_d<RECON>(S.b[a], s, sb, baB, baT);
   iface_along_d<RECON>(S.b[b], s, sa, bbL, bbR);
@@ -474,119 +595,177 @@ __global__ void __launch_bounds__(kBlock)
   T amb = tmax(W.am[b][s - sa], W.am[b][s]);
   T eps = ld04(e[0], e[1], e[2], e[3], apa, ama, apb, amb, baB, baT, bbL, bbR);
   if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
-  W.E[stage][c][s] = eps;
+  return eps;
+}
+
+// All three edge directions at the edge positions [g, g+n] on every axis
+// (an edge of direction c exists for s_c < g + n_c).
+template <typename T, int RECON, int EMF>
+__global__ void __launch_bounds__(kBlock)
+    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
+  if (*stop) return;
+  const int L0 = G.n[0] + 1, L1 = G.n[1] + 1, L2 = G.n[2] + 1;
+  int t = gidx();
+  if (t >= L0 * L1 * L2) return;
+  int s3[3] = {G.g + t % L0, G.g + (t / L0) % L1, G.g + t / (L0 * L1)};
+  int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (s3[c] < G.g + G.n[c]) W.E[stage][c][s] = edge_emf<T, RECON, EMF>(S, G, W, s, c, eta_d);
 }
 
 // ---------------------------------------------------------------------------
 // Update (eqs. rk:increment-state, rk:increment-bfield, rk1:update,
-// rk2:update).  stage 0: out = S^n + D^n.  stage 1: out = S^n + (D^n + D^{n+1/2})/2.
-// Increments are formed in FP64 from the stored fluxes and EMFs.
+// rk2:update).  stage 0: out = S^n + D^n.  stage 1: out = S^n + (D^n +
+// D^{n+1/2})/2.  Increments are formed in FP64 from the stored fluxes and
+// EMFs (which are single-valued per face and edge: conservation and div b
+// hold to FP64 round-off in both precision forms).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void incr(const Geom& G, const Work<T>& W, int st, int s, double dt,
-                                     double dc[5], double db[3]) {
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    double f = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T* Fa = W.F[st][a][m];
-      f += ((double)Fa[s] - (double)Fa[s + G.st[a]]) * G.idx[a];
-    }
-    dc[m] = dt * f;
-  }
+__device__ __forceinline__ double dcons(const Geom& G, const Work<T>& W, int st, int s, int m,
+                                        double dt) {
+  double f = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    const T* Ec = W.E[st][c];
-    const T* Eb = W.E[st][b];
-    double circ = ((double)Ec[s] - (double)Ec[s + G.st[b]]) * G.idx[b] +
-                  ((double)Eb[s + G.st[c]] - (double)Eb[s]) * G.idx[c];
-    db[a] = dt * circ;
+    const T* Fa = W.F[st][a][m];
+    f += ((double)Fa[s] - (double)Fa[s + G.st[a]]) * G.idx[a];
   }
+  return dt * f;
 }
 
+// increment of the face field b_a stored at s
+template <typename T>
+__device__ __forceinline__ double dface(const Geom& G, const Work<T>& W, int st, int s, int a,
+                                        double dt) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const T* Ec = W.E[st][c];
+  const T* Eb = W.E[st][b];
+  double circ = ((double)Ec[s] - (double)Ec[s + G.st[b]]) * G.idx[b] +
+                ((double)Eb[s + G.st[c]] - (double)Eb[s]) * G.idx[c];
+  return dt * circ;
+}
+
+// New face field.  stage 0: b^n + D^n.  stage 1, main pass: the SSP form
+// (b^n + b^{n+1/2} + D^{n+1/2}) / 2, which equals b^n + (D^n + D^{n+1/2}) / 2
+// up to round-off and does not re-read the first-stage EMFs; stage 1 after a
+// first-order replacement: b^n + (D^n + D^{n+1/2}) / 2 with the replaced
+// values of both stages.
+template <typename T>
+__device__ __forceinline__ double new_face(const State& base, const State& half, const Geom& G,
+                                           const Work<T>& W, int stage, int fixup, int s, int a,
+                                           double dt) {
+  if (stage == 0) return base.b[a][s] + dface(G, W, 0, s, a, dt);
+  if (!fixup) return 0.5 * (base.b[a][s] + half.b[a][s] + dface(G, W, 1, s, a, dt));
+  return base.b[a][s] + 0.5 * (dface(G, W, 0, s, a, dt) + dface(G, W, 1, s, a, dt));
+}
+
+struct UpdateCfg {
+  int fofc;          // flag the new state
+  int crit;          // CTMHD_FLAG_*
+  double gamma;
+  double sres;       // resistive signal speed term of the CFL maximum
+  const uint8_t* force;  // forced flags of this stage or null
+};
+
+// fixup = 0: main update (flags, and for stage 1 the CFL maximum into slot 0)
+// fixup = 1: after first-order replacement; runs only if this stage flagged
+//            cells; stage 1 recomputes the CFL maximum into slot 1.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_update(State base, State out, Geom G, Work<T> W, int stage, int only_if_flagged,
-             const int* stop) {
+    k_update(State base, State half, State out, Geom G, Work<T> W, int stage, int fixup,
+             UpdateCfg U, long long* diag, const int* stop) {
   if (*stop) return;
-  if (only_if_flagged && W.nflag[stage] == 0) return;
-  int t = gidx();
-  int ninter = G.n[0] * G.n[1] * G.n[2];
-  if (t >= ninter) return;
-  int i = t % G.n[0] + G.g;
-  int q = t / G.n[0];
-  int j = q % G.n[1] + G.g;
-  int k = q / G.n[1] + G.g;
-  int s = i + G.st[1] * j + G.st[2] * k;
-  double dt = *W.dt;
-  double d1c[5], d1b[3];
-  incr(G, W, 0, s, dt, d1c, d1b);
-  if (stage == 0) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) out.c[m][s] = base.c[m][s] + d1c[m];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) out.b[a][s] = base.b[a][s] + d1b[a];
-  } else {
-    double d2c[5], d2b[3];
-    incr(G, W, 1, s, dt, d2c, d2b);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) out.c[m][s] = base.c[m][s] + 0.5 * (d1c[m] + d2c[m]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) out.b[a][s] = base.b[a][s] + 0.5 * (d1b[a] + d2b[a]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// First-order flux correction (Sec. 2.5).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-    k_flag(State X, Geom G, uint8_t* flag, const uint8_t* force, int crit, double gamma,
-           int* nflag, long long* diag, const int* stop) {
-  if (*stop) return;
-  int t = gidx();
-  int ninter = G.n[0] * G.n[1] * G.n[2];
+  if (fixup && W.nflag[stage] == 0) return;
+  const int t = gidx();
+  const int ninter = G.n[0] * G.n[1] * G.n[2];
+  const bool live = t < ninter;
+  const double dt = *W.dt;
   int bad = 0;
-  if (t < ninter) {
-    int i0 = t % G.n[0];
-    int q = t / G.n[0];
-    int j0 = q % G.n[1];
-    int k0 = q / G.n[1];
-    int i = i0 + G.g, j = j0 + G.g, k = k0 + G.g;
-    int s = i + G.st[1] * j + G.st[2] * k;
-    int up[3] = {((i0 + 1) % G.n[0]) + G.g + G.st[1] * j + G.st[2] * k,
-                 i + G.st[1] * (((j0 + 1) % G.n[1]) + G.g) + G.st[2] * k,
-                 i + G.st[1] * j + G.st[2] * (((k0 + 1) % G.n[2]) + G.g)};
-    double rho = X.c[0][s];
-    bool nonfin = false;
+  double sig = 0.0;
+  if (live) {
+    const int i0 = t % G.n[0];
+    const int q = t / G.n[0];
+    const int j0 = q % G.n[1];
+    const int k0 = q / G.n[1];
+    const int p3[3] = {i0, j0, k0};
+    const int s = (i0 + G.g) + G.st[1] * (j0 + G.g) + G.st[2] * (k0 + G.g);
+    double c[5], bl[3];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) nonfin |= !__builtin_isfinite(X.c[m][s]);
-    double m2 = 0.0, b2 = 0.0;
+    for (int m = 0; m < 5; ++m) {
+      if (stage == 0)
+        c[m] = base.c[m][s] + dcons(G, W, 0, s, m, dt);
+      else if (!fixup)
+        c[m] = 0.5 * (base.c[m][s] + half.c[m][s] + dcons(G, W, 1, s, m, dt));
+      else
+        c[m] = base.c[m][s] + 0.5 * (dcons(G, W, 0, s, m, dt) + dcons(G, W, 1, s, m, dt));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) bl[a] = new_face(base, half, G, W, stage, fixup, s, a, dt);
+    // periodic images: every storage position congruent to this cell
+    int mlo[3], mhi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double bl = X.b[d][s], bu = X.b[d][up[d]];
-      nonfin |= !__builtin_isfinite(bl) || !__builtin_isfinite(bu);
-      double bc = 0.5 * (bl + bu);
-      double u = X.c[1 + d][s] / rho;
-      m2 += rho * u * u;
-      b2 += bc * bc;
+      const int pos = p3[d] + G.g;
+      mlo[d] = -(pos / G.n[d]);
+      mhi[d] = (G.N[d] - 1 - pos) / G.n[d];
     }
-    double p = (gamma - 1.0) * (X.c[4][s] - 0.5 * m2 - 0.5 * b2);
-    if ((crit & CTMHD_FLAG_RHO) && !(rho > 0.0)) bad = 1;
-    if ((crit & CTMHD_FLAG_P) && !(p > 0.0)) bad = 1;
-    if ((crit & CTMHD_FLAG_NONFINITE) && (nonfin || !__builtin_isfinite(p))) bad = 1;
-    if (force && force[t]) bad = 1;
-    flag[t] = (uint8_t)bad;
+    for (int mz = mlo[2]; mz <= mhi[2]; ++mz)
+      for (int my = mlo[1]; my <= mhi[1]; ++my)
+        for (int mx = mlo[0]; mx <= mhi[0]; ++mx) {
+          const int sw = s + mx * G.n[0] + my * G.n[1] * G.st[1] + mz * G.n[2] * G.st[2];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) out.c[m][sw] = c[m];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) out.b[a][sw] = bl[a];
+        }
+    const bool need_state = (U.fofc && !fixup) || stage == 1;
+    if (need_state) {
+      // upper faces of this cell, recomputed with the same arithmetic as
+      // the neighbour that owns them
+      double bu[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) bu[a] = new_face(base, half, G, W, stage, fixup, s + G.st[a], a, dt);
+      const double rho = c[0];
+      double u[3], bc[3];
+      bool nonfin = false;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) nonfin |= !__builtin_isfinite(c[m]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        nonfin |= !__builtin_isfinite(bl[d]) || !__builtin_isfinite(bu[d]);
+        bc[d] = 0.5 * (bl[d] + bu[d]);
+        u[d] = c[1 + d] / rho;
+      }
+      const double p = (U.gamma - 1.0) * (c[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
+                                          0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
+      if (U.fofc && !fixup) {
+        if ((U.crit & CTMHD_FLAG_RHO) && !(rho > 0.0)) bad = 1;
+        if ((U.crit & CTMHD_FLAG_P) && !(p > 0.0)) bad = 1;
+        if ((U.crit & CTMHD_FLAG_NONFINITE) && (nonfin || !__builtin_isfinite(p))) bad = 1;
+        if (U.force && U.force[t]) bad = 1;
+        W.flag[t] = (uint8_t)bad;
+      }
+      if (stage == 1) sig = cfl_signal(rho, u, p, bc, G, U.gamma, U.sres);
+    }
   }
-  unsigned long long m = __ballot(bad);
-  if ((threadIdx.x & 63) == 0 && m) {
-    int cnt = __popcll(m);
-    atomicAdd(nflag, cnt);
-    if (diag) atomicAdd((unsigned long long*)diag, (unsigned long long)cnt);
+  if (U.fofc && !fixup) {
+    unsigned long long m = __ballot(bad);
+    if ((threadIdx.x & 63) == 0 && m) {
+      int cnt = __popcll(m);
+      atomicAdd(&W.nflag[stage], cnt);
+      if (diag) atomicAdd((unsigned long long*)&diag[stage], (unsigned long long)cnt);
+    }
+  }
+  if (stage == 1) {
+    if (fixup && threadIdx.x == 0 && blockIdx.x == 0) W.nflag[2] = 1;
+    block_max_to_slots(sig, W.smax + (fixup ? kMaxSlots : 0));
   }
 }
 
+// ---------------------------------------------------------------------------
+// First-order flux correction (Sec. 2.5): faces touching a flagged cell take
+// the PC + LLF flux of S^n, edges touching one the first-order EMF of S^n.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int interior_id(const Geom& G, int s0, int s1, int s2) {
   int i = (s0 - G.g) % G.n[0];
   if (i < 0) i += G.n[0];
@@ -597,39 +776,16 @@ __device__ __forceinline__ int interior_id(const Geom& G, int s0, int s1, int s2
   return i + G.n[0] * (j + G.n[1] * k);
 }
 
-// PC face state from the conserved state of cell l (left) or r (right).
-template <typename T>
-__device__ __forceinline__ void pc_cell(const State& S, const Geom& G, int s, double gamma, T& rho,
-                                        T u[3], T& p, T bc[3]) {
-  double r = S.c[0][s];
-  double ir = 1.0 / r;
-  double uu[3], bb[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    uu[d] = S.c[1 + d][s] * ir;
-    bb[d] = 0.5 * (S.b[d][s] + S.b[d][s + G.st[d]]);
-  }
-  double pp = (gamma - 1.0) * (S.c[4][s] - 0.5 * r * (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) -
-                               0.5 * (bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2]));
-  rho = (T)r;
-  p = (T)pp;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    u[d] = (T)uu[d];
-    bc[d] = (T)bb[d];
-  }
-}
-
 // First-order (PC + LLF) flux at the x_a face s; returns s_LLF and u*.
 template <typename T>
 __device__ __forceinline__ T fo_face(const State& S, const Geom& G, int s, int a, double gamma_d,
                                      T F[5], T& ustar) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
-  T rl, ul[3], pl, bl[3], rr, ur[3], pr, br[3];
-  pc_cell<T>(S, G, s - G.st[a], gamma_d, rl, ul, pl, bl);
-  pc_cell<T>(S, G, s, gamma_d, rr, ur, pr, br);
-  FState<T> L{rl, ul[a], ul[b], ul[c], pl, bl[b], bl[c]};
-  FState<T> R{rr, ur[a], ur[b], ur[c], pr, br[b], br[c]};
+  T vl[7], vr[7];
+  face_local<T>(S, G, s - G.st[a], a, gamma_d, vl);
+  face_local<T>(S, G, s, a, gamma_d, vr);
+  FState<T> L{vl[0], vl[1], vl[2], vl[3], vl[4], vl[5], vl[6]};
+  FState<T> R{vr[0], vr[1], vr[2], vr[3], vr[4], vr[5], vr[6]};
   T Fl[5];
   T sp = llf_flux(L, R, (T)S.b[a][s], (T)gamma_d, Fl);
   F[0] = Fl[0];
@@ -641,123 +797,90 @@ __device__ __forceinline__ T fo_face(const State& S, const Geom& G, int s, int a
   return sp;
 }
 
-// Joule flux at the x_a face s with cell fields from the conserved state.
-template <typename T>
-__device__ __forceinline__ T joule_sn(const State& S, const Geom& G, int s, int a, T eta) {
-  int b = (a + 1) % 3, c = (a + 2) % 3;
-  T eb = T(0.5) * (eta_j<T>(S, G, s, b, eta) + eta_j<T>(S, G, s + G.st[c], b, eta));
-  T ec = T(0.5) * (eta_j<T>(S, G, s, c, eta) + eta_j<T>(S, G, s + G.st[b], c, eta));
-  int l = s - G.st[a];
-  T bbl = (T)(0.5 * (S.b[b][l] + S.b[b][l + G.st[b]]));
-  T bbr = (T)(0.5 * (S.b[b][s] + S.b[b][s + G.st[b]]));
-  T bcl = (T)(0.5 * (S.b[c][l] + S.b[c][l + G.st[c]]));
-  T bcr = (T)(0.5 * (S.b[c][s] + S.b[c][s + G.st[c]]));
-  return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
-}
-
-// Replace the flux at every interior x_a face that touches a flagged cell by
-// the first-order flux from S^n (stage 0: the stage-1 flux; stage 1: both
-// stored fluxes, so that their RK average is the FO flux).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_fo_face(State Sn, Geom G, Work<T> W, int a, int stage, double gamma, double eta_d,
-              const int* stop) {
-  if (*stop) return;
-  if (W.nflag[stage] == 0) return;
-  int t = gidx();
-  int nf = G.n[0] * G.n[1] * G.n[2];
-  if (t >= nf) return;
-  int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
-  int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-  int l3[3] = {s3[0], s3[1], s3[2]};
-  l3[a] -= 1;
-  if (!W.flag[interior_id(G, s3[0], s3[1], s3[2])] && !W.flag[interior_id(G, l3[0], l3[1], l3[2])]) return;
-  T F[5], us;
-  fo_face<T>(Sn, G, s, a, gamma, F, us);
-  if (eta_d > 0.0) F[4] += joule_sn<T>(Sn, G, s, a, (T)eta_d);
-  // periodic images: the update reads faces s and s + e_a of interior cells,
-  // so the face at the upper boundary (s_a = g + n_a) holds the same value
-#pragma unroll
-  for (int rep = 0; rep < 2; ++rep) {
-    int sw = s + (rep ? G.n[a] * G.st[a] : 0);
-    if (rep && s3[a] != G.g) break;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      W.F[stage][a][m][sw] = F[m];
-      if (stage == 1) W.F[0][a][m][sw] = F[m];
-    }
-  }
-}
-
 template <typename T, int EMF>
 __device__ __forceinline__ T fo_corner_cell(const State& Sn, const Geom& G, int s, int a, int b,
                                             double gamma, T baY, T bbX) {
   // ideal EMF of a cell (PC): -u_a b_b + u_b b_a, from cell-centred values
-  T rho, u[3], p, bc[3];
-  pc_cell<T>(Sn, G, s, gamma, rho, u, p, bc);
-  if (EMF == kB25A) return -u[a] * bc[b] + u[b] * bc[a];
-  return -u[a] * bbX + u[b] * baY;  // FS18 with PC: cell velocity, edge field
+  double rho, u[3], p, bc[3];
+  cell_prim(Sn, G, s, gamma, rho, u, p, bc);
+  if (EMF == kB25A) return -(T)u[a] * (T)bc[b] + (T)u[b] * (T)bc[a];
+  return -(T)u[a] * bbX + (T)u[b] * baY;  // FS18 with PC: cell velocity, edge field
 }
 
-// Replace the EMF at every interior edge that touches a flagged cell by the
-// first-order EMF from S^n.
+// One thread per interior cell position s: its three lower faces and the
+// three edges at its lower corner.  Stage 1 writes both stored flux sets so
+// that their RK average is the first-order value.  Periodic images of the
+// upper boundary faces / edges are written as well (the update reads them).
 template <typename T, int EMF>
 __global__ void __launch_bounds__(kBlock)
-    k_fo_edge(State Sn, Geom G, Work<T> W, int c, int stage, double gamma, double eta_d,
-              const int* stop) {
+    k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
   if (*stop) return;
   if (W.nflag[stage] == 0) return;
   int t = gidx();
   int nf = G.n[0] * G.n[1] * G.n[2];
   if (t >= nf) return;
-  const int a = (c + 1) % 3, b = (c + 2) % 3;
-  int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
-  int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-  int fl = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int p3[3] = {s3[0], s3[1], s3[2]};
-    p3[a] -= (q & 1);
-    p3[b] -= (q >> 1);
-    fl |= W.flag[interior_id(G, p3[0], p3[1], p3[2])];
-  }
-  if (!fl) return;
-  const int sa = G.st[a], sb = G.st[b];
-  T F[5];
-  T usaB, usaT, usbL, usbR;
-  T apB = fo_face<T>(Sn, G, s - sb, a, gamma, F, usaB);
-  T apT = fo_face<T>(Sn, G, s, a, gamma, F, usaT);
-  T bpL = fo_face<T>(Sn, G, s - sa, b, gamma, F, usbL);
-  T bpR = fo_face<T>(Sn, G, s, b, gamma, F, usbR);
-  T baB = (T)Sn.b[a][s - sb], baT = (T)Sn.b[a][s];
-  T bbL = (T)Sn.b[b][s - sa], bbR = (T)Sn.b[b][s];
-  T e[4];
-  if (EMF == kQ26) {
-    e[0] = -usaB * bbL + usbL * baB;
-    e[1] = -usaB * bbR + usbR * baB;
-    e[2] = -usaT * bbL + usbL * baT;
-    e[3] = -usaT * bbR + usbR * baT;
-  } else {
-    // corner XY is the cell on side X along a and side Y along b
-    e[0] = fo_corner_cell<T, EMF>(Sn, G, s - sa - sb, a, b, gamma, baB, bbL);
-    e[1] = fo_corner_cell<T, EMF>(Sn, G, s - sb, a, b, gamma, baB, bbR);
-    e[2] = fo_corner_cell<T, EMF>(Sn, G, s - sa, a, b, gamma, baT, bbL);
-    e[3] = fo_corner_cell<T, EMF>(Sn, G, s, a, b, gamma, baT, bbR);
-  }
-  T aa = tmax(apB, apT), ab = tmax(bpL, bpR);
-  T eps = ld04(e[0], e[1], e[2], e[3], aa, aa, ab, ab, baB, baT, bbL, bbR);
-  if (eta_d > 0.0) eps += eta_j<T>(Sn, G, s, c, (T)eta_d);
-  // the update reads edges s, s + e_a, s + e_b: also write the periodic images
-  // on the upper boundary rows
-#pragma unroll
-  for (int qa = 0; qa < 2; ++qa)
-#pragma unroll
-    for (int qb = 0; qb < 2; ++qb) {
-      if ((qa && s3[a] != G.g) || (qb && s3[b] != G.g)) continue;
-      int sw = s + (qa ? G.n[a] * sa : 0) + (qb ? G.n[b] * sb : 0);
-      W.E[stage][c][sw] = eps;
-      if (stage == 1) W.E[0][c][sw] = eps;
+  const int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
+  const int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
+  const bool f0 = W.flag[t] != 0;
+  for (int a = 0; a < 3; ++a) {
+    int l3[3] = {s3[0], s3[1], s3[2]};
+    l3[a] -= 1;
+    if (!f0 && !W.flag[interior_id(G, l3[0], l3[1], l3[2])]) continue;
+    T F[5], us;
+    fo_face<T>(Sn, G, s, a, gamma, F, us);
+    if (eta_d > 0.0) F[4] += joule<T>(Sn, G, s, a, (T)eta_d);
+    for (int rep = 0; rep < 2; ++rep) {
+      if (rep && s3[a] != G.g) break;
+      const int sw = s + (rep ? G.n[a] * G.st[a] : 0);
+      for (int m = 0; m < 5; ++m) {
+        W.F[stage][a][m][sw] = F[m];
+        if (stage == 1) W.F[0][a][m][sw] = F[m];
+      }
     }
+  }
+  for (int c = 0; c < 3; ++c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    int fl = 0;
+    for (int q = 0; q < 4; ++q) {
+      int p3[3] = {s3[0], s3[1], s3[2]};
+      p3[a] -= (q & 1);
+      p3[b] -= (q >> 1);
+      fl |= W.flag[interior_id(G, p3[0], p3[1], p3[2])];
+    }
+    if (!fl) continue;
+    const int sa = G.st[a], sb = G.st[b];
+    T F[5];
+    T usaB, usaT, usbL, usbR;
+    T apB = fo_face<T>(Sn, G, s - sb, a, gamma, F, usaB);
+    T apT = fo_face<T>(Sn, G, s, a, gamma, F, usaT);
+    T bpL = fo_face<T>(Sn, G, s - sa, b, gamma, F, usbL);
+    T bpR = fo_face<T>(Sn, G, s, b, gamma, F, usbR);
+    T baB = (T)Sn.b[a][s - sb], baT = (T)Sn.b[a][s];
+    T bbL = (T)Sn.b[b][s - sa], bbR = (T)Sn.b[b][s];
+    T e[4];
+    if (EMF == kQ26) {
+      e[0] = -usaB * bbL + usbL * baB;
+      e[1] = -usaB * bbR + usbR * baB;
+      e[2] = -usaT * bbL + usbL * baT;
+      e[3] = -usaT * bbR + usbR * baT;
+    } else {
+      // corner XY is the cell on side X along a and side Y along b
+      e[0] = fo_corner_cell<T, EMF>(Sn, G, s - sa - sb, a, b, gamma, baB, bbL);
+      e[1] = fo_corner_cell<T, EMF>(Sn, G, s - sb, a, b, gamma, baB, bbR);
+      e[2] = fo_corner_cell<T, EMF>(Sn, G, s - sa, a, b, gamma, baT, bbL);
+      e[3] = fo_corner_cell<T, EMF>(Sn, G, s, a, b, gamma, baT, bbR);
+    }
+    T aa = tmax(apB, apT), ab = tmax(bpL, bpR);
+    T eps = ld04(e[0], e[1], e[2], e[3], aa, aa, ab, ab, baB, baT, bbL, bbR);
+    if (eta_d > 0.0) eps += eta_j<T>(Sn, G, s, c, (T)eta_d);
+    for (int qa = 0; qa < 2; ++qa)
+      for (int qb = 0; qb < 2; ++qb) {
+        if ((qa && s3[a] != G.g) || (qb && s3[b] != G.g)) continue;
+        const int sw = s + (qa ? G.n[a] * sa : 0) + (qb ? G.n[b] * sb : 0);
+        W.E[stage][c][sw] = eps;
+        if (stage == 1) W.E[0][c][sw] = eps;
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -800,26 +923,25 @@ int check_box(const ctmhd_params* p, const ctmhd_box* b) {
   return CTMHD_OK;
 }
 
-// Workspace of one box for stencil type of `tbytes` bytes.
-size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes) {
+// Workspace of one box for the stencil type of `tbytes` bytes.
+size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, int emf) {
   size_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
   size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
   size_t bytes = 0;
-  bytes += 2 * 8 * align256(e * 8);        // two state buffers
-  bytes += (8 + 3) * align256(e * tbytes); // prim + B25a cell EMF
-  bytes += 2 * 15 * align256(e * tbytes);  // fluxes, two stages
-  bytes += 9 * align256(e * tbytes);       // alpha+, alpha-, u*
-  bytes += 6 * align256(e * tbytes);       // EMFs, two stages
-  bytes += align256(ninter);               // flags
-  bytes += 256;                            // scalars
+  bytes += 2 * 8 * align256(e * 8);           // two state buffers
+  if (emf == CTMHD_EMF_B25A) bytes += 3 * align256(e * tbytes);  // cell EMF
+  if (emf == CTMHD_EMF_FS18) bytes += 3 * align256(e * tbytes);  // cell velocity
+  bytes += 2 * 15 * align256(e * tbytes);     // fluxes, two stages
+  bytes += 9 * align256(e * tbytes);          // alpha+, alpha-, u*
+  bytes += 6 * align256(e * tbytes);          // EMFs, two stages
+  bytes += align256(ninter);                  // flags
+  bytes += align256(2 * kMaxSlots * 8) + 256; // CFL slots + scalars
   return bytes;
 }
 
-template <typename T>
 struct Carve {
   char* p;
-  char* end;
   template <typename U>
   U* take(size_t n) {
     U* r = (U*)p;
@@ -829,34 +951,39 @@ struct Carve {
 };
 
 template <typename T>
-int build_work(void* ws, size_t ws_bytes, const ctmhd_box& b, Work<T>& W, State& A2, State& H) {
-  size_t need = box_ws_bytes(b, sizeof(T));
+int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_box& b, Work<T>& W,
+               State& A2, State& H) {
+  size_t need = box_ws_bytes(b, sizeof(T), prm->emf_compute);
   if (!ws || ws_bytes < need) return fail(CTMHD_EARG, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
   size_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
   size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
-  Carve<T> cv{(char*)ws, (char*)ws + ws_bytes};
-  for (int m = 0; m < 5; ++m) A2.c[m] = cv.template take<double>(e);
-  for (int a = 0; a < 3; ++a) A2.b[a] = cv.template take<double>(e);
-  for (int m = 0; m < 5; ++m) H.c[m] = cv.template take<double>(e);
-  for (int a = 0; a < 3; ++a) H.b[a] = cv.template take<double>(e);
-  for (int v = 0; v < 8; ++v) W.prim[v] = cv.template take<T>(e);
-  for (int c = 0; c < 3; ++c) W.ecell[c] = cv.template take<T>(e);
+  Carve cv{(char*)ws};
+  for (int m = 0; m < 5; ++m) A2.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) A2.b[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) H.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) H.b[a] = cv.take<double>(e);
+  for (int v = 0; v < 8; ++v) W.prim[v] = nullptr;
+  for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
+  if (prm->emf_compute == CTMHD_EMF_B25A)
+    for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
+  if (prm->emf_compute == CTMHD_EMF_FS18)
+    for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
   for (int st = 0; st < 2; ++st)
     for (int a = 0; a < 3; ++a)
-      for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.template take<T>(e);
-  for (int a = 0; a < 3; ++a) W.ap[a] = cv.template take<T>(e);
-  for (int a = 0; a < 3; ++a) W.am[a] = cv.template take<T>(e);
-  for (int a = 0; a < 3; ++a) W.us[a] = cv.template take<T>(e);
+      for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.ap[a] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.am[a] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.us[a] = cv.take<T>(e);
   for (int st = 0; st < 2; ++st)
-    for (int c = 0; c < 3; ++c) W.E[st][c] = cv.template take<T>(e);
-  W.flag = cv.template take<uint8_t>(ninter);
+    for (int c = 0; c < 3; ++c) W.E[st][c] = cv.take<T>(e);
+  W.flag = cv.take<uint8_t>(ninter);
+  W.smax = cv.take<unsigned long long>(2 * kMaxSlots);
   char* sc = cv.p;
-  W.smax = (unsigned long long*)sc;
-  W.dt = (double*)(sc + 8);
-  W.stop = (int*)(sc + 16);
-  W.nflag = (int*)(sc + 24);
+  W.dt = (double*)sc;
+  W.stop = (int*)(sc + 8);
+  W.nflag = (int*)(sc + 16);
   return CTMHD_OK;
 }
 
@@ -882,100 +1009,109 @@ inline void prof_end(hipStream_t st) {
     if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: " #kern); \
   } while (0)
 
-// Dispatch helpers: template kernels selected at run time.
+// Face plan: ranges and launch shape of the fused face kernel.
+FacePlan make_face_plan(const Geom& G, int recon, int emf) {
+  FacePlan P;
+  const int r = recon_halfwidth(recon);
+  const int g = G.g;
+  // Q26 reconstructs u* along the transverse axes to the edges, which needs
+  // faces r+1 beyond the edge range [g, g+n]; the other schemes only need
+  // alpha on the faces next to the edges.
+  const int tlo = emf == CTMHD_EMF_Q26 ? g - 1 - r : g - 1;
+  P.tlo = tlo;
+  for (int d = 0; d < 3; ++d) {
+    P.lo[d] = g;
+    P.nf[d] = G.n[d] + 1;  // faces g .. g+n read by the update and the edges
+    P.tlen[d] = (emf == CTMHD_EMF_Q26 ? g + G.n[d] + r : g + G.n[d]) - tlo + 1;
+    P.ulo[d] = g;
+    P.ulen[d] = G.n[d];
+  }
+  // x part
+  P.xseg = 64 - 2 * r - 1;
+  P.xnseg = (P.nf[0] + P.xseg - 1) / P.xseg;
+  P.xwaves = P.xnseg * P.tlen[1] * P.tlen[2];
+  P.xblocks = (P.xwaves + kBlock / 64 - 1) / (kBlock / 64);
+  // y and z parts: enough chunks along the march for ~8192 waves in flight
+  P.total_blocks = P.xblocks;
+  for (int A = 1; A <= 2; ++A) {
+    const int C = A == 1 ? 2 : 1;
+    P.lanes[A] = P.tlen[0] * P.tlen[C];
+    P.lblocks[A] = (P.lanes[A] + kBlock - 1) / kBlock;
+    int want = (8192 * 64 / kBlock) / (P.lblocks[A] > 0 ? P.lblocks[A] : 1);
+    int maxch = (P.nf[A] + 31) / 32;  // chunks of at least ~32 faces (window warm-up 2r+1)
+    if (want > maxch) want = maxch;
+    if (want < 1) want = 1;
+    P.chunk[A] = (P.nf[A] + want - 1) / want;
+    P.nchunk[A] = (P.nf[A] + P.chunk[A] - 1) / P.chunk[A];
+    P.blocks[A] = P.lblocks[A] * P.nchunk[A];
+    P.total_blocks += P.blocks[A];
+  }
+  P.chunk[0] = P.nchunk[0] = P.lanes[0] = P.lblocks[0] = P.blocks[0] = 0;
+  return P;
+}
+
 template <typename T, int RECON>
-int launch_face(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
-                Range R, int a, int stage, Range upd, long long* diag) {
-  if (R.count() <= 0) return CTMHD_OK;
+int launch_faces(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
+                 const FacePlan& FP, int stage, long long* diag) {
   prof_begin(st);
   if (p->riemann == CTMHD_RIEMANN_HLLD)
-    LAUNCH((k_face<T, RECON, kHLLD>), nblocks(R.count()), S, G, W, R, a, stage, p->gamma, p->eta, upd,
-           diag, W.stop);
+    LAUNCH((k_faces<T, RECON, kHLLD>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta, diag,
+           W.stop);
   else
-    LAUNCH((k_face<T, RECON, kLLF>), nblocks(R.count()), S, G, W, R, a, stage, p->gamma, p->eta, upd,
-           diag, W.stop);
+    LAUNCH((k_faces<T, RECON, kLLF>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta, diag,
+           W.stop);
   prof_end(st);
   return CTMHD_OK;
 }
 
 template <typename T, int RECON>
 int launch_emf(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
-               Range R, int c, int stage) {
+               int stage) {
+  const int cnt = (G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
   if (p->emf_compute == CTMHD_EMF_Q26)
-    LAUNCH((k_emf<T, RECON, kQ26>), nblocks(R.count()), S, G, W, R, c, stage, p->eta, W.stop);
+    LAUNCH((k_emf3<T, RECON, kQ26>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
   else if (p->emf_compute == CTMHD_EMF_B25A)
-    LAUNCH((k_emf<T, RECON, kB25A>), nblocks(R.count()), S, G, W, R, c, stage, p->eta, W.stop);
+    LAUNCH((k_emf3<T, RECON, kB25A>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
   else
-    LAUNCH((k_emf<T, RECON, kFS18>), nblocks(R.count()), S, G, W, R, c, stage, p->eta, W.stop);
+    LAUNCH((k_emf3<T, RECON, kFS18>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
   return CTMHD_OK;
 }
 
 template <typename T>
-int launch_prim(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W) {
-  if (p->emf_compute == CTMHD_EMF_B25A)
-    LAUNCH((k_prim<T, kB25A>), nblocks(G.elems), S, G, W, p->gamma, W.stop);
-  else
-    LAUNCH((k_prim<T, kQ26>), nblocks(G.elems), S, G, W, p->gamma, W.stop);
-  return CTMHD_OK;
-}
-
-template <typename T>
-int launch_fo_edge(hipStream_t st, const ctmhd_params* p, State Sn, const Geom& G, const Work<T>& W,
-                   int c, int stage, int ninter) {
+int launch_fo(hipStream_t st, const ctmhd_params* p, State Sn, const Geom& G, const Work<T>& W,
+              int stage, int ninter) {
   if (p->emf_compute == CTMHD_EMF_Q26)
-    LAUNCH((k_fo_edge<T, kQ26>), nblocks(ninter), Sn, G, W, c, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kQ26>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
   else if (p->emf_compute == CTMHD_EMF_B25A)
-    LAUNCH((k_fo_edge<T, kB25A>), nblocks(ninter), Sn, G, W, c, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kB25A>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
   else
-    LAUNCH((k_fo_edge<T, kFS18>), nblocks(ninter), Sn, G, W, c, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kFS18>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
   return CTMHD_OK;
 }
 
 // One stage: fluxes and EMFs of `in`, update into `out` from `base` = S^n.
 template <typename T, int RECON>
-int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T>& W, State in,
-              State base, State out, int stage, const uint8_t* force, long long* diag) {
+int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T>& W,
+              const FacePlan& FP, State in, State base, State out, int stage, double sres,
+              long long* diag) {
   int rc;
-  if ((rc = launch_prim<T>(st, p, in, G, W))) return rc;
-  const int r = recon_halfwidth(RECON);
-  const int g = G.g;
-  Range upd;
-  for (int d = 0; d < 3; ++d) {
-    upd.lo[d] = g;
-    upd.len[d] = G.n[d];
-  }
-  for (int a = 0; a < 3; ++a) {
-    Range R, U = upd;
-    for (int d = 0; d < 3; ++d) {
-      if (d == a) {
-        R.lo[d] = g - 1;
-        R.len[d] = G.n[d] + 2;  // [g-1, g+n]
-      } else {
-        R.lo[d] = 0;
-        R.len[d] = g + G.n[d] + r + 1;  // [0, g+n+r]
-      }
-    }
-    U.len[a] = G.n[a] + 1;  // faces g .. g+n along a are read by the update
-    if ((rc = launch_face<T, RECON>(st, p, in, G, W, R, a, stage, U, diag))) return rc;
-  }
-  for (int c = 0; c < 3; ++c) {
-    Range R;
-    for (int d = 0; d < 3; ++d) {
-      R.lo[d] = g;
-      R.len[d] = G.n[d] + (d == c ? 0 : 1);
-    }
-    if ((rc = launch_emf<T, RECON>(st, p, in, G, W, R, c, stage))) return rc;
-  }
+  if (p->emf_compute == CTMHD_EMF_B25A)
+    LAUNCH((k_prim<T, kB25A>), nblocks(G.elems), in, G, W, p->gamma, W.stop);
+  else if (p->emf_compute == CTMHD_EMF_FS18)
+    LAUNCH((k_prim<T, kFS18>), nblocks(G.elems), in, G, W, p->gamma, W.stop);
+  if ((rc = launch_faces<T, RECON>(st, p, in, G, W, FP, stage, diag))) return rc;
+  if ((rc = launch_emf<T, RECON>(st, p, in, G, W, stage))) return rc;
   const int ninter = G.n[0] * G.n[1] * G.n[2];
-  LAUNCH(k_update<T>, nblocks(ninter), base, out, G, W, stage, 0, W.stop);
+  UpdateCfg U;
+  U.fofc = p->fofc;
+  U.crit = p->flag_criteria;
+  U.gamma = p->gamma;
+  U.sres = sres;
+  U.force = p->force_flags ? p->force_flags + (size_t)stage * ninter : nullptr;
+  LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 0, U, diag, W.stop);
   if (p->fofc) {
-    LAUNCH(k_flag, nblocks(ninter), out, G, W.flag, force ? force + (size_t)stage * ninter : nullptr,
-           p->flag_criteria, p->gamma, W.nflag + stage, diag ? diag + stage : nullptr, W.stop);
-    for (int a = 0; a < 3; ++a)
-      LAUNCH(k_fo_face<T>, nblocks(ninter), base, G, W, a, stage, p->gamma, p->eta, W.stop);
-    for (int c = 0; c < 3; ++c)
-      if ((rc = launch_fo_edge<T>(st, p, base, G, W, c, stage, ninter))) return rc;
-    LAUNCH(k_update<T>, nblocks(ninter), base, out, G, W, stage, 1, W.stop);
+    if ((rc = launch_fo<T>(st, p, base, G, W, stage, ninter))) return rc;
+    LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 1, U, diag, W.stop);
   }
   return CTMHD_OK;
 }
@@ -987,26 +1123,27 @@ int step_box(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
   Geom G = make_geom(*box);
   Work<T> W;
   State B, H;
-  int rc = build_work<T>(ws, ws_bytes, *box, W, B, H);
+  int rc = build_work<T>(p, ws, ws_bytes, *box, W, B, H);
   if (rc) return rc;
   State A;
   for (int m = 0; m < 5; ++m) A.c[m] = cons[m];
   for (int a = 0; a < 3; ++a) A.b[a] = bface[a];
   const State user = A;
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute);
   double dxmin = fmin(G.dx[0], fmin(G.dx[1], G.dx[2]));
   double sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
   const int ninter = G.n[0] * G.n[1] * G.n[2];
-  LAUNCH(k_init, 1, W.stop);
+  LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
+  LAUNCH(k_wrap, nblocks(G.elems), A, G, W.stop);
+  int dtb = nblocks(ninter);
+  if (dtb > 2048) dtb = 2048;
+  LAUNCH(k_dt, dtb, A, G, p->gamma, sres, W.smax, W.stop);
   for (int n = 0; n < nsteps; ++n) {
     long long* dg = diag ? (long long*)diag + 4 * n : nullptr;
-    LAUNCH(k_begin, 1, W.smax, W.nflag, dg, W.stop);
-    LAUNCH(k_wrap, nblocks(G.elems), A, G, W.stop);
-    if (!dt_fixed) LAUNCH(k_dt, nblocks(ninter), A, G, p->gamma, sres, W.smax, W.stop);
-    LAUNCH(k_dt_final, 1, W.smax, p->cfl, dt_fixed ? dt_fixed + n : nullptr, W.dt,
+    LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt_fixed ? dt_fixed + n : nullptr, W.dt,
            dt_out ? dt_out + n : nullptr, W.stop, dg);
-    if ((rc = run_stage<T, RECON>(st, p, G, W, A, A, H, 0, p->force_flags, dg))) return rc;
-    LAUNCH(k_wrap, nblocks(G.elems), H, G, W.stop);
-    if ((rc = run_stage<T, RECON>(st, p, G, W, H, A, B, 1, p->force_flags, dg))) return rc;
+    if ((rc = run_stage<T, RECON>(st, p, G, W, FP, A, A, H, 0, sres, dg))) return rc;
+    if ((rc = run_stage<T, RECON>(st, p, G, W, FP, H, A, B, 1, sres, dg))) return rc;
     // a stopped step leaves the state where it was: carry it to the next buffer
     LAUNCH(k_copy, nblocks(G.elems), B, A, G.elems, W.stop);
     State tmp = A;
@@ -1014,9 +1151,6 @@ int step_box(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
     B = tmp;
   }
   if (A.c[0] != user.c[0]) LAUNCH(k_copy, nblocks(G.elems), user, A, G.elems, (const int*)nullptr);
-  // ghosts of the result hold the periodic copy on return
-  LAUNCH(k_init, 1, W.stop);
-  LAUNCH(k_wrap, nblocks(G.elems), user, G, W.stop);
   return CTMHD_OK;
 }
 
@@ -1056,7 +1190,7 @@ int64_t ctmhd_box_elems(const ctmhd_box* b) {
 size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
   if (check_params(p) || !boxes || nbox < 1) return 0;
   size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
-  if (nbox == 1) return box_ws_bytes(boxes[0], tb);
+  if (nbox == 1) return box_ws_bytes(boxes[0], tb, p->emf_compute);
   return 0;
 }
 

@@ -19,9 +19,17 @@ __host__ __device__ constexpr int recon_halfwidth(int m) {
   return m == kPC ? 0 : (m == kPPM ? 2 : 1);
 }
 
-template <typename T> __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
-template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
-template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a <= b ? a : b; }
+// abs / min / max / sign transfer as single instructions (v_max_f64 etc.);
+// on non-NaN operands they return the same values as the comparisons
+// a >= b ? a : b and x < 0 ? -x : x (up to the sign of a zero).
+__device__ __forceinline__ double tabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float tabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double tmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tsign(double mag, double s) { return __builtin_copysign(mag, s); }
+__device__ __forceinline__ float tsign(float mag, float s) { return __builtin_copysignf(mag, s); }
 __device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ bool tfinite(double x) { return __builtin_isfinite(x); }
@@ -41,7 +49,7 @@ __device__ __forceinline__ T plm_slope(T qm, T q0, T qp) {
     s = tmin(tmin(T(2) * tabs(dl), T(2) * tabs(dr)), T(0.5) * tabs(dl + dr));
   else
     s = tmin(tabs(dl), tabs(dr));
-  s = dr > T(0) ? s : -s;
+  s = tsign(s, dr);  // dl * dr > 0: dr carries the common sign
   return dl * dr > T(0) ? s : T(0);
 }
 
@@ -50,8 +58,34 @@ __device__ __forceinline__ T ppm_slope(T qm, T q0, T qp) {
   T dl = q0 - qm, dr = qp - q0;
   T dc = T(0.5) * (qp - qm);
   T s = tmin(tabs(dc), T(2) * tmin(tabs(dl), tabs(dr)));
-  s = dc > T(0) ? s : -s;
+  s = tsign(s, dc);  // dl * dr > 0: dc carries the common sign
   return dl * dr > T(0) ? s : T(0);
+}
+
+// PPM interface value between cells with values qa, qb and limited slopes
+// da, db (Colella-Woodward).
+template <typename T>
+__device__ __forceinline__ T ppm_iface(T qa, T qb, T da, T db) {
+  return T(0.5) * (qa + qb) - (db - da) * (T(1) / T(6));
+}
+
+// Colella-Woodward monotonicity constraints on a cell with centre value q0
+// and face values qL, qR (in place).
+template <typename T>
+__device__ __forceinline__ void ppm_constrain(T q0, T& qL, T& qR) {
+  const T sixth = T(1) / T(6);
+  if ((qR - q0) * (q0 - qL) <= T(0)) {
+    qL = q0;
+    qR = q0;
+  } else {
+    T dq = qR - qL;
+    T q6 = dq * (q0 - T(0.5) * (qL + qR));
+    T d6 = dq * dq * sixth;
+    if (q6 > d6)
+      qL = T(3) * q0 - T(2) * qR;
+    else if (-d6 > q6)
+      qR = T(3) * q0 - T(2) * qL;
+  }
 }
 
 template <int M, typename T>
@@ -64,29 +98,52 @@ __device__ __forceinline__ void recon_cell(const T* q, T& qm, T& qp) {
     qm = q[2] - s;
     qp = q[2] + s;
   } else {
-    const T sixth = T(1) / T(6);
     T d1 = ppm_slope(q[0], q[1], q[2]);
     T d2 = ppm_slope(q[1], q[2], q[3]);
     T d3 = ppm_slope(q[2], q[3], q[4]);
-    T qL = T(0.5) * (q[1] + q[2]) - (d2 - d1) * sixth;
-    T qR = T(0.5) * (q[2] + q[3]) - (d3 - d2) * sixth;
-    T q0 = q[2];
-    if ((qR - q0) * (q0 - qL) <= T(0)) {
-      qL = q0;
-      qR = q0;
-    } else {
-      T dq = qR - qL;
-      T q6 = dq * (q0 - T(0.5) * (qL + qR));
-      T d6 = dq * dq * sixth;
-      if (q6 > d6)
-        qL = T(3) * q0 - T(2) * qR;
-      else if (-d6 > q6)
-        qR = T(3) * q0 - T(2) * qL;
-    }
+    T qL = ppm_iface(q[1], q[2], d1, d2);
+    T qR = ppm_iface(q[2], q[3], d2, d3);
+    ppm_constrain(q[2], qL, qR);
     qm = qL;
     qp = qR;
   }
 }
+
+// Streaming reconstruction along a line of cells: push the cell values in
+// order; after the warm-up each push completes the cell r behind the newest
+// one and returns its lower / upper face values.  Every limited slope and
+// interface value is formed once and gives the same numbers as recon_cell.
+template <int M, typename T>
+struct ReconStream {
+  T q1 = T(0), q2 = T(0);  // the previous two cells (q1 newest)
+  T dm1 = T(0);            // PPM: limited slope of the cell behind q1
+  T ilo = T(0);            // PPM: interface below the cell completed next
+  __device__ __forceinline__ void push(T v, T& qm, T& qp) {
+    if constexpr (M == kPC) {
+      qm = v;
+      qp = v;
+    } else if constexpr (M == kPLM_MC || M == kPLM_MM) {
+      // completes cell q1 (values q2, q1, v)
+      T s = T(0.5) * plm_slope<M>(q2, q1, v);
+      qm = q1 - s;
+      qp = q1 + s;
+      q2 = q1;
+      q1 = v;
+    } else {
+      // slope of cell q1, interface between q2 and q1, completes cell q2
+      T dm = ppm_slope(q2, q1, v);
+      T ihi = ppm_iface(q2, q1, dm1, dm);
+      T qL = ilo, qR = ihi;
+      ppm_constrain(q2, qL, qR);
+      qm = qL;
+      qp = qR;
+      ilo = ihi;
+      dm1 = dm;
+      q2 = q1;
+      q1 = v;
+    }
+  }
+};
 
 // Whether entry m of the six-point sequence q[0..5] below enters the
 // reconstruction at the q[2]|q[3] interface: m in [2 - r, 3 + r].
@@ -100,9 +157,25 @@ __host__ __device__ constexpr bool stencil_uses(int m) {
 // cell 3.
 template <int M, typename T>
 __device__ __forceinline__ void recon_iface(const T* q, T& lo, T& hi) {
-  T d;
-  recon_cell<M>(q, d, lo);
-  recon_cell<M>(q + 1, hi, d);
+  if constexpr (M == kPPM) {
+    // cells 2 and 3 share slopes d2, d3 and the interface between them
+    T d1 = ppm_slope(q[0], q[1], q[2]);
+    T d2 = ppm_slope(q[1], q[2], q[3]);
+    T d3 = ppm_slope(q[2], q[3], q[4]);
+    T d4 = ppm_slope(q[3], q[4], q[5]);
+    T i1 = ppm_iface(q[1], q[2], d1, d2);
+    T i2 = ppm_iface(q[2], q[3], d2, d3);
+    T i3 = ppm_iface(q[3], q[4], d3, d4);
+    T aL = i1, aR = i2, bL = i2, bR = i3;
+    ppm_constrain(q[2], aL, aR);
+    ppm_constrain(q[3], bL, bR);
+    lo = aR;
+    hi = bL;
+  } else {
+    T d;
+    recon_cell<M>(q, d, lo);
+    recon_cell<M>(q + 1, hi, d);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -148,7 +221,7 @@ __device__ __forceinline__ void phys_flux(const FState<T>& s, T bn, T gm1inv, T*
 template <typename T>
 __device__ __forceinline__ T llf_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
                                       T* F) {
-  T gm1inv = T(1) / (gamma - T(1));
+  const T gm1inv = T(1) / (gamma - T(1));
   T UL[5], FL[5], UR[5], FR[5], pL, pR;
   phys_flux(L, bn, gm1inv, UL, FL, pL);
   phys_flux(R, bn, gm1inv, UR, FR, pR);
@@ -192,7 +265,8 @@ __device__ __forceinline__ int hlld_flux(const FState<T>& L, const FState<T>& R,
   T SM = (mR * R.un - mL * L.un - pTR + pTL) * iden;
   T pTs = (mR * pTL - mL * pTR + mL * mR * (R.un - L.un)) * iden;
   T dsL = SL - SM, dsR = SR - SM;
-  T rsL = mL / dsL, rsR = mR / dsR;
+  T idsL = T(1) / dsL, idsR = T(1) / dsR;
+  T rsL = mL * idsL, rsR = mR * idsR;
 
   // star transverse states
   T vsL, wsL, bysL, bzsL, vsR, wsR, bysR, bzsR;
@@ -224,8 +298,8 @@ __device__ __forceinline__ int hlld_flux(const FState<T>& L, const FState<T>& R,
   T vbR = R.un * bn + R.ut1 * R.bt1 + R.ut2 * R.bt2;
   T vbsL = SM * bn + vsL * bysL + wsL * bzsL;
   T vbsR = SM * bn + vsR * bysR + wsR * bzsR;
-  T esL = (dL * UL[4] - pTL * L.un + pTs * SM + bn * (vbL - vbsL)) / dsL;
-  T esR = (dR * UR[4] - pTR * R.un + pTs * SM + bn * (vbR - vbsR)) / dsR;
+  T esL = (dL * UL[4] - pTL * L.un + pTs * SM + bn * (vbL - vbsL)) * idsL;
+  T esR = (dR * UR[4] - pTR * R.un + pTs * SM + bn * (vbR - vbsR)) * idsR;
 
   bool bad = !(rsL > T(0)) || !(rsR > T(0)) || !(pTs > T(0)) || !(SL < SM) || !(SM < SR) ||
              !tfinite(SM) || !tfinite(vsL + wsL + bysL + bzsL + esL) ||
