@@ -1,0 +1,87 @@
+"""The FP32 form (stencil arithmetic in float32; pressure recovery, dt and the
+state / face-b accumulation in float64) against the FP64 oracle.
+
+Bar: relative L1 error <= 1e-5 per field after 100 steps of the Mach-5
+turbulent box; conservation and discrete div b at FP64 round-off (the FP32
+fluxes and EMFs are single-valued per face and edge and accumulated in FP64).
+Every measured error is printed ("[fp32]" lines).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import divb_rel, rel_l1
+from paper_2609_10816_amd import ctmhd, inputs
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["rho", "m0", "m1", "m2", "e_tot", "b0", "b1", "b2"]
+
+
+def _field_errors(cg, bg, co, bo):
+    errs = {}
+    for m in range(5):
+        errs[NAMES[m]] = rel_l1(cg[m], co[m])
+    for a in range(3):
+        errs[NAMES[5 + a]] = rel_l1(bg[a], bo[a])
+    return errs
+
+
+def _conserved(c0, c1, tol=1e-13):
+    for m in range(5):
+        scale = np.abs(c0[m]).sum() + np.abs(c1[m]).sum()
+        assert abs(c1[m].sum() - c0[m].sum()) <= tol * scale, m
+
+
+@pytest.mark.parametrize("emf", ["q26", "b25a"])
+def test_fp32_vs_oracle_100_steps(emf):
+    n = 48
+    cons, bf, info = inputs.turbulent_box((n, n, n), mach=5.0, b0=(0.1, 0.0, 0.0), db_rms=0.05,
+                                          seed_v=1, seed_a=2)
+    dx = info["dx"]
+    co, bo, dts, do = oracle.step(dict(recon="ppm", emf=emf), cons, bf, dx, nsteps=100)
+    P = ctmhd.make_params(recon="ppm", emf=emf, precision="fp32")
+    cg, bg, dtg, dg = ctmhd.run(P, cons, bf, dx, 100, dt_fixed=dts)
+    errs = _field_errors(cg, bg, co, bo)
+    print(f"[fp32] {n}^3 Mach-5 PPM {emf}, 100 steps vs FP64 oracle: " +
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+    _conserved(cons, cg)
+    assert divb_rel(bg, dx) < 1e-13
+    assert int(dg[:, :2].sum()) == int(do[0] + do[1])
+
+
+def test_fp32_one_step_close():
+    """One step: FP32 rounding only (~1e-7 relative)."""
+    cons, bf, info = inputs.turbulent_box((24, 20, 16), mach=2.0, b0=(1.0, 0.0, 0.0), db_rms=0.5,
+                                          seed_v=3, seed_a=4)
+    dx = [1 / 24, 1 / 20, 1 / 16]
+    co, bo, dts, _ = oracle.step(dict(recon="ppm", eta=1e-3), cons, bf, dx, nsteps=1)
+    P = ctmhd.make_params(recon="ppm", eta=1e-3, precision="fp32")
+    cg, bg, dtg, _ = ctmhd.run(P, cons, bf, dx, 1)
+    assert dtg[0] == pytest.approx(dts[0], rel=1e-13)  # dt stays FP64
+    errs = _field_errors(cg, bg, co, bo)
+    print("[fp32] one step 24x20x16 Mach-2 eta 1e-3: " +
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) <= 1e-6
+
+
+def test_fp32_full_size_128_100_steps():
+    """The 128^3 Mach-5 turbulent workload, 100 steps: FP32 form against the
+    FP64 path (which matches the oracle step by step to 1e-12), same dt
+    sequence; plus the FP32 form's invariants at full size."""
+    import torch
+    cons, bf, info = inputs.turbulent_mach5(128)
+    dx = info["dx"]
+    P64 = ctmhd.make_params(recon="ppm", emf="q26")
+    c64, b64, dts, d64 = ctmhd.run(P64, cons, bf, dx, 100)
+    P32 = ctmhd.make_params(recon="ppm", emf="q26", precision="fp32")
+    c32, b32, _, d32 = ctmhd.run(P32, cons, bf, dx, 100, dt_fixed=dts)
+    errs = _field_errors(c32, b32, c64, b64)
+    print("[fp32] 128^3 Mach-5 PPM q26, 100 steps vs FP64 path: " +
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+          f" flagged fp64={int(d64[:, :2].sum())} fp32={int(d32[:, :2].sum())}", flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+    _conserved(cons, c32)
+    assert divb_rel(b32, dx) < 1e-13
+    torch.cuda.empty_cache()

@@ -1,0 +1,68 @@
+"""Parity at full size: the 256^3 Mach-2, beta-1, eta = 1e-3 turbulent box
+(PPM + HLLD + Q26/B25a + LD04, FP64), one step in the launch configuration the
+benchmark times.
+
+The oracle cannot step 16.7 M cells quickly, but one step only couples a cell
+to its neighbours within a bounded distance (reconstruction half-width 2, the
+u* shell of the edges, two RK stages: < 16 cells).  For seeded sample cells
+the oracle steps a periodic window of half-width 20 cropped around the cell,
+with the GPU's dt; the sampled cell's 5 conserved values and its 3 lower faces
+must agree to 1e-12 of the field scale.  dt (a global maximum),
+conservation and div b are checked on the whole box.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import divb_rel
+from paper_2609_10816_amd import ctmhd, inputs
+
+pytestmark = pytest.mark.gpu
+
+HW = 20  # window half-width
+
+
+def _crop(a, k, j, i):
+    idx = [np.arange(c - HW, c + HW + 1) for c in (k, j, i)]
+    out = np.take(a, idx[0], axis=-3, mode="wrap")
+    out = np.take(out, idx[1], axis=-2, mode="wrap")
+    return np.take(out, idx[2], axis=-1, mode="wrap")
+
+
+@pytest.mark.parametrize("emf", ["q26", "b25a"])
+def test_full_size_256_sampled(emf):
+    n = 256
+    cons, bf, info = inputs.turbulent_mach2_beta1(n)
+    dx = info["dx"]
+    P = ctmhd.make_params(recon="ppm", emf=emf, eta=1e-3)
+    cg, bg, dtg, dg = ctmhd.run(P, cons, bf, dx, 1)
+    Q = dict(recon="ppm", emf=emf, eta=1e-3)
+    dt_oracle = oracle.cfl_dt(Q, cons, bf, dx)
+    assert dtg[0] == pytest.approx(dt_oracle, rel=1e-13)
+    # whole-box invariants of the GPU result
+    for m in range(5):
+        scale = np.abs(cons[m]).sum() + np.abs(cg[m]).sum()
+        assert abs(cg[m].sum() - cons[m].sum()) <= 1e-13 * scale, m
+    assert divb_rel(bg, dx) < 1e-13
+    # sampled cells against the oracle on cropped periodic windows
+    rng = np.random.default_rng(2026)
+    samples = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(14)]
+    samples += [(0, 0, 0), (n - 1, n - 1, n - 1)]  # the periodic seams
+    cscale = [np.abs(cons[m]).mean() for m in range(5)]
+    cscale[1] = cscale[2] = cscale[3] = cscale[0] * 3.0  # rho times the signal speed
+    bscale = np.abs(bf).mean()
+    worst = 0.0
+    for (k, j, i) in samples:
+        cw = _crop(cons, k, j, i)
+        bw = _crop(bf, k, j, i)
+        co, bo, _, do = oracle.step(Q, cw, bw, dx, nsteps=1, dt_fixed=[dtg[0]])
+        for m in range(5):
+            d = abs(cg[m, k, j, i] - co[m, HW, HW, HW]) / cscale[m]
+            worst = max(worst, d)
+            assert d <= 1e-12, (emf, (k, j, i), m, d)
+        for a in range(3):
+            d = abs(bg[a, k, j, i] - bo[a, HW, HW, HW]) / bscale
+            worst = max(worst, d)
+            assert d <= 1e-12, (emf, (k, j, i), "b", a, d)
+    print(f"[fullsize] 256^3 {emf}: dt {dtg[0]:.6e} (oracle {dt_oracle:.6e}), 16 sampled cells, "
+          f"worst scaled difference {worst:.2e}, flagged {int(dg[0, :2].sum())}", flush=True)
