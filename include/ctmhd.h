@@ -85,7 +85,9 @@ typedef struct ctmhd_params {
   int32_t fofc;          /* 1: first-order flux correction on, 0: off */
   int32_t flag_criteria; /* OR of CTMHD_FLAG_* */
   int32_t precision;     /* CTMHD_FP64 or CTMHD_FP32 */
-  int32_t reserved;      /* must be 0 */
+  int32_t tile;          /* launch-shape knob (0 = defaults): bits 0-7 minimum faces per
+                            marching chunk of the face pass (default 32), bits 8-15
+                            256-element strips per work item of the batched call (default 1) */
   /* Test hook: NULL, or a DEVICE mask of 2 * n0*n1*n2 bytes (stage-1 mask then
    * stage-2 mask, interior cells, x0 fastest) OR-ed into the invalid-cell
    * flags of every step.  Single-box call only. */
@@ -106,7 +108,7 @@ int ctmhd_required_ghosts(const ctmhd_params* p);
 /* Elements (not bytes) of one field array of a box: prod(n_d + 2 ng). */
 int64_t ctmhd_box_elems(const ctmhd_box* box);
 
-/* Workspace bytes for ctmhd_step (nbox = 1) or ctmhd_step_batched. */
+/* Workspace bytes for ctmhd_step (nbox = 1) or ctmhd_step_batched (nbox > 1). */
 size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox);
 
 /* Advance one box by `nsteps` RK2 steps (Sec. 2.5).
@@ -123,15 +125,32 @@ int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
                double* const bface[3], int nsteps, const double* dt_fixed, double* dt_out,
                int64_t* diag, void* workspace, size_t ws_bytes, void* stream);
 
+/* Batched boxes (the AMR-like form): plan of the work queue.  The plan is
+ * built on the host into a caller buffer of ctmhd_batch_plan_bytes() bytes
+ * (boxes: HOST array) and must be copied by the caller into device memory
+ * before ctmhd_step_batched; it depends on params (scheme, tile knob, fofc)
+ * and on the boxes only, so one upload serves every later call. */
+size_t ctmhd_batch_plan_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox);
+int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* host_plan,
+                     size_t bytes);
+
 /* Advance `nbox` independent periodic boxes of different sizes by `nsteps`
- * steps in one persistent launch per step.  Box b's 8 fields start at element
- * boxes[b].offset of the packed arrays cons[m] / bface[a] (each box is laid
- * out as in ctmhd_step).  `boxes` is a HOST array.  dt_mode CTMHD_DT_GLOBAL:
- * one dt = min over boxes (every box must share dx); CTMHD_DT_PER_BOX: each
- * box its own CFL dt.  dt_fixed / dt_out hold nsteps values (global) or
- * nsteps*nbox values (per box, step-major).  diag as in ctmhd_step, summed
- * over boxes. */
-int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes,
+ * steps, one persistent launch per step: workgroups drain a device work
+ * queue of (phase, box, tile) items in phase-major order; an item waits only
+ * for the previous phase of its own box.  Box b's 8 fields start at element
+ * boxes[b].offset of the packed arrays cons[m] / bface[a] and are laid out as
+ * in ctmhd_step (its own ghost layers; each box is periodic on itself);
+ * boxes must not overlap.  `boxes` is the HOST array the plan was made from,
+ * `plan` its DEVICE copy.  dt_mode CTMHD_DT_GLOBAL: one dt = CFL / (maximum
+ * signal speed over all boxes); CTMHD_DT_PER_BOX: each box its own CFL dt.
+ * dt_fixed / dt_out hold nsteps values (global) or nsteps*nbox (per box,
+ * step-major).  diag as in ctmhd_step, summed over boxes; diag[3] |= 2
+ * reports an internal dependency-wait timeout, diag[3] |= 4 a plan that was
+ * not built for these params and boxes (the plan carries a hash of them; the
+ * kernels then leave the state untouched).  The call enqueues kernels
+ * only (no host-device copies), so multi-step sequences can be captured in a
+ * hipGraph.  force_flags must be NULL here. */
+int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
                        double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
                        const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
                        size_t ws_bytes, void* stream);

@@ -114,9 +114,7 @@ __device__ __forceinline__ int pwrap(int s, int g, int n) {
 // Periodic ghost fill of all 8 fields (faces follow the same rule: the face at
 // storage index s is the lower face of cell s).  Used on the caller's state at
 // the start of a call; later states get their ghost images from k_update.
-__global__ void k_wrap(State S, Geom G, const int* stop) {
-  if (*stop) return;
-  int t = gidx();
+__device__ __forceinline__ void wrap_at(const State& S, const Geom& G, int t) {
   if (t >= G.elems) return;
   int i = t % G.N[0];
   int q = t / G.N[0];
@@ -130,6 +128,11 @@ __global__ void k_wrap(State S, Geom G, const int* stop) {
   for (int m = 0; m < 5; ++m) S.c[m][t] = S.c[m][src];
 #pragma unroll
   for (int a = 0; a < 3; ++a) S.b[a][t] = S.b[a][src];
+}
+
+__global__ void k_wrap(State S, Geom G, const int* stop) {
+  if (*stop) return;
+  wrap_at(S, G, gidx());
 }
 
 __global__ void k_copy(State dst, State src, int elems, const int* only_if_stop) {
@@ -177,7 +180,7 @@ __device__ __forceinline__ double cfl_signal(double rho, const double u[3], doub
 // Block maximum of a non-negative (or NaN) double, folded into one of
 // kMaxSlots device slots by an atomic max on its bit pattern (a NaN has
 // larger bits than +inf as an unsigned integer).  All threads must call.
-__device__ __forceinline__ void block_max_to_slots(double s, unsigned long long* slots) {
+__device__ __forceinline__ void block_max_to_slots(double s, unsigned long long* slots, int slot) {
   __shared__ unsigned long long red[kBlock / 64];
   unsigned long long bits = (unsigned long long)__double_as_longlong(s);
 #pragma unroll
@@ -191,8 +194,23 @@ __device__ __forceinline__ void block_max_to_slots(double s, unsigned long long*
   if (threadIdx.x == 0) {
     unsigned long long m = 0;
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = red[q] > m ? red[q] : m;
-    atomicMax(&slots[blockIdx.x % kMaxSlots], m);
+    atomicMax(&slots[slot], m);
   }
+}
+
+// CFL signal of interior cell t (0 for t outside the box).
+__device__ __forceinline__ double dt_sig_at(const State& S, const Geom& G, double gamma,
+                                            double sres, int t) {
+  int ninter = G.n[0] * G.n[1] * G.n[2];
+  if (t >= ninter) return 0.0;
+  int i = t % G.n[0] + G.g;
+  int q = t / G.n[0];
+  int j = q % G.n[1] + G.g;
+  int k = q / G.n[1] + G.g;
+  int c = i + G.st[1] * j + G.st[2] * k;
+  double rho, u[3], p, bc[3];
+  cell_prim(S, G, c, gamma, rho, u, p, bc);
+  return cfl_signal(rho, u, p, bc, G, gamma, sres);
 }
 
 // CFL maximum of a whole state (start of a call).
@@ -202,17 +220,10 @@ __global__ void __launch_bounds__(kBlock) k_dt(State S, Geom G, double gamma, do
   int ninter = G.n[0] * G.n[1] * G.n[2];
   double s = 0.0;
   for (int t = gidx(); t < ninter; t += gridDim.x * blockDim.x) {
-    int i = t % G.n[0] + G.g;
-    int q = t / G.n[0];
-    int j = q % G.n[1] + G.g;
-    int k = q / G.n[1] + G.g;
-    int c = i + G.st[1] * j + G.st[2] * k;
-    double rho, u[3], p, bc[3];
-    cell_prim(S, G, c, gamma, rho, u, p, bc);
-    double v = cfl_signal(rho, u, p, bc, G, gamma, sres);
+    double v = dt_sig_at(S, G, gamma, sres, t);
     s = (v > s || v != v) ? v : s;
   }
-  block_max_to_slots(s, slots);
+  block_max_to_slots(s, slots, blockIdx.x % kMaxSlots);
 }
 
 // dt of a step.  smax[0..kMaxSlots) holds the CFL maximum of the step's
@@ -257,10 +268,8 @@ __global__ void k_dt_final(unsigned long long* smax, int* nflag, double cfl,
 // velocity), over cells whose upper faces are stored.
 // ---------------------------------------------------------------------------
 template <typename T, int EMF>
-__global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, double gamma,
-                                                 const int* stop) {
-  if (*stop) return;
-  int t = gidx();
+__device__ __forceinline__ void prim_at(const State& S, const Geom& G, const Work<T>& W,
+                                        double gamma, int t) {
   if (t >= G.elems) return;
   int i = t % G.N[0];
   int q = t / G.N[0];
@@ -281,6 +290,13 @@ __global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, dou
     W.prim[2][t] = (T)u[1];
     W.prim[3][t] = (T)u[2];
   }
+}
+
+template <typename T, int EMF>
+__global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, double gamma,
+                                                 const int* stop) {
+  if (*stop) return;
+  prim_at<T, EMF>(S, G, W, gamma, gidx());
 }
 
 // eta j_c at the edge stored at s (lower corner in a and b), eq.
@@ -482,13 +498,11 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
   }
 }
 
+// One virtual block (256 threads) of the face pass.
 template <typename T, int RECON, int RIEMANN>
-__global__ void __launch_bounds__(kBlock)
-    k_faces(State S, Geom G, Work<T> W, FacePlan FP, int stage, double gamma, double eta,
-            long long* diag, const int* stop) {
-  if (*stop) return;
-  int nfb = 0;
-  int b = blockIdx.x;
+__device__ __forceinline__ void faces_block(const State& S, const Geom& G, const Work<T>& W,
+                                            const FacePlan& FP, int b, int stage, double gamma,
+                                            double eta, int& nfb) {
   // long-running marching blocks first, the short x-face wavefronts fill in
   if (b < FP.blocks[2]) {
     faces_march<T, RECON, RIEMANN, 2>(S, G, W, FP, b / FP.nchunk[2], b % FP.nchunk[2], stage,
@@ -501,6 +515,15 @@ __global__ void __launch_bounds__(kBlock)
     const int wave = b * (kBlock / 64) + (threadIdx.x >> 6);
     if (wave < FP.xwaves) faces_x<T, RECON, RIEMANN>(S, G, W, FP, wave, stage, gamma, eta, nfb);
   }
+}
+
+template <typename T, int RECON, int RIEMANN>
+__global__ void __launch_bounds__(kBlock)
+    k_faces(State S, Geom G, Work<T> W, FacePlan FP, int stage, double gamma, double eta,
+            long long* diag, const int* stop) {
+  if (*stop) return;
+  int nfb = 0;
+  faces_block<T, RECON, RIEMANN>(S, G, W, FP, blockIdx.x, stage, gamma, eta, nfb);
   if (diag && nfb) atomicAdd((unsigned long long*)&diag[2], (unsigned long long)nfb);
 }
 
@@ -601,17 +624,22 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
 // All three edge directions at the edge positions [g, g+n] on every axis
 // (an edge of direction c exists for s_c < g + n_c).
 template <typename T, int RECON, int EMF>
-__global__ void __launch_bounds__(kBlock)
-    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
-  if (*stop) return;
+__device__ __forceinline__ void emf_at(const State& S, const Geom& G, const Work<T>& W, int stage,
+                                       double eta_d, int t) {
   const int L0 = G.n[0] + 1, L1 = G.n[1] + 1, L2 = G.n[2] + 1;
-  int t = gidx();
   if (t >= L0 * L1 * L2) return;
   int s3[3] = {G.g + t % L0, G.g + (t / L0) % L1, G.g + t / (L0 * L1)};
   int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     if (s3[c] < G.g + G.n[c]) W.E[stage][c][s] = edge_emf<T, RECON, EMF>(S, G, W, s, c, eta_d);
+}
+
+template <typename T, int RECON, int EMF>
+__global__ void __launch_bounds__(kBlock)
+    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
+  if (*stop) return;
+  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, gidx());
 }
 
 // ---------------------------------------------------------------------------
@@ -671,15 +699,16 @@ struct UpdateCfg {
 // fixup = 1: after first-order replacement; runs only if this stage flagged
 //            cells; stage 1 recomputes the CFL maximum into slot 1.
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_update(State base, State half, State out, Geom G, Work<T> W, int stage, int fixup,
-             UpdateCfg U, long long* diag, const int* stop) {
-  if (*stop) return;
-  if (fixup && W.nflag[stage] == 0) return;
-  const int t = gidx();
+__device__ __forceinline__ void update_item(const State& base, const State& half, const State& out,
+                                            const Geom& G, const Work<T>& W, int stage, int fixup,
+                                            const UpdateCfg& U, long long* diag, int vb, int strips,
+                                            unsigned long long* slots, int slot) {
   const int ninter = G.n[0] * G.n[1] * G.n[2];
-  const bool live = t < ninter;
   const double dt = *W.dt;
+  double sigmax = 0.0;
+  for (int strip = 0; strip < strips; ++strip) {
+  const int t = (vb * strips + strip) * kBlock + (int)threadIdx.x;
+  const bool live = t < ninter;
   int bad = 0;
   double sig = 0.0;
   if (live) {
@@ -756,10 +785,22 @@ __global__ void __launch_bounds__(kBlock)
       if (diag) atomicAdd((unsigned long long*)&diag[stage], (unsigned long long)cnt);
     }
   }
-  if (stage == 1) {
-    if (fixup && threadIdx.x == 0 && blockIdx.x == 0) W.nflag[2] = 1;
-    block_max_to_slots(sig, W.smax + (fixup ? kMaxSlots : 0));
+  sigmax = (sig > sigmax || sig != sig) ? sig : sigmax;
   }
+  if (stage == 1) {
+    if (fixup && threadIdx.x == 0) W.nflag[2] = 1;
+    block_max_to_slots(sigmax, slots, slot);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_update(State base, State half, State out, Geom G, Work<T> W, int stage, int fixup,
+             UpdateCfg U, long long* diag, const int* stop) {
+  if (*stop) return;
+  if (fixup && W.nflag[stage] == 0) return;
+  update_item<T>(base, half, out, G, W, stage, fixup, U, diag, blockIdx.x, 1,
+                 W.smax + (fixup ? kMaxSlots : 0), blockIdx.x % kMaxSlots);
 }
 
 // ---------------------------------------------------------------------------
@@ -812,11 +853,8 @@ __device__ __forceinline__ T fo_corner_cell(const State& Sn, const Geom& G, int 
 // that their RK average is the first-order value.  Periodic images of the
 // upper boundary faces / edges are written as well (the update reads them).
 template <typename T, int EMF>
-__global__ void __launch_bounds__(kBlock)
-    k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
-  if (*stop) return;
-  if (W.nflag[stage] == 0) return;
-  int t = gidx();
+__device__ __forceinline__ void fo_at(const State& Sn, const Geom& G, const Work<T>& W, int stage,
+                                      double gamma, double eta_d, int t) {
   int nf = G.n[0] * G.n[1] * G.n[2];
   if (t >= nf) return;
   const int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
@@ -883,6 +921,302 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+template <typename T, int EMF>
+__global__ void __launch_bounds__(kBlock)
+    k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
+  if (*stop) return;
+  if (W.nflag[stage] == 0) return;
+  fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, gidx());
+}
+
+// ---------------------------------------------------------------------------
+// Batched boxes: one persistent launch per step drains a work queue of
+// (phase, box, tile) items.  Items are ordered phase-major (largest boxes
+// first inside a phase), so an item only ever waits for items that precede
+// it in the queue (the previous phase of its own box): with workgroups that
+// claim an item only after finishing the last one, the queue always drains.
+// Each box is a periodic box of its own (ghosts wrapped per box); no data
+// crosses boxes.
+// ---------------------------------------------------------------------------
+enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P };
+constexpr int kMaxPhases = 16;
+
+struct BoxDesc {
+  Geom G;
+  FacePlan FP;
+  long long off;       // element offset of the box in the packed field arrays
+  long long flag_off;  // offset of the box in the packed flag array
+  double sres;         // resistive term of the CFL maximum (depends on dx)
+};
+
+struct PlanHeader {
+  int nbox, nphase, strips, magic;
+  unsigned long long key;    // hash of the parameters and boxes the plan was built for
+  int kind[kMaxPhases];      // PH_*
+  int stage[kMaxPhases];     // RK stage of F/E/U/O/X phases
+  int item_off[kMaxPhases];  // first queue index of each phase inside its launch
+  int range[3][2];           // phase ranges [lo, hi) of the start, step and copy launches
+  int range_items[3];        // items of each launch
+  long long order_off, prefix_off, desc_off;  // byte offsets of the arrays below
+  // int order[nbox]; int prefix[nphase][nbox + 1]; BoxDesc desc[nbox]
+};
+constexpr int kPlanMagic = 0x43544d48;
+
+template <typename T>
+struct BatchArgs {
+  State user, B, H;   // packed states (box offsets from the plan)
+  Work<T> W;          // packed stencil arrays; per-box scalars below
+  const char* plan;
+  int* cursor;        // queue cursor of this launch
+  int* done;          // [nphase][nbox] finished items
+  int* nflag;         // [nbox][4]: flagged cells stage 0 / 1, stage-1 fix-up ran
+  unsigned long long* slots;  // [nbox][2]: CFL maximum (main pass, fix-up)
+  double* dt;         // [nbox] (per-box dt) or [1]
+  int* stop;
+  int* err;           // set when a dependency wait times out
+  long long* diag;    // this step's counters or null
+  int dt_per_box;
+  const int* loc;     // where the current state lives: 0 `user`, 1 B (flipped by each step that ran)
+  int launch;         // 0 start (wrap + CFL), 1 step, 2 copy-back
+  unsigned long long key;  // must equal the plan's key
+  double gamma, eta;
+  int fofc, crit;
+};
+
+__device__ __forceinline__ State shift_state(const State& S, long long off) {
+  State R;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) R.c[m] = S.c[m] + off;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) R.b[a] = S.b[a] + off;
+  return R;
+}
+
+template <typename T>
+__device__ __forceinline__ Work<T> shift_work(const Work<T>& W0, long long off) {
+  Work<T> W = W0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) W.prim[v] = W0.prim[v] ? W0.prim[v] + off : nullptr;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) W.ecell[c] = W0.ecell[c] ? W0.ecell[c] + off : nullptr;
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) W.F[st][a][m] = W0.F[st][a][m] + off;
+      W.E[st][a] = W0.E[st][a] + off;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    W.ap[a] = W0.ap[a] + off;
+    W.am[a] = W0.am[a] + off;
+    W.us[a] = W0.us[a] + off;
+  }
+  return W;
+}
+
+// Wait (thread 0, acquire) until *cnt >= need; bounded: on a timeout the
+// error flag is raised and every later wait returns at once.
+__device__ __forceinline__ void wait_count(const int* cnt, int need, int* err) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins > (1 << 20)) {
+        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  // every wave acquires: the producer may sit on another XCD (another L2)
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Every wave releases its own stores at agent scope before thread 0 counts
+// the item as done.
+__device__ __forceinline__ void signal_count(int* cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, int RECON, int RIEMANN, int EMF>
+__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
+  if (*A.stop && A.launch != 2) return;  // the copy-back runs even after a stop
+  const PlanHeader* P = (const PlanHeader*)A.plan;
+  if (P->magic != kPlanMagic || P->key != A.key) {  // plan built for other boxes: no work
+    if (threadIdx.x == 0) atomicOr(A.err, 2);
+    return;
+  }
+  const int* order = (const int*)(A.plan + P->order_off);
+  const int* prefix = (const int*)(A.plan + P->prefix_off);
+  const BoxDesc* desc = (const BoxDesc*)(A.plan + P->desc_off);
+  const int nbox = P->nbox;
+  const int lo = P->range[A.launch][0], hi = P->range[A.launch][1];
+  const int total = P->range_items[A.launch];
+  const int strips = P->strips;
+  const int cl = *A.loc;  // fixed for the whole launch
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(A.cursor, 1);
+    __syncthreads();
+    const int q = item_s;
+    __syncthreads();
+    if (q >= total) break;
+    int p = lo;
+    while (p + 1 < hi && P->item_off[p + 1] <= q) ++p;
+    const int* pre = prefix + (long long)p * (nbox + 1);
+    const int r = q - P->item_off[p];
+    int k0 = 0, k1 = nbox;  // largest k with pre[k] <= r
+    while (k1 - k0 > 1) {
+      int mid = (k0 + k1) >> 1;
+      if (pre[mid] <= r) k0 = mid; else k1 = mid;
+    }
+    const int b = order[k0];
+    const int tile = r - pre[k0];
+    if (p > lo) {
+      const int* ppre = prefix + (long long)(p - 1) * (nbox + 1);
+      wait_count(A.done + (long long)(p - 1) * nbox + b, ppre[k0 + 1] - ppre[k0], A.err);
+    }
+    const BoxDesc& d = desc[b];
+    const Geom G = d.G;
+    const State cur = shift_state(cl == 0 ? A.user : A.B, d.off);
+    const State oth = shift_state(cl == 0 ? A.B : A.user, d.off);
+    const State Hs = shift_state(A.H, d.off);
+    Work<T> W = shift_work(A.W, d.off);
+    W.flag = A.W.flag + d.flag_off;
+    W.dt = A.dt + (A.dt_per_box ? b : 0);
+    W.nflag = A.nflag + 4 * b;
+    W.smax = A.slots + 2 * b;
+    W.stop = A.stop;
+    const int kind = P->kind[p], stage = P->stage[p];
+    const State in = stage == 0 ? cur : Hs;
+    UpdateCfg U;
+    U.fofc = A.fofc;
+    U.crit = A.crit;
+    U.gamma = A.gamma;
+    U.sres = d.sres;
+    U.force = nullptr;
+    if (kind == PH_P) {
+      for (int s = 0; s < strips; ++s)
+        prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if (kind == PH_F) {
+      int nfb = 0;
+      faces_block<T, RECON, RIEMANN>(in, G, W, d.FP, tile, stage, A.gamma, A.eta, nfb);
+      if (A.diag && nfb) atomicAdd((unsigned long long*)&A.diag[2], (unsigned long long)nfb);
+    } else if (kind == PH_E) {
+      for (int s = 0; s < strips; ++s)
+        emf_at<T, RECON, EMF>(in, G, W, stage, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if (kind == PH_U) {
+      update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, 0, U, A.diag, tile, strips,
+                     W.smax, 0);
+    } else if (kind == PH_O) {
+      if (W.nflag[stage])
+        for (int s = 0; s < strips; ++s)
+          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if (kind == PH_X) {
+      if (W.nflag[stage])
+        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, 1, U, A.diag, tile, strips,
+                       W.smax, 1);
+    } else if (kind == PH_WRAP) {
+      for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if (kind == PH_DT) {
+      double sig = 0.0;
+      for (int s = 0; s < strips; ++s) {
+        double v = dt_sig_at(cur, G, A.gamma, d.sres, (tile * strips + s) * kBlock + threadIdx.x);
+        sig = (v > sig || v != v) ? v : sig;
+      }
+      block_max_to_slots(sig, W.smax, 0);
+    } else if (cl == 1) {  // PH_COPY: the state of this box back into the caller's arrays
+      for (int s = 0; s < strips; ++s) {
+        const int t = (tile * strips + s) * kBlock + threadIdx.x;
+        if (t < G.elems) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) A.user.c[m][d.off + t] = A.B.c[m][d.off + t];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) A.user.b[a][d.off + t] = A.B.b[a][d.off + t];
+        }
+      }
+    }
+    signal_count(A.done + (long long)p * nbox + b);
+  }
+}
+
+// dt of a batched step from the per-box CFL maxima (the fix-up maximum where
+// a box's second stage was fixed up); resets the per-step counters.
+__global__ void __launch_bounds__(kBlock)
+    k_bdt_final(int nbox, int nphase, int dt_per_box, unsigned long long* slots, int* nflag,
+                int* done, int* cursor, double cfl, const double* dt_fixed, double* dt,
+                double* dt_out, int* stop, const int* err, long long* diag) {
+  __shared__ unsigned long long red[kBlock];
+  const int t = threadIdx.x;
+  unsigned long long mx = 0;
+  const bool stopped = *stop != 0;
+  for (int b = t; b < nbox; b += kBlock) {
+    unsigned long long v = nflag[4 * b + 2] ? slots[2 * b + 1] : slots[2 * b];
+    mx = v > mx ? v : mx;
+    if (dt_per_box) {
+      double x = stopped ? 0.0 : (dt_fixed ? dt_fixed[b] : cfl / __longlong_as_double((long long)v));
+      if (!stopped && (!(x > 0.0) || !__builtin_isfinite(x))) atomicExch(stop, 1);
+      dt[b] = x;
+      if (dt_out) dt_out[b] = x;
+    }
+  }
+  red[t] = mx;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] = red[t + o] > red[t] ? red[t + o] : red[t];
+    __syncthreads();
+  }
+  if (t == 0 && !dt_per_box) {
+    double x = stopped ? 0.0 : (dt_fixed ? dt_fixed[0] : cfl / __longlong_as_double((long long)red[0]));
+    if (!stopped && (!(x > 0.0) || !__builtin_isfinite(x))) *stop = 1;
+    dt[0] = x;
+    if (dt_out) dt_out[0] = x;
+  }
+  for (int b = t; b < nbox; b += kBlock) {
+    slots[2 * b] = slots[2 * b + 1] = 0ull;
+    nflag[4 * b] = nflag[4 * b + 1] = nflag[4 * b + 2] = nflag[4 * b + 3] = 0;
+  }
+  for (int i = t; i < nphase * nbox; i += kBlock) done[i] = 0;
+  if (t < 4) cursor[t] = 0;
+  __syncthreads();
+  if (t == 0 && diag) {
+    diag[0] = diag[1] = diag[2] = 0;
+    diag[3] = (*stop ? 1 : 0) | (*err << 1);
+  }
+}
+
+// Reset before a launch of the queue (start / copy launches); init = 1 at the
+// start of a call also clears the stop / error flags, the state location and
+// the per-box CFL slots.
+__global__ void k_breset(int nbox, int nphase, int* done, int* cursor, int init, int* stop,
+                         int* err, int* loc, unsigned long long* slots, int* nflag) {
+  for (int i = threadIdx.x; i < nphase * nbox; i += kBlock) done[i] = 0;
+  if (threadIdx.x < 4) cursor[threadIdx.x] = 0;
+  if (!init) return;
+  for (int b = threadIdx.x; b < nbox; b += kBlock) {
+    slots[2 * b] = slots[2 * b + 1] = 0ull;
+    nflag[4 * b] = nflag[4 * b + 1] = nflag[4 * b + 2] = nflag[4 * b + 3] = 0;
+  }
+  if (threadIdx.x == 0) {
+    *stop = 0;
+    *err = 0;
+    *loc = 0;
+  }
+}
+
+// After a batched step: the new state is in the other buffer unless the step
+// was stopped (non-finite dt), which leaves it where it was.
+__global__ void k_bstep_end(int* loc, const int* stop, const int* err, long long* diag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (diag) diag[3] |= *err << 1;
+  if (!*stop) *loc ^= 1;
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -894,6 +1228,18 @@ int fail(int code, const char* msg) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Tuning knobs in ctmhd_params.tile: bits 0-7 minimum faces per marching
+// chunk (default 32), bits 8-15 256-element strips per batched work item
+// (default 1).
+int tile_chunk(const ctmhd_params* p) {
+  int c = p->tile & 0xff;
+  return c > 0 ? c : 32;
+}
+int tile_strips(const ctmhd_params* p) {
+  int s = (p->tile >> 8) & 0xff;
+  return s > 0 ? s : 1;
+}
 
 int check_params(const ctmhd_params* p) {
   if (!p) return fail(CTMHD_EARG, "params is NULL");
@@ -907,6 +1253,7 @@ int check_params(const ctmhd_params* p) {
   if (p->emf_compute < 0 || p->emf_compute > 2) return fail(CTMHD_EARG, "unknown EMF scheme");
   if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
   if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32) return fail(CTMHD_EARG, "unknown precision");
+  if (p->tile < 0 || p->tile > 0xffff) return fail(CTMHD_EARG, "tile knob out of range");
   return CTMHD_OK;
 }
 
@@ -994,11 +1341,11 @@ int g_prof_used = 0;
 
 inline void prof_begin(hipStream_t st) {
   if (g_prof_events && g_prof_used < g_prof_pairs)
-    hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used], st);
+    (void)hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used], st);
 }
 inline void prof_end(hipStream_t st) {
   if (g_prof_events && g_prof_used < g_prof_pairs) {
-    hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used + 1], st);
+    (void)hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used + 1], st);
     ++g_prof_used;
   }
 }
@@ -1010,7 +1357,7 @@ inline void prof_end(hipStream_t st) {
   } while (0)
 
 // Face plan: ranges and launch shape of the fused face kernel.
-FacePlan make_face_plan(const Geom& G, int recon, int emf) {
+FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min) {
   FacePlan P;
   const int r = recon_halfwidth(recon);
   const int g = G.g;
@@ -1038,7 +1385,7 @@ FacePlan make_face_plan(const Geom& G, int recon, int emf) {
     P.lanes[A] = P.tlen[0] * P.tlen[C];
     P.lblocks[A] = (P.lanes[A] + kBlock - 1) / kBlock;
     int want = (8192 * 64 / kBlock) / (P.lblocks[A] > 0 ? P.lblocks[A] : 1);
-    int maxch = (P.nf[A] + 31) / 32;  // chunks of at least ~32 faces (window warm-up 2r+1)
+    int maxch = (P.nf[A] + chunk_min - 1) / chunk_min;  // chunk >= chunk_min faces (warm-up 2r+1)
     if (want > maxch) want = maxch;
     if (want < 1) want = 1;
     P.chunk[A] = (P.nf[A] + want - 1) / want;
@@ -1129,7 +1476,7 @@ int step_box(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
   for (int m = 0; m < 5; ++m) A.c[m] = cons[m];
   for (int a = 0; a < 3; ++a) A.b[a] = bface[a];
   const State user = A;
-  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute);
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
   double dxmin = fmin(G.dx[0], fmin(G.dx[1], G.dx[2]));
   double sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
   const int ninter = G.n[0] * G.n[1] * G.n[2];
@@ -1170,6 +1517,263 @@ int step_box_t(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched boxes (host): plan, workspace and launch sequence.
+// ---------------------------------------------------------------------------
+long long box_elems_ll(const ctmhd_box& b) {
+  long long e = 1;
+  for (int d = 0; d < 3; ++d) e *= (long long)(b.n[d] + 2 * b.ng);
+  return e;
+}
+long long box_inter_ll(const ctmhd_box& b) { return (long long)b.n[0] * b.n[1] * b.n[2]; }
+
+// Phase lists: start launch (wrap, CFL), step launch, copy-back launch.
+int plan_phases(const ctmhd_params* p, int kind[kMaxPhases], int stage[kMaxPhases], int range[3][2]) {
+  int n = 0;
+  range[0][0] = n;
+  kind[n] = PH_WRAP; stage[n++] = 0;
+  kind[n] = PH_DT; stage[n++] = 0;
+  range[0][1] = n;
+  range[1][0] = n;
+  for (int st = 0; st < 2; ++st) {
+    if (p->emf_compute != CTMHD_EMF_Q26) {
+      kind[n] = PH_P; stage[n++] = st;
+    }
+    kind[n] = PH_F; stage[n++] = st;
+    kind[n] = PH_E; stage[n++] = st;
+    kind[n] = PH_U; stage[n++] = st;
+    if (p->fofc) {
+      kind[n] = PH_O; stage[n++] = st;
+      kind[n] = PH_X; stage[n++] = st;
+    }
+  }
+  range[1][1] = n;
+  range[2][0] = n;
+  kind[n] = PH_COPY; stage[n++] = 0;
+  range[2][1] = n;
+  return n;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// FNV-1a over everything a plan depends on: the kernel refuses a plan whose
+// key differs from the one computed for the call's own parameters and boxes.
+unsigned long long plan_key(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
+  unsigned long long h = 0xcbf29ce484222325ull;
+  auto mix = [&h](const void* v, size_t n) {
+    const unsigned char* c = (const unsigned char*)v;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+  };
+  const int f[6] = {p->recon, p->emf_compute, p->fofc, tile_strips(p), tile_chunk(p), nbox};
+  mix(f, sizeof(f));
+  for (int b = 0; b < nbox; ++b) {
+    mix(boxes[b].n, sizeof(boxes[b].n));
+    mix(&boxes[b].ng, sizeof(boxes[b].ng));
+    mix(boxes[b].dx, sizeof(boxes[b].dx));
+    mix(&boxes[b].offset, sizeof(boxes[b].offset));
+  }
+  return h;
+}
+
+size_t plan_layout(int nbox, int nphase, long long* order_off, long long* prefix_off,
+                   long long* desc_off) {
+  size_t o = align16(sizeof(PlanHeader));
+  *order_off = (long long)o;
+  o = align16(o + sizeof(int) * (size_t)nbox);
+  *prefix_off = (long long)o;
+  o = align16(o + sizeof(int) * (size_t)nphase * (nbox + 1));
+  *desc_off = (long long)o;
+  o += sizeof(BoxDesc) * (size_t)nbox;
+  return o;
+}
+
+int check_boxes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
+  if (!boxes || nbox < 1) return fail(CTMHD_EARG, "no boxes");
+  for (int b = 0; b < nbox; ++b) {
+    int rc = check_box(p, &boxes[b]);
+    if (rc) return rc;
+    if (boxes[b].offset < 0) return fail(CTMHD_EARG, "negative box offset");
+  }
+  // boxes must not overlap in the packed arrays
+  for (int b = 0; b < nbox; ++b) {
+    const long long b0 = boxes[b].offset, b1 = b0 + box_elems_ll(boxes[b]);
+    for (int c = b + 1; c < nbox; ++c) {
+      const long long c0 = boxes[c].offset, c1 = c0 + box_elems_ll(boxes[c]);
+      if (b0 < c1 && c0 < b1) return fail(CTMHD_EARG, "boxes overlap in the packed arrays");
+    }
+  }
+  return CTMHD_OK;
+}
+
+long long packed_elems(const ctmhd_box* boxes, int nbox) {
+  long long m = 0;
+  for (int b = 0; b < nbox; ++b) {
+    long long e = boxes[b].offset + box_elems_ll(boxes[b]);
+    m = e > m ? e : m;
+  }
+  return m;
+}
+
+size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
+  const size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
+  const size_t e = (size_t)packed_elems(boxes, nbox);
+  long long ninter = 0;
+  for (int b = 0; b < nbox; ++b) ninter += box_inter_ll(boxes[b]);
+  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
+  const int nphase = plan_phases(p, kind, stage, range);
+  size_t bytes = 0;
+  bytes += 2 * 8 * align256(e * 8);  // B and H states
+  if (p->emf_compute != CTMHD_EMF_Q26) bytes += 3 * align256(e * tb);
+  bytes += (2 * 15 + 9 + 6) * align256(e * tb);
+  bytes += align256((size_t)ninter);                         // flags
+  bytes += align256(sizeof(int) * (size_t)nphase * nbox);    // done
+  bytes += align256(sizeof(int) * 4 * (size_t)nbox);         // nflag
+  bytes += align256(sizeof(unsigned long long) * 2 * (size_t)nbox);  // CFL slots
+  bytes += align256(sizeof(double) * (size_t)nbox);          // dt
+  bytes += 256;                                              // cursor, stop, err, loc
+  return bytes;
+}
+
+template <typename T>
+int batch_args(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* ws, size_t ws_bytes,
+               BatchArgs<T>& A, int& nphase) {
+  if (!ws || ws_bytes < batch_ws_bytes(p, boxes, nbox)) return fail(CTMHD_EARG, "workspace too small");
+  if (((uintptr_t)ws & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
+  const size_t e = (size_t)packed_elems(boxes, nbox);
+  long long ninter = 0;
+  for (int b = 0; b < nbox; ++b) ninter += box_inter_ll(boxes[b]);
+  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
+  nphase = plan_phases(p, kind, stage, range);
+  Carve cv{(char*)ws};
+  for (int m = 0; m < 5; ++m) A.B.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) A.B.b[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) A.H.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) A.H.b[a] = cv.take<double>(e);
+  Work<T>& W = A.W;
+  for (int v = 0; v < 8; ++v) W.prim[v] = nullptr;
+  for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
+  if (p->emf_compute == CTMHD_EMF_B25A)
+    for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
+  if (p->emf_compute == CTMHD_EMF_FS18)
+    for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
+  for (int st = 0; st < 2; ++st)
+    for (int a = 0; a < 3; ++a)
+      for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.ap[a] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.am[a] = cv.take<T>(e);
+  for (int a = 0; a < 3; ++a) W.us[a] = cv.take<T>(e);
+  for (int st = 0; st < 2; ++st)
+    for (int c = 0; c < 3; ++c) W.E[st][c] = cv.take<T>(e);
+  W.flag = cv.take<uint8_t>((size_t)ninter);
+  A.done = cv.take<int>((size_t)nphase * nbox);
+  A.nflag = cv.take<int>(4 * (size_t)nbox);
+  A.slots = cv.take<unsigned long long>(2 * (size_t)nbox);
+  A.dt = cv.take<double>((size_t)nbox);
+  char* sc = cv.p;
+  A.cursor = (int*)sc;          // 4 ints
+  A.stop = (int*)(sc + 16);
+  A.err = (int*)(sc + 20);
+  A.loc = (const int*)(sc + 24);
+  W.dt = A.dt;
+  W.nflag = A.nflag;
+  W.smax = A.slots;
+  W.stop = A.stop;
+  A.gamma = p->gamma;
+  A.eta = p->eta;
+  A.fofc = p->fofc;
+  A.crit = p->flag_criteria;
+  return CTMHD_OK;
+}
+
+// Persistent grid: every workgroup that can be resident at once.
+template <typename K>
+int persistent_blocks(K kernel) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) return 0;
+  if (per < 1) per = 1;
+  return ncu * per;
+}
+
+template <typename T, int RECON, int RIEMANN, int EMF>
+int batched_run(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
+                double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
+                const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+  BatchArgs<T> A;
+  int nphase = 0;
+  int rc = batch_args<T>(p, boxes, nbox, ws, ws_bytes, A, nphase);
+  if (rc) return rc;
+  for (int m = 0; m < 5; ++m) A.user.c[m] = cons[m];
+  for (int a = 0; a < 3; ++a) A.user.b[a] = bface[a];
+  A.plan = (const char*)plan;
+  A.key = plan_key(p, boxes, nbox);
+  A.diag = nullptr;
+  A.dt_per_box = dt_mode == CTMHD_DT_PER_BOX;
+  const int grid = persistent_blocks(k_batch<T, RECON, RIEMANN, EMF>);
+  if (grid < 1) return fail(CTMHD_EHIP, "occupancy query failed");
+  const int ndt = A.dt_per_box ? nbox : 1;
+  LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 1, A.stop, A.err, (int*)A.loc, A.slots,
+         A.nflag);
+  A.launch = 0;
+  LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
+  for (int n = 0; n < nsteps; ++n) {
+    long long* dg = diag ? (long long*)diag + 4 * n : nullptr;
+    LAUNCH(k_bdt_final, 1, nbox, nphase, A.dt_per_box, A.slots, A.nflag, A.done, A.cursor, p->cfl,
+           dt_fixed ? dt_fixed + (size_t)n * ndt : nullptr, A.dt,
+           dt_out ? dt_out + (size_t)n * ndt : nullptr, A.stop, A.err, dg);
+    A.launch = 1;
+    A.diag = dg;
+    prof_begin(st);
+    LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
+    prof_end(st);
+    LAUNCH(k_bstep_end, 1, (int*)A.loc, A.stop, A.err, dg);
+  }
+  LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 0, A.stop, A.err, (int*)A.loc, A.slots,
+         A.nflag);
+  A.launch = 2;
+  A.diag = nullptr;
+  LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
+  return CTMHD_OK;
+}
+
+template <typename T, int RECON>
+int batched_emf(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
+                double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
+                const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+#define CTMHD_BATCH(RI, EM) \
+  batched_run<T, RECON, RI, EM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st)
+  if (p->riemann == CTMHD_RIEMANN_HLLD) {
+    if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kHLLD, kQ26);
+    if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kHLLD, kB25A);
+    return CTMHD_BATCH(kHLLD, kFS18);
+  }
+  if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kLLF, kQ26);
+  if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kLLF, kB25A);
+  return CTMHD_BATCH(kLLF, kFS18);
+#undef CTMHD_BATCH
+}
+
+template <typename T>
+int batched_t(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
+              double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
+              const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
+              hipStream_t st) {
+  switch (p->recon) {
+    case CTMHD_RECON_PC:
+      return batched_emf<T, kPC>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
+    case CTMHD_RECON_PLM_MC:
+      return batched_emf<T, kPLM_MC>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
+    case CTMHD_RECON_PLM_MINMOD:
+      return batched_emf<T, kPLM_MM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
+    default:
+      return batched_emf<T, kPPM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1191,7 +1795,108 @@ size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int 
   if (check_params(p) || !boxes || nbox < 1) return 0;
   size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
   if (nbox == 1) return box_ws_bytes(boxes[0], tb, p->emf_compute);
-  return 0;
+  return batch_ws_bytes(p, boxes, nbox);
+}
+
+size_t ctmhd_batch_plan_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
+  if (check_params(p) || check_boxes(p, boxes, nbox)) return 0;
+  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
+  const int nphase = plan_phases(p, kind, stage, range);
+  long long a, b, c;
+  return plan_layout(nbox, nphase, &a, &b, &c);
+}
+
+int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* host_plan,
+                     size_t bytes) {
+  g_err[0] = 0;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_boxes(p, boxes, nbox))) return rc;
+  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
+  const int nphase = plan_phases(p, kind, stage, range);
+  long long order_off, prefix_off, desc_off;
+  const size_t need = plan_layout(nbox, nphase, &order_off, &prefix_off, &desc_off);
+  if (!host_plan || bytes < need) return fail(CTMHD_EARG, "plan buffer too small");
+  char* base = (char*)host_plan;
+  memset(base, 0, need);
+  PlanHeader* P = (PlanHeader*)base;
+  int* order = (int*)(base + order_off);
+  int* prefix = (int*)(base + prefix_off);
+  BoxDesc* desc = (BoxDesc*)(base + desc_off);
+  P->nbox = nbox;
+  P->nphase = nphase;
+  P->strips = tile_strips(p);
+  P->magic = kPlanMagic;
+  P->key = plan_key(p, boxes, nbox);
+  for (int q = 0; q < nphase; ++q) {
+    P->kind[q] = kind[q];
+    P->stage[q] = stage[q];
+  }
+  for (int l = 0; l < 3; ++l) {
+    P->range[l][0] = range[l][0];
+    P->range[l][1] = range[l][1];
+  }
+  P->order_off = order_off;
+  P->prefix_off = prefix_off;
+  P->desc_off = desc_off;
+  // largest boxes first (stable), so that the longest items start early
+  for (int b = 0; b < nbox; ++b) order[b] = b;
+  for (int i = 1; i < nbox; ++i) {
+    int v = order[i], j = i;
+    long long ev = box_inter_ll(boxes[v]);
+    while (j > 0 && box_inter_ll(boxes[order[j - 1]]) < ev) {
+      order[j] = order[j - 1];
+      --j;
+    }
+    order[j] = v;
+  }
+  const int strips = P->strips;
+  const long long per = (long long)kBlock * strips;
+  long long flag_off = 0;
+  for (int b = 0; b < nbox; ++b) {
+    const ctmhd_box& bx = boxes[b];
+    BoxDesc& d = desc[b];
+    d.G = make_geom(bx);
+    d.FP = make_face_plan(d.G, p->recon, p->emf_compute, tile_chunk(p));
+    d.off = bx.offset;
+    d.flag_off = flag_off;
+    flag_off += box_inter_ll(bx);
+    double dxmin = fmin(bx.dx[0], fmin(bx.dx[1], bx.dx[2]));
+    d.sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
+  }
+  long long items_in_launch = 0;
+  int launch = 0;
+  for (int q = 0; q < nphase; ++q) {
+    while (launch < 2 && q >= range[launch][1]) {
+      P->range_items[launch] = (int)items_in_launch;
+      ++launch;
+      items_in_launch = 0;
+    }
+    P->item_off[q] = (int)items_in_launch;
+    int* pre = prefix + (long long)q * (nbox + 1);
+    pre[0] = 0;
+    for (int k = 0; k < nbox; ++k) {
+      const BoxDesc& d = desc[order[k]];
+      const long long ninter = (long long)d.G.n[0] * d.G.n[1] * d.G.n[2];
+      long long cnt;
+      switch (kind[q]) {
+        case PH_F: cnt = d.FP.total_blocks; break;
+        case PH_E:
+          cnt = ((long long)(d.G.n[0] + 1) * (d.G.n[1] + 1) * (d.G.n[2] + 1) + per - 1) / per;
+          break;
+        case PH_P:
+        case PH_WRAP:
+        case PH_COPY: cnt = ((long long)d.G.elems + per - 1) / per; break;
+        default: cnt = (ninter + per - 1) / per; break;
+      }
+      if ((long long)pre[k] + cnt >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
+      pre[k + 1] = pre[k] + (int)cnt;
+    }
+    items_in_launch += pre[nbox];
+    if (items_in_launch >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
+  }
+  P->range_items[launch] = (int)items_in_launch;
+  return CTMHD_OK;
 }
 
 int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
@@ -1216,13 +1921,31 @@ int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
                             ws_bytes, st);
 }
 
-int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes,
+int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
                        double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
                        const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
                        size_t ws_bytes, void* stream) {
-  (void)p; (void)nbox; (void)boxes; (void)cons; (void)bface; (void)nsteps; (void)dt_mode;
-  (void)dt_fixed; (void)dt_out; (void)diag; (void)workspace; (void)ws_bytes; (void)stream;
-  return fail(CTMHD_EUNSUPPORTED, "ctmhd_step_batched is not built yet");
+  g_err[0] = 0;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_boxes(p, boxes, nbox))) return rc;
+  if (p->force_flags) return fail(CTMHD_EARG, "force_flags is a single-box test hook");
+  if (!plan) return fail(CTMHD_EARG, "plan is NULL");
+  if (!cons || !bface) return fail(CTMHD_EARG, "state pointers are NULL");
+  for (int m = 0; m < 5; ++m)
+    if (!cons[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!bface[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
+  if (dt_mode != CTMHD_DT_GLOBAL && dt_mode != CTMHD_DT_PER_BOX) return fail(CTMHD_EARG, "unknown dt mode");
+  if (nsteps < 0) return fail(CTMHD_EARG, "nsteps must be >= 0");
+  if (nsteps == 0) return CTMHD_OK;
+  if (packed_elems(boxes, nbox) * 6 >= (1LL << 31) * 64LL) return fail(CTMHD_EARG, "packed arrays too large");
+  hipStream_t st = (hipStream_t)stream;
+  if (p->precision == CTMHD_FP32)
+    return batched_t<float>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out,
+                            diag, workspace, ws_bytes, st);
+  return batched_t<double>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out,
+                           diag, workspace, ws_bytes, st);
 }
 
 int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],

@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
                 ("recon", ctypes.c_int32), ("riemann", ctypes.c_int32),
                 ("emf_compute", ctypes.c_int32), ("emf_average", ctypes.c_int32),
                 ("fofc", ctypes.c_int32), ("flag_criteria", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("force_flags", ctypes.c_void_p)]
 
 
@@ -64,8 +64,12 @@ def lib():
         L.ctmhd_step.argtypes = [_P, _B, _PTR5, _PTR3, ctypes.c_int, _vp, _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]
         L.ctmhd_step.restype = ctypes.c_int
-        L.ctmhd_step_batched.argtypes = [_P, ctypes.c_int, _B, _PTR5, _PTR3, ctypes.c_int,
+        L.ctmhd_step_batched.argtypes = [_P, ctypes.c_int, _B, _vp, _PTR5, _PTR3, ctypes.c_int,
                                          ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.ctmhd_batch_plan_bytes.argtypes = [_P, _B, ctypes.c_int]
+        L.ctmhd_batch_plan_bytes.restype = ctypes.c_size_t
+        L.ctmhd_batch_plan.argtypes = [_P, _B, ctypes.c_int, _vp, ctypes.c_size_t]
+        L.ctmhd_batch_plan.restype = ctypes.c_int
         L.ctmhd_step_batched.restype = ctypes.c_int
         L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
                                          _vp, ctypes.c_size_t, _vp]
@@ -81,7 +85,8 @@ def lib():
 
 
 EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
-            "ctmhd_step_batched", "ctmhd_step_adjoint", "ctmhd_profile_events",
+            "ctmhd_batch_plan_bytes", "ctmhd_batch_plan", "ctmhd_step_batched",
+            "ctmhd_step_adjoint", "ctmhd_profile_events",
             "ctmhd_profile_recorded", "ctmhd_last_error")
 
 
@@ -92,12 +97,17 @@ def _check(rc):
 
 
 def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", emf="q26",
-                fofc=True, flag_mask=7, precision="fp64", force_flags=None) -> Params:
+                fofc=True, flag_mask=7, precision="fp64", force_flags=None, tile=0) -> Params:
     ff = None
     if force_flags is not None:
         ff = force_flags.data_ptr()
     return Params(float(gamma), float(eta), float(cfl), RECON[recon], RIEMANN[riemann], EMF[emf],
-                  0, int(bool(fofc)), int(flag_mask), PRECISION[precision], 0, ff)
+                  0, int(bool(fofc)), int(flag_mask), PRECISION[precision], int(tile), ff)
+
+
+def make_tile(chunk=0, strips=0):
+    """The ctmhd_params.tile knob: minimum marching chunk and batched strips."""
+    return (int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8)
 
 
 def make_box(n, ng, dx, offset=0) -> Box:
@@ -141,11 +151,23 @@ def ctmhd_step(params: Params, box: Box, cons, bface, nsteps, dt_fixed=None, dt_
     return _check(rc)
 
 
-def ctmhd_step_batched(params: Params, boxes, cons, bface, nsteps, dt_mode=DT_GLOBAL,
+def batch_plan(params: Params, boxes):
+    """Host plan bytes of the batched work queue (a numpy uint8 array)."""
+    arr = (Box * len(boxes))(*boxes)
+    n = int(lib().ctmhd_batch_plan_bytes(ctypes.byref(params), arr, len(boxes)))
+    if n == 0:
+        _check(-1)
+    buf = np.zeros(n, np.uint8)
+    _check(lib().ctmhd_batch_plan(ctypes.byref(params), arr, len(boxes),
+                                  buf.ctypes.data_as(ctypes.c_void_p), n))
+    return buf
+
+
+def ctmhd_step_batched(params: Params, boxes, plan, cons, bface, nsteps, dt_mode=DT_GLOBAL,
                        dt_fixed=None, dt_out=None, diag=None, workspace=None, stream=None):
     arr = (Box * len(boxes))(*boxes)
     ws = workspace
-    rc = lib().ctmhd_step_batched(ctypes.byref(params), len(boxes), arr,
+    rc = lib().ctmhd_step_batched(ctypes.byref(params), len(boxes), arr, _p(plan),
                                   _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
                                   int(nsteps), int(dt_mode), _p(dt_fixed), _p(dt_out), _p(diag),
                                   _p(ws), ws.numel() if ws is not None else 0, _stream(stream))
@@ -291,3 +313,145 @@ class KernelTimer:
     def close(self):
         for i in range(2 * self.npairs):
             self.hip.hipEventDestroy(self.events[i])
+
+
+# ---------------------------------------------------------------------------
+# Batched boxes: packed device arrays and convenience wrappers.
+# ---------------------------------------------------------------------------
+class BatchedState:
+    """Many ghosted boxes packed back to back in 8 float64 device arrays."""
+
+    def __init__(self, shapes, ng, dxs, device="cuda"):
+        import torch
+        self.ng = int(ng)
+        self.shapes = [tuple(int(v) for v in n) for n in shapes]
+        self.dxs = [tuple(float(v) for v in dx) for dx in dxs]
+        self.offsets = []
+        off = 0
+        self.boxes = []
+        for n, dx in zip(self.shapes, self.dxs):
+            self.offsets.append(off)
+            self.boxes.append(make_box(n, self.ng, dx, off))
+            off += (n[0] + 2 * ng) * (n[1] + 2 * ng) * (n[2] + 2 * ng)
+        self.total = off
+        self.cons = [torch.zeros(off, dtype=torch.float64, device=device) for _ in range(5)]
+        self.bface = [torch.zeros(off, dtype=torch.float64, device=device) for _ in range(3)]
+
+    def _view(self, t, b):
+        n = self.shapes[b]
+        g = self.ng
+        e = (n[0] + 2 * g) * (n[1] + 2 * g) * (n[2] + 2 * g)
+        return t[self.offsets[b]:self.offsets[b] + e].view(n[2] + 2 * g, n[1] + 2 * g, n[0] + 2 * g)
+
+    def _interior(self, b):
+        g = self.ng
+        n = self.shapes[b]
+        return (slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
+
+    @classmethod
+    def from_numpy(cls, states, ng, device="cuda"):
+        """states: list of (cons (5,n2,n1,n0), bface (3,n2,n1,n0), dx)."""
+        import torch
+        shapes = [(c.shape[3], c.shape[2], c.shape[1]) for c, _, _ in states]
+        st = cls(shapes, ng, [dx for _, _, dx in states], device)
+        # fill on the host, one transfer per field
+        hc = [np.zeros(st.total) for _ in range(5)]
+        hb = [np.zeros(st.total) for _ in range(3)]
+        for b, (c, bf, _) in enumerate(states):
+            n = st.shapes[b]
+            g = st.ng
+            shp = (n[2] + 2 * g, n[1] + 2 * g, n[0] + 2 * g)
+            sl = st._interior(b)
+            e = shp[0] * shp[1] * shp[2]
+            for m in range(5):
+                hc[m][st.offsets[b]:st.offsets[b] + e].reshape(shp)[sl] = c[m]
+            for a in range(3):
+                hb[a][st.offsets[b]:st.offsets[b] + e].reshape(shp)[sl] = bf[a]
+        for m in range(5):
+            st.cons[m].copy_(torch.from_numpy(hc[m]))
+        for a in range(3):
+            st.bface[a].copy_(torch.from_numpy(hb[a]))
+        return st
+
+    def to_numpy(self):
+        hc = [t.cpu().numpy() for t in self.cons]
+        hb = [t.cpu().numpy() for t in self.bface]
+        out = []
+        for b in range(len(self.shapes)):
+            n = self.shapes[b]
+            g = self.ng
+            shp = (n[2] + 2 * g, n[1] + 2 * g, n[0] + 2 * g)
+            e = shp[0] * shp[1] * shp[2]
+            sl = self._interior(b)
+            c = np.stack([hc[m][self.offsets[b]:self.offsets[b] + e].reshape(shp)[sl] for m in range(5)])
+            bf = np.stack([hb[a][self.offsets[b]:self.offsets[b] + e].reshape(shp)[sl] for a in range(3)])
+            out.append((c, bf))
+        return out
+
+
+class BatchedStepper:
+    """Workspace and device plan for one parameter set and one set of boxes."""
+
+    def __init__(self, params: Params, state: BatchedState):
+        import torch
+        self.params = params
+        self.state = state
+        dev = state.cons[0].device
+        plan = batch_plan(params, state.boxes)
+        self.plan = torch.from_numpy(plan).to(dev)
+        nbytes = workspace_bytes(params, state.boxes)
+        if nbytes == 0:
+            raise CtmhdError("workspace size query failed")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        if self.workspace.data_ptr() % 256 or self.plan.data_ptr() % 16:
+            raise CtmhdError("workspace / plan allocation is not aligned")
+
+    def step(self, nsteps=1, dt_mode=DT_GLOBAL, dt_fixed=None, dt_out=None, diag=None,
+             stream=None):
+        ctmhd_step_batched(self.params, self.state.boxes, self.plan, self.state.cons,
+                           self.state.bface, nsteps, dt_mode, dt_fixed, dt_out, diag,
+                           self.workspace, stream)
+
+
+def run_batched(params: Params, states, nsteps=1, dt_mode=DT_GLOBAL, dt_fixed=None, ng=None,
+                device="cuda"):
+    """Convenience: list of numpy (cons, bface, dx) in, list of (cons, bface)
+    out, with dt values (nsteps or nsteps x nbox) and per-step diagnostics."""
+    import torch
+    if ng is None:
+        ng = required_ghosts(params)
+    st = BatchedState.from_numpy(states, ng, device)
+    S = BatchedStepper(params, st)
+    ndt = len(states) if dt_mode == DT_PER_BOX else 1
+    dts = torch.zeros(nsteps * ndt, dtype=torch.float64, device=device)
+    diag = torch.zeros(4 * nsteps, dtype=torch.int64, device=device)
+    dtf = None
+    if dt_fixed is not None:
+        dtf = torch.as_tensor(np.asarray(dt_fixed, np.float64).reshape(-1).copy(), device=device)
+    S.step(nsteps, dt_mode, dtf, dts, diag)
+    torch.cuda.synchronize()
+    return st.to_numpy(), dts.cpu().numpy().reshape(nsteps, ndt), diag.cpu().numpy().reshape(nsteps, 4)
+
+
+def parse_plan(plan):
+    """Decode a host plan (for checks on the CPU): header fields, box order,
+    per-phase item prefixes."""
+    import struct
+    buf = bytes(plan)
+    nbox, nphase, strips, magic = struct.unpack_from("4i", buf, 0)
+    (key,) = struct.unpack_from("Q", buf, 16)
+    kmax = 16
+    o = 24
+    kind = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
+    stage = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
+    item_off = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
+    rng = struct.unpack_from("6i", buf, o); o += 24
+    range_items = struct.unpack_from("3i", buf, o); o += 12
+    o = (o + 7) & ~7
+    order_off, prefix_off, desc_off = struct.unpack_from("3q", buf, o)
+    order = np.frombuffer(buf, np.int32, nbox, order_off)
+    prefix = np.frombuffer(buf, np.int32, nphase * (nbox + 1), prefix_off).reshape(nphase, nbox + 1)
+    return dict(nbox=nbox, nphase=nphase, strips=strips, magic=magic, key=key, kind=kind[:nphase],
+                stage=stage[:nphase], item_off=item_off[:nphase],
+                range=[rng[0:2], rng[2:4], rng[4:6]], range_items=list(range_items),
+                order=order, prefix=prefix)

@@ -290,3 +290,47 @@ def turbulent_mach2_beta1(n=256):
     along x0), rms |db| = |b0|/2."""
     b = math.sqrt(2.0 / GAMMA)
     return turbulent_box((n, n, n), mach=2.0, b0=(b, 0.0, 0.0), db_rms=0.5 * b, seed_v=1, seed_a=2)
+
+
+def amr_like_boxes(nbox=2000, seed=4, dx=1.0 / 64.0, sizes=(8, 16, 32, 64), gamma=GAMMA):
+    """Many small periodic boxes of uneven sizes (one AMR level, common dx).
+    Per box: edge lengths drawn per axis from `sizes`; rho = 1 + 0.2 S_rho,
+    u_d = 0.5 S_ud, edge potential A_c = 0.1 |b0| S_Ac, where each S is a sum
+    of 3 sine modes with integer per-box-periodic wave vectors (components in
+    {0,1,2}, not all zero) and uniform random phases; p = 1/gamma; b0 along a
+    random axis with |b0| = sqrt(2p/beta), log10 beta uniform in [-1, 1].
+    Returns a list of (cons, bface, dx)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nbox):
+        n = tuple(int(v) for v in rng.choice(sizes, size=3))
+        L = tuple(n[d] * dx for d in range(3))
+
+        def modes():
+            ks = []
+            while len(ks) < 3:
+                k = rng.integers(0, 3, size=3)
+                if k.any():
+                    ks.append(k)
+            return ks, rng.uniform(0.0, 2.0 * np.pi, size=3)
+
+        def series(ks, ph, x):
+            return sum(np.sin(2.0 * np.pi * (k[0] * x[0] / L[0] + k[1] * x[1] / L[1] +
+                                             k[2] * x[2] / L[2]) + f) for k, f in zip(ks, ph))
+
+        xc = _coords(n, L)
+        ks, ph = modes()
+        rho = 1.0 + 0.2 * series(ks, ph, xc)
+        u = np.stack([0.5 * series(*modes(), xc) for _ in range(3)])
+        p0 = 1.0 / gamma
+        beta = 10.0 ** rng.uniform(-1.0, 1.0)
+        bmag = math.sqrt(2.0 * p0 / beta)
+        axis = int(rng.integers(0, 3))
+        A = np.zeros((3, n[2], n[1], n[0]))
+        for c in range(3):
+            A[c] = 0.1 * bmag * series(*modes(), edge_coords(n, c, L))
+        bf = curl_edges(A, [dx, dx, dx])
+        bf[axis] += bmag
+        p = np.full(rho.shape, p0)
+        out.append((from_primitives(rho, u, p, bf, gamma), bf, (dx, dx, dx)))
+    return out

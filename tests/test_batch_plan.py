@@ -1,0 +1,109 @@
+"""The batched work-queue plan, built by the library on the host: item
+decoding, per-box item counts and the dependency order the persistent kernel
+relies on (every item's dependencies precede it in the queue)."""
+import numpy as np
+import pytest
+
+from paper_2609_10816_amd import ctmhd
+
+PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P = range(9)
+
+
+def _boxes(seed, nbox, ng=4):
+    rng = np.random.default_rng(seed)
+    boxes, off = [], 0
+    for _ in range(nbox):
+        n = [int(v) for v in rng.choice([1, 3, 8, 16, 32, 64], size=3)]
+        boxes.append(ctmhd.make_box(n, ng, (1 / 64,) * 3, off))
+        off += int(np.prod([v + 2 * ng for v in n])) + int(rng.integers(0, 100))
+    return boxes
+
+
+def _decode(d, launch, q):
+    lo, hi = d["range"][launch]
+    p = lo
+    while p + 1 < hi and d["item_off"][p + 1] <= q:
+        p += 1
+    pre = d["prefix"][p]
+    r = q - d["item_off"][p]
+    k = int(np.searchsorted(pre, r, side="right") - 1)
+    return p, k, r - pre[k]
+
+
+@pytest.mark.parametrize("fofc,emf", [(True, "q26"), (False, "q26"), (True, "b25a"),
+                                      (False, "fs18")])
+@pytest.mark.parametrize("tile", [0, ctmhd.make_tile(chunk=8, strips=4)])
+def test_plan_queue_invariants(fofc, emf, tile):
+    boxes = _boxes(1, 37)
+    P = ctmhd.make_params(recon="ppm", fofc=fofc, emf=emf, tile=tile)
+    d = ctmhd.parse_plan(ctmhd.batch_plan(P, boxes))
+    assert d["magic"] == 0x43544D48 and d["nbox"] == len(boxes)
+    kinds = d["kind"]
+    step = kinds[d["range"][1][0]:d["range"][1][1]]
+    expect = ([PH_P] if emf != "q26" else []) + [PH_F, PH_E, PH_U] + ([PH_O, PH_X] if fofc else [])
+    assert step == expect * 2
+    assert kinds[d["range"][0][0]:d["range"][0][1]] == [PH_WRAP, PH_DT]
+    # largest boxes first
+    inter = [b.n[0] * b.n[1] * b.n[2] for b in boxes]
+    assert all(inter[d["order"][i]] >= inter[d["order"][i + 1]] for i in range(len(boxes) - 1))
+    strips = d["strips"]
+    for launch in range(3):
+        lo, hi = d["range"][launch]
+        total = 0
+        for p in range(lo, hi):
+            assert d["item_off"][p] == total
+            total += int(d["prefix"][p][-1])
+        assert d["range_items"][launch] == total
+        # per-box counts for cell-strip phases
+        for p in range(lo, hi):
+            for k in range(len(boxes)):
+                cnt = d["prefix"][p][k + 1] - d["prefix"][p][k]
+                b = boxes[d["order"][k]]
+                ninter = b.n[0] * b.n[1] * b.n[2]
+                if kinds[p] in (PH_U, PH_O, PH_X, PH_DT):
+                    assert cnt == -(-ninter // (256 * strips))
+                elif kinds[p] in (PH_P, PH_WRAP, PH_COPY):
+                    elems = int(np.prod([v + 2 * b.ng for v in b.n]))
+                    assert cnt == -(-elems // (256 * strips))
+                elif kinds[p] == PH_E:
+                    assert cnt == -(-((b.n[0] + 1) * (b.n[1] + 1) * (b.n[2] + 1)) // (256 * strips))
+                else:
+                    assert cnt >= 1
+        # decoding is a bijection onto (phase, box, tile) and every dependency
+        # (all items of the previous phase of the same box) comes earlier
+        seen = set()
+        last_of = {}
+        first_of = {}
+        for q in range(total):
+            p, k, tile_ = _decode(d, launch, q)
+            assert 0 <= tile_ < d["prefix"][p][k + 1] - d["prefix"][p][k]
+            key = (p, k, tile_)
+            assert key not in seen
+            seen.add(key)
+            last_of[(p, k)] = q
+            first_of.setdefault((p, k), q)
+        for (p, k), q0 in first_of.items():
+            if p > lo:
+                assert last_of[(p - 1, k)] < q0
+
+
+def test_plan_rejects_overlap_and_bad_buffers():
+    P = ctmhd.make_params(recon="plm")
+    b = [ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3, 0), ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3, 100)]
+    with pytest.raises(ctmhd.CtmhdError):
+        ctmhd.batch_plan(P, b)
+
+
+def test_plan_key_depends_on_params_and_boxes():
+    boxes = _boxes(2, 5)
+    P = ctmhd.make_params(recon="ppm")
+    k0 = ctmhd.parse_plan(ctmhd.batch_plan(P, boxes))["key"]
+    assert k0 == ctmhd.parse_plan(ctmhd.batch_plan(P, boxes))["key"]
+    moved = list(boxes)
+    last = moved[-1]
+    moved[-1] = ctmhd.make_box(tuple(last.n), last.ng, tuple(last.dx), last.offset + 1)
+    assert ctmhd.parse_plan(ctmhd.batch_plan(P, moved))["key"] != k0
+    P2 = ctmhd.make_params(recon="ppm", tile=ctmhd.make_tile(strips=2))
+    assert ctmhd.parse_plan(ctmhd.batch_plan(P2, boxes))["key"] != k0
+    P3 = ctmhd.make_params(recon="ppm", emf="b25a")
+    assert ctmhd.parse_plan(ctmhd.batch_plan(P3, boxes))["key"] != k0

@@ -1,0 +1,202 @@
+"""The batched form (ctmhd_step_batched): many periodic boxes of uneven sizes
+in one persistent launch per step.  Each box is checked against the oracle
+run on that box alone (same dt sequence), and against the single-box GPU
+path; the launch sequence is replayed from a captured HIP graph."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import divb_rel, rel_l1
+from paper_2609_10816_amd import ctmhd, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_boxes(seed=5, nbox=7):
+    states = inputs.amr_like_boxes(nbox=nbox, seed=seed, sizes=(4, 8, 12, 16))
+    # one degenerate box (1D in 3D) and one blast box that trips the FOFC flags
+    n = (16, 1, 1)
+    shape = (1, 1, 16)
+    x = (np.arange(16) + 0.5) / 16
+    rho = np.ones(shape)
+    u = np.zeros((3,) + shape)
+    p = np.where(np.abs(x - 0.5) < 0.1, 1e3, 0.1).reshape(shape)
+    bf = np.zeros((3,) + shape)
+    bf[0] = 1.0
+    bf[1] = 8.0
+    states.append((inputs.from_primitives(rho, u, p, bf), bf, (1 / 16, 1.0, 1.0)))
+    return states
+
+
+def _params(**kw):
+    ok = {k: v for k, v in kw.items() if k not in ("precision", "tile")}
+    return ctmhd.make_params(**kw), oracle.make_params(**ok)
+
+
+def _cmp_box(cg, bg, co, bo, tol, label):
+    scale_c = [max(np.abs(co[m]).mean(), np.abs(co[0]).mean()) for m in range(5)]
+    scale_b = max(np.abs(bo).mean(), 1e-300)
+    worst = 0.0
+    for m in range(5):
+        worst = max(worst, np.abs(cg[m] - co[m]).max() / scale_c[m])
+    for a in range(3):
+        worst = max(worst, np.abs(bg[a] - bo[a]).max() / scale_b)
+    assert worst <= tol, (label, worst)
+    return worst
+
+
+@pytest.mark.parametrize("emf", ["q26", "b25a"])
+def test_batched_equals_single_box_path(emf):
+    states = _small_boxes()
+    P, _ = _params(recon="ppm", emf=emf, eta=1e-3)
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=3)
+    for b, (c, bf, dx) in enumerate(states):
+        cg, bg, _, _ = ctmhd.run(P, c, bf, dx, 3, dt_fixed=dts[:, 0])
+        assert np.array_equal(outs[b][0], cg) and np.array_equal(outs[b][1], bg), b
+
+
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
+def test_batched_vs_oracle_global_dt(emf):
+    states = _small_boxes()
+    P, Q = _params(recon="ppm", emf=emf, eta=1e-3)
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=2)
+    # the global dt is the CFL dt of the box with the largest signal speed
+    dt0 = min(oracle.cfl_dt(Q, c, bf, dx) for c, bf, dx in states)
+    assert dts[0, 0] == pytest.approx(dt0, rel=1e-13)
+    nflag = 0
+    worst = 0.0
+    for b, (c, bf, dx) in enumerate(states):
+        co, bo, _, do = oracle.step(Q, c, bf, dx, nsteps=2, dt_fixed=dts[:, 0])
+        nflag += do[0] + do[1]
+        worst = max(worst, _cmp_box(outs[b][0], outs[b][1], co, bo, 1e-12, f"box {b}"))
+        assert divb_rel(outs[b][1], dx) < 1e-13
+    assert int(dg[:, :2].sum()) == nflag
+    print(f"[batched] {len(states)} boxes {emf}: worst scaled diff {worst:.2e}, flagged {nflag}",
+          flush=True)
+
+
+def test_batched_per_box_dt():
+    states = _small_boxes(seed=6)
+    P, Q = _params(recon="plm", emf="q26")
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=2, dt_mode=ctmhd.DT_PER_BOX)
+    for b, (c, bf, dx) in enumerate(states):
+        co, bo, dto, _ = oracle.step(Q, c, bf, dx, nsteps=2)
+        np.testing.assert_allclose(dts[:, b], dto, rtol=1e-13)
+        _cmp_box(outs[b][0], outs[b][1], co, bo, 1e-12, f"box {b}")
+
+
+def test_batched_fp32_vs_oracle():
+    states = _small_boxes(seed=7)
+    P, Q = _params(recon="ppm", emf="q26", precision="fp32")
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=10)
+    worst = 0.0
+    for b, (c, bf, dx) in enumerate(states):
+        co, bo, _, _ = oracle.step(Q, c, bf, dx, nsteps=10, dt_fixed=dts[:, 0])
+        for m in range(5):
+            worst = max(worst, rel_l1(outs[b][0][m], co[m]))
+        for a in range(3):
+            worst = max(worst, rel_l1(outs[b][1][a], bo[a]))
+        for m in range(5):
+            s0, s1 = c[m].sum(), outs[b][0][m].sum()
+            assert abs(s1 - s0) <= 1e-13 * (np.abs(c[m]).sum() + np.abs(outs[b][0][m]).sum())
+        assert divb_rel(outs[b][1], dx) < 1e-13
+    print(f"[batched] fp32, 10 steps: worst relative L1 vs oracle {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+
+
+def test_batched_tile_knob_same_result():
+    states = _small_boxes(seed=8)
+    P0, _ = _params(recon="ppm")
+    P1, _ = _params(recon="ppm", tile=ctmhd.make_tile(chunk=8, strips=3))
+    a, da, _ = ctmhd.run_batched(P0, states, nsteps=2)
+    b, db, _ = ctmhd.run_batched(P1, states, nsteps=2)
+    assert np.array_equal(da, db)
+    for x, y in zip(a, b):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_batched_hipgraph_replay():
+    """Capture a 2-step batched call in a HIP graph; replay it three times from
+    the same initial state with eager work in between; every replay equals
+    the eager result."""
+    import torch
+    states = _small_boxes(seed=9)
+    P, _ = _params(recon="ppm", emf="q26")
+    st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
+    S = ctmhd.BatchedStepper(P, st)
+    init_c = [t.clone() for t in st.cons]
+    init_b = [t.clone() for t in st.bface]
+    dts = torch.zeros(2, dtype=torch.float64, device="cuda")
+    diag = torch.zeros(8, dtype=torch.int64, device="cuda")
+
+    def reset():
+        for t, s in zip(st.cons + st.bface, init_c + init_b):
+            t.copy_(s)
+
+    reset()
+    S.step(2, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    ref_c = [t.clone() for t in st.cons]
+    ref_b = [t.clone() for t in st.bface]
+    ref_dt = dts.clone()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        reset()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            S.step(2, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        reset()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for t, r in zip(st.cons + st.bface, ref_c + ref_b):
+            assert torch.equal(t, r), rep
+        assert torch.equal(dts, ref_dt), rep
+        del junk
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_amr_like_2000_boxes_sampled(precision):
+    """The 2000-box AMR-like workload (edges from {8,16,32,64}, 4 ghost
+    layers, PPM + Q26), 2 steps; 24 sampled boxes of every size class against
+    the oracle on each box alone with the same dt; invariants on every
+    sampled box."""
+    import torch
+    states = inputs.amr_like_boxes(2000, seed=4)
+    P, Q = _params(recon="ppm", emf="q26", precision=precision)
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=2)
+    rng = np.random.default_rng(11)
+    by_size = {}
+    for b, (c, _, _) in enumerate(states):
+        by_size.setdefault(max(c.shape[1:]), []).append(b)
+    sample = []
+    for sz in sorted(by_size):
+        sample += list(rng.choice(by_size[sz], size=min(6, len(by_size[sz])), replace=False))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    worst = 0.0
+    for b in sample:
+        c, bf, dx = states[b]
+        co, bo, _, _ = oracle.step(Q, c, bf, dx, nsteps=2, dt_fixed=dts[:, 0])
+        if precision == "fp64":
+            worst = max(worst, _cmp_box(outs[b][0], outs[b][1], co, bo, tol, f"box {b}"))
+        else:
+            e = max([rel_l1(outs[b][0][m], co[m]) for m in range(5)] +
+                    [rel_l1(outs[b][1][a], bo[a]) for a in range(3)])
+            worst = max(worst, e)
+            assert e <= tol, (b, e)
+        for m in range(5):
+            s0, s1 = c[m].sum(), outs[b][0][m].sum()
+            assert abs(s1 - s0) <= 1e-13 * (np.abs(c[m]).sum() + np.abs(outs[b][0][m]).sum())
+        assert divb_rel(outs[b][1], dx) < 1e-13
+    print(f"[batched] 2000 boxes {precision}: {len(sample)} sampled boxes, worst {worst:.2e}, "
+          f"dt {dts[0, 0]:.4e}, flagged {int(dg[:, :2].sum())}, timeout flag {int(dg[:, 3].max())}",
+          flush=True)
+    assert int(dg[:, 3].max()) == 0
+    torch.cuda.empty_cache()
