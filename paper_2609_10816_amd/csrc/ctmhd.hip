@@ -1110,17 +1110,17 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
     } else if (kind == PH_E) {
       for (int s = 0; s < strips; ++s)
         emf_at<T, RECON, EMF>(in, G, W, stage, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_U) {
-      update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, 0, U, A.diag, tile, strips,
-                     W.smax, 0);
+    } else if (kind == PH_U || kind == PH_X) {
+      // one call site, fixup a run-time value as in k_update, so that both
+      // paths compile to the same arithmetic
+      const int fix = kind == PH_X ? 1 : 0;
+      if (!fix || W.nflag[stage])
+        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, fix, U, A.diag, tile, strips,
+                       W.smax, fix);
     } else if (kind == PH_O) {
       if (W.nflag[stage])
         for (int s = 0; s < strips; ++s)
           fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_X) {
-      if (W.nflag[stage])
-        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, 1, U, A.diag, tile, strips,
-                       W.smax, 1);
     } else if (kind == PH_WRAP) {
       for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
     } else if (kind == PH_DT) {

@@ -295,7 +295,8 @@ def turbulent_mach2_beta1(n=256):
 def amr_like_boxes(nbox=2000, seed=4, dx=1.0 / 64.0, sizes=(8, 16, 32, 64), gamma=GAMMA):
     """Many small periodic boxes of uneven sizes (one AMR level, common dx).
     Per box: edge lengths drawn per axis from `sizes`; rho = 1 + 0.2 S_rho,
-    u_d = 0.5 S_ud, edge potential A_c = 0.1 |b0| S_Ac, where each S is a sum
+    u_d = 0.5 S_ud, edge potential A_c = 0.1 |b0| L_min / (2 pi) S_Ac (so that
+    each mode's field perturbation is at most 0.1 |b0| |k|), where each S is a sum
     of 3 sine modes with integer per-box-periodic wave vectors (components in
     {0,1,2}, not all zero) and uniform random phases; p = 1/gamma; b0 along a
     random axis with |b0| = sqrt(2p/beta), log10 beta uniform in [-1, 1].
@@ -327,8 +328,9 @@ def amr_like_boxes(nbox=2000, seed=4, dx=1.0 / 64.0, sizes=(8, 16, 32, 64), gamm
         bmag = math.sqrt(2.0 * p0 / beta)
         axis = int(rng.integers(0, 3))
         A = np.zeros((3, n[2], n[1], n[0]))
+        amp = 0.1 * bmag * min(L) / (2.0 * np.pi)
         for c in range(3):
-            A[c] = 0.1 * bmag * series(*modes(), edge_coords(n, c, L))
+            A[c] = amp * series(*modes(), edge_coords(n, c, L))
         bf = curl_edges(A, [dx, dx, dx])
         bf[axis] += bmag
         p = np.full(rho.shape, p0)

@@ -54,7 +54,20 @@ def test_batched_equals_single_box_path(emf):
     outs, dts, dg = ctmhd.run_batched(P, states, nsteps=3)
     for b, (c, bf, dx) in enumerate(states):
         cg, bg, _, _ = ctmhd.run(P, c, bf, dx, 3, dt_fixed=dts[:, 0])
-        assert np.array_equal(outs[b][0], cg) and np.array_equal(outs[b][1], bg), b
+        diff = max(np.abs(outs[b][0] - cg).max(), np.abs(outs[b][1] - bg).max())
+        assert np.array_equal(outs[b][0], cg) and np.array_equal(outs[b][1], bg), (b, diff)
+
+
+def test_batched_deterministic():
+    """Two runs of the same batched call agree bit for bit (the schedule of
+    the work queue differs between runs; the arithmetic must not)."""
+    states = _small_boxes(seed=12)
+    P, _ = _params(recon="ppm", emf="q26", eta=1e-3)
+    a, da, ga = ctmhd.run_batched(P, states, nsteps=3)
+    b, db, gb = ctmhd.run_batched(P, states, nsteps=3)
+    assert np.array_equal(da, db) and np.array_equal(ga, gb)
+    for x, y in zip(a, b):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
 
 
 @pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
@@ -107,14 +120,26 @@ def test_batched_fp32_vs_oracle():
 
 
 def test_batched_tile_knob_same_result():
+    """The strips knob only regroups work items: bitwise the same result.  The
+    chunk knob moves where the y/z face marches start, so a face's
+    reconstruction may be evaluated with another grouping of fused
+    multiply-adds: the same result to round-off, in the single-box path too."""
     states = _small_boxes(seed=8)
-    P0, _ = _params(recon="ppm")
-    P1, _ = _params(recon="ppm", tile=ctmhd.make_tile(chunk=8, strips=3))
+    P0, Q = _params(recon="ppm")
     a, da, _ = ctmhd.run_batched(P0, states, nsteps=2)
+    P1, _ = _params(recon="ppm", tile=ctmhd.make_tile(strips=3))
     b, db, _ = ctmhd.run_batched(P1, states, nsteps=2)
     assert np.array_equal(da, db)
     for x, y in zip(a, b):
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+    P2, _ = _params(recon="ppm", tile=ctmhd.make_tile(chunk=8, strips=3))
+    c2, dc, _ = ctmhd.run_batched(P2, states, nsteps=2)
+    assert np.array_equal(da, dc)
+    for k, (x, y) in enumerate(zip(a, c2)):
+        _cmp_box(y[0], y[1], x[0], x[1], 1e-14, f"box {k}")
+        c, bf, dx = states[k]
+        single = ctmhd.run(P2, c, bf, dx, 2, dt_fixed=da[:, 0])
+        assert np.array_equal(single[0], y[0]) and np.array_equal(single[1], y[1])
 
 
 def test_batched_hipgraph_replay():
@@ -200,3 +225,25 @@ def test_amr_like_2000_boxes_sampled(precision):
           flush=True)
     assert int(dg[:, 3].max()) == 0
     torch.cuda.empty_cache()
+
+
+def test_batched_refuses_plan_of_other_boxes():
+    """A plan built for other boxes is refused on the device: diag[3] bit 4,
+    the state is left untouched, and the kernels exit normally."""
+    import torch
+    states = _small_boxes(seed=10, nbox=4)
+    P, _ = _params(recon="plm")
+    st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
+    S = ctmhd.BatchedStepper(P, st)
+    other = [ctmhd.make_box(tuple(b.n), b.ng, tuple(b.dx), b.offset) for b in st.boxes]
+    last = other[-1]
+    other[-1] = ctmhd.make_box((last.n[0], last.n[1], last.n[2]), last.ng,
+                               (last.dx[0] * 2, last.dx[1], last.dx[2]), last.offset)
+    S.plan = torch.from_numpy(ctmhd.batch_plan(P, other)).to("cuda")
+    before = [t.clone() for t in st.cons + st.bface]
+    diag = torch.zeros(4, dtype=torch.int64, device="cuda")
+    S.step(1, diag=diag)
+    torch.cuda.synchronize()
+    assert int(diag[3]) & 4
+    for t, r in zip(st.cons + st.bface, before):
+        assert torch.equal(t, r)
