@@ -132,6 +132,91 @@ def run_gpu(cfg, precision, emf, K, W, timer_pairs=0, copy_calibration=False):
     return res, (cons, bf, info)
 
 
+def run_batched_form(K, W, log_tune=True):
+    """The batched AMR-like workload: 2000 periodic boxes with edges drawn
+    per axis from {8, 16, 32, 64}, 4 ghost layers, PPM + HLLD + Q26 + LD04,
+    global CFL dt.  The tile knob is picked by the autotuner; K steps are
+    captured in one HIP graph and replayed once inside the timed region.
+    Also times the same boxes stepped one ctmhd_step call at a time (the
+    per-box loop the batched launch replaces)."""
+    import torch
+
+    from paper_2609_10816_amd import autotune, ctmhd, inputs
+
+    t0 = time.time()
+    states = inputs.amr_like_boxes(2000, seed=4)
+    cells = sum(c[0].size for c, _, _ in states)
+    log(f"batched input: 2000 boxes, {cells / 1e6:.2f} M cells, generated in "
+        f"{time.time() - t0:.1f}s")
+    out = {"workload": "amr-like-2000-boxes-8..64-ppm", "boxes": len(states), "cells": cells,
+           "steps": K}
+    for precision in ("fp32", "fp64"):
+        P = ctmhd.make_params(recon="ppm", emf="q26", cfl=0.3, precision=precision)
+        st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
+        if precision == "fp32":
+            tile, tms = autotune.tune_batched(P, st, steps=2, reps=1)
+            log("autotune (ms/step): " + ", ".join(
+                f"{'persistent' if int(k) >> 16 else 'per-phase'} chunk {int(k) & 255}"
+                f"/strips {(int(k) >> 8) & 255}: {v:.2f}" for k, v in tms.items()))
+        P.tile = tile
+        S = ctmhd.BatchedStepper(P, st)
+        dev = st.cons[0].device
+        dts = torch.zeros(max(K, W, 1), dtype=torch.float64, device=dev)
+        diag = torch.zeros(4 * max(K, W, 1), dtype=torch.int64, device=dev)
+        if W:
+            S.step(W, dt_out=dts, diag=diag)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g):
+                S.step(K, dt_out=dts, diag=diag)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        dg = diag[: 4 * K].view(K, 4).cpu().numpy()
+        v = cells * K / el / 1e6
+        log(f"batched {precision}: {v:.1f} Mcell-updates/s ({el / K * 1e3:.2f} ms/step, "
+            f"flagged {int(dg[:, :2].sum())}, wait timeouts {int((dg[:, 3] & 2).any())})")
+        out[precision] = {"value": v, "unit": "Mcell-updates/s", "ms_per_step": el / K * 1e3,
+                          "fofc_flagged_cells": int(dg[:, :2].sum()),
+                          "queue_wait_timeout": bool((dg[:, 3] & 2).any())}
+        if precision == "fp32":
+            out["tile"] = {"chunk": tile & 255 or 32, "strips": ((tile >> 8) & 255) or 1,
+                           "schedule": "persistent" if tile >> 16 else "per-phase"}
+            out["autotune_ms_per_step"] = {
+                f"{'persistent' if int(k) >> 16 else 'per-phase'}/chunk{int(k) & 255}"
+                f"/strips{(int(k) >> 8) & 255}": v for k, v in tms.items()}
+            # the same boxes, one ctmhd_step call per box and step
+            ws = torch.empty(max(ctmhd.workspace_bytes(P, ctmhd.make_box(b.n, b.ng, b.dx))
+                                 for b in st.boxes), dtype=torch.uint8, device=dev)
+            single = [ctmhd.make_box(tuple(b.n), b.ng, tuple(b.dx)) for b in st.boxes]
+            views = [([st._view(t, k) for t in st.cons], [st._view(t, k) for t in st.bface])
+                     for k in range(len(single))]
+            Ploop = ctmhd.make_params(recon="ppm", emf="q26", cfl=0.3, precision=precision)
+            Ploop.tile = tile
+            nl = 2
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for n in range(nl):
+                for k, bx in enumerate(single):
+                    ctmhd.ctmhd_step(Ploop, bx, views[k][0], views[k][1], 1, dts[n:n + 1], None,
+                                     None, ws)
+            torch.cuda.synchronize()
+            el_loop = time.perf_counter() - t1
+            out["per_box_loop_fp32"] = {"value": cells * nl / el_loop / 1e6,
+                                        "unit": "Mcell-updates/s",
+                                        "ms_per_step": el_loop / nl * 1e3,
+                                        "steps": nl}
+            del ws, views
+        del S, st, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(cfg, emf, state):
     """The oracle (plain FP64 C++, OpenMP over z-planes) on one step of the
     same state."""
@@ -159,6 +244,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -213,6 +300,11 @@ def main():
         r32, _ = run_gpu(cfg, "fp32", args.emf, K, W)
         v32 = n3 * K / r32["elapsed"] / 1e6
         out["fp32_form"] = {"value": v32, "unit": "Mcell-updates/s", "speedup": v32 / value}
+    if not args.no_batched:
+        bf = run_batched_form(args.batched_steps, W)
+        bf["speedup_fp32_vs_fp64_single_box_step"] = bf["fp32"]["value"] / value
+        bf["speedup_vs_per_box_loop"] = bf["fp32"]["value"] / bf["per_box_loop_fp32"]["value"]
+        out["batched_form"] = bf
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.emf, state)
     print(json.dumps(out), flush=True)

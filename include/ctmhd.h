@@ -87,7 +87,9 @@ typedef struct ctmhd_params {
   int32_t precision;     /* CTMHD_FP64 or CTMHD_FP32 */
   int32_t tile;          /* launch-shape knob (0 = defaults): bits 0-7 minimum faces per
                             marching chunk of the face pass (default 32), bits 8-15
-                            256-element strips per work item of the batched call (default 1) */
+                            256-element strips per work item of the batched call (default 1),
+                            bits 16-23 schedule of the batched call (0 one launch per phase,
+                            1 one persistent launch per step) */
   /* Test hook: NULL, or a DEVICE mask of 2 * n0*n1*n2 bytes (stage-1 mask then
    * stage-2 mask, interior cells, x0 fastest) OR-ed into the invalid-cell
    * flags of every step.  Single-box call only. */
@@ -135,9 +137,17 @@ int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, vo
                      size_t bytes);
 
 /* Advance `nbox` independent periodic boxes of different sizes by `nsteps`
- * steps, one persistent launch per step: workgroups drain a device work
- * queue of (phase, box, tile) items in phase-major order; an item waits only
- * for the previous phase of its own box.  Box b's 8 fields start at element
+ * steps.  The work of a step is a list of (phase, box, tile) items in
+ * phase-major order, described by the plan.  Two schedules (tile bits
+ * 16-23), with bitwise the same result:
+ *   0: one launch per phase over all boxes, workgroup r runs item r; the
+ *      launch boundaries order the phases (about 10-14 launches per step);
+ *   1: one persistent launch per step whose workgroups claim items from a
+ *      device queue; an item waits (acquire) only for the previous phase of
+ *      its own box, and publishes its results (release) at agent scope.
+ *      Currently DISABLED: returns CTMHD_EUNSUPPORTED (a launch of it did not
+ *      finish; the cause has not been found).
+ * Box b's 8 fields start at element
  * boxes[b].offset of the packed arrays cons[m] / bface[a] and are laid out as
  * in ctmhd_step (its own ghost layers; each box is periodic on itself);
  * boxes must not overlap.  `boxes` is the HOST array the plan was made from,

@@ -979,9 +979,24 @@ struct BatchArgs {
   const int* loc;     // where the current state lives: 0 `user`, 1 B (flipped by each step that ran)
   int launch;         // 0 start (wrap + CFL), 1 step, 2 copy-back
   unsigned long long key;  // must equal the plan's key
+  unsigned long long tab;  // device address of BoxTab<T>[nbox]
   double gamma, eta;
   int fofc, crit;
 };
+
+// Everything one box needs, with its pointers already shifted to the box:
+// built once per batched call by k_btab in the workspace and read through the
+// constant address space (uniform scalar loads that may be indexed at run
+// time, as kernel arguments are in the single-box kernels).
+template <typename T>
+struct BoxTab {
+  State su, sb, sh;  // the box in the caller's arrays, in B, in H
+  Work<T> w;         // its stencil arrays and per-box scalars
+  Geom G;
+  FacePlan FP;
+  double sres;
+};
+#define CTMHD_CONST __attribute__((address_space(4)))
 
 __device__ __forceinline__ State shift_state(const State& S, long long off) {
   State R;
@@ -1016,23 +1031,27 @@ __device__ __forceinline__ Work<T> shift_work(const Work<T>& W0, long long off) 
   return W;
 }
 
-// Wait (thread 0, acquire) until *cnt >= need; bounded: on a timeout the
-// error flag is raised and every later wait returns at once.
+// Wait until *cnt >= need.  Thread 0 polls with relaxed loads (an acquire
+// per poll would invalidate the XCD's L2 on every iteration and starve the
+// working workgroups), then acquires once.  Bounded by wall-clock time
+// (100 MHz counter, about 1 s): on a timeout the error flag is raised and
+// every later wait returns at once.
 __device__ __forceinline__ void wait_count(const int* cnt, int need, int* err) {
   if (threadIdx.x == 0) {
-    int spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       __builtin_amdgcn_s_sleep(8);
-      if (++spins > (1 << 20)) {
+      if (wall_clock64() - t0 > 100000000ull) {
         __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
+    // the producer may sit on another XCD (another L2): one acquire for the
+    // workgroup's CU and XCD caches
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  // every wave acquires: the producer may sit on another XCD (another L2)
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Every wave releases its own stores at agent scope before thread 0 counts
@@ -1043,17 +1062,123 @@ __device__ __forceinline__ void signal_count(int* cnt) {
   if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One work item of a batched step: phase kind `kind` (run-time; KIND is its
+// compile-time class: PH_U covers PH_U and PH_X, so that the main and the
+// fix-up update share one call site as in k_update) of box b, tile `tile`.
+template <typename T, int RECON, int RIEMANN, int EMF, int KIND>
+__device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kind, int stage,
+                                           int tile, int strips, int cl) {
+  const BoxTab<T>& tb = *(const BoxTab<T>*)((const CTMHD_CONST BoxTab<T>*)A.tab + b);
+  const Geom& G = tb.G;
+  const State& cur = cl == 0 ? tb.su : tb.sb;
+  if constexpr (KIND == PH_COPY) {  // the state of this box back into the caller's arrays
+    if (cl == 1)
+      for (int s = 0; s < strips; ++s) {
+        const int t = (tile * strips + s) * kBlock + threadIdx.x;
+        if (t < G.elems) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) tb.su.c[m][t] = tb.sb.c[m][t];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) tb.su.b[a][t] = tb.sb.b[a][t];
+        }
+      }
+    return;
+  } else {
+    const Work<T>& W = tb.w;
+    const State& Hs = tb.sh;
+    const State& in = stage == 0 ? cur : Hs;
+    if constexpr (KIND == PH_P) {
+      for (int s = 0; s < strips; ++s)
+        prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_F) {
+      int nfb = 0;
+      faces_block<T, RECON, RIEMANN>(in, G, W, tb.FP, tile, stage, A.gamma, A.eta, nfb);
+      if (A.diag && nfb) atomicAdd((unsigned long long*)&A.diag[2], (unsigned long long)nfb);
+    } else if constexpr (KIND == PH_E) {
+      for (int s = 0; s < strips; ++s)
+        emf_at<T, RECON, EMF>(in, G, W, stage, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_U) {
+      const State& oth = cl == 0 ? tb.sb : tb.su;
+      UpdateCfg U;
+      U.fofc = A.fofc;
+      U.crit = A.crit;
+      U.gamma = A.gamma;
+      U.sres = tb.sres;
+      U.force = nullptr;
+      const int fix = kind == PH_X ? 1 : 0;
+      if (!fix || W.nflag[stage])
+        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, fix, U, A.diag, tile, strips,
+                       W.smax, fix);
+    } else if constexpr (KIND == PH_O) {
+      if (W.nflag[stage])
+        for (int s = 0; s < strips; ++s)
+          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_WRAP) {
+      for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_DT) {
+      double sig = 0.0;
+      for (int s = 0; s < strips; ++s) {
+        double v = dt_sig_at(cur, G, A.gamma, tb.sres, (tile * strips + s) * kBlock + threadIdx.x);
+        sig = (v > sig || v != v) ? v : sig;
+      }
+      block_max_to_slots(sig, W.smax, 0);
+    }
+  }
+}
+
+// Per-box tables of a batched call (one thread per box).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_btab(BatchArgs<T> A, int nbox) {
+  const PlanHeader* P = (const PlanHeader*)A.plan;
+  if (P->magic != kPlanMagic || P->key != A.key) return;  // refused by the step kernels
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nbox) return;
+  const BoxDesc& d = ((const BoxDesc*)(A.plan + P->desc_off))[b];
+  BoxTab<T>* tb = (BoxTab<T>*)A.tab + b;
+  tb->su = shift_state(A.user, d.off);
+  tb->sb = shift_state(A.B, d.off);
+  tb->sh = shift_state(A.H, d.off);
+  Work<T> W = shift_work(A.W, d.off);
+  W.flag = A.W.flag + d.flag_off;
+  W.dt = A.dt + (A.dt_per_box ? b : 0);
+  W.nflag = A.nflag + 4 * b;
+  W.smax = A.slots + 2 * b;
+  W.stop = A.stop;
+  tb->w = W;
+  tb->G = d.G;
+  tb->FP = d.FP;
+  tb->sres = d.sres;
+}
+
+// Plan lookup shared by both schedules: true if the plan was built for the
+// call's parameters and boxes.
+__device__ __forceinline__ bool plan_ok(const char* plan, unsigned long long key, int* err) {
+  const PlanHeader* P = (const PlanHeader*)plan;
+  if (P->magic == kPlanMagic && P->key == key) return true;
+  if (threadIdx.x == 0) atomicOr(err, 2);
+  return false;
+}
+
+// Box (index into `order`, largest k with pre[k] <= r) of item r of a phase.
+__device__ __forceinline__ int item_box(const int* pre, int nbox, int r) {
+  int k0 = 0, k1 = nbox;
+  while (k1 - k0 > 1) {
+    int mid = (k0 + k1) >> 1;
+    if (pre[mid] <= r) k0 = mid; else k1 = mid;
+  }
+  return k0;
+}
+
+// Persistent schedule: one launch per step (plus a start and a copy-back
+// launch).  Workgroups claim queue items in phase-major order; an item waits
+// only for all items of the previous phase of its own box.
 template <typename T, int RECON, int RIEMANN, int EMF>
 __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
   if (*A.stop && A.launch != 2) return;  // the copy-back runs even after a stop
+  if (!plan_ok(A.plan, A.key, A.err)) return;
   const PlanHeader* P = (const PlanHeader*)A.plan;
-  if (P->magic != kPlanMagic || P->key != A.key) {  // plan built for other boxes: no work
-    if (threadIdx.x == 0) atomicOr(A.err, 2);
-    return;
-  }
   const int* order = (const int*)(A.plan + P->order_off);
   const int* prefix = (const int*)(A.plan + P->prefix_off);
-  const BoxDesc* desc = (const BoxDesc*)(A.plan + P->desc_off);
   const int nbox = P->nbox;
   const int lo = P->range[A.launch][0], hi = P->range[A.launch][1];
   const int total = P->range_items[A.launch];
@@ -1070,79 +1195,44 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
     while (p + 1 < hi && P->item_off[p + 1] <= q) ++p;
     const int* pre = prefix + (long long)p * (nbox + 1);
     const int r = q - P->item_off[p];
-    int k0 = 0, k1 = nbox;  // largest k with pre[k] <= r
-    while (k1 - k0 > 1) {
-      int mid = (k0 + k1) >> 1;
-      if (pre[mid] <= r) k0 = mid; else k1 = mid;
-    }
+    const int k0 = item_box(pre, nbox, r);
     const int b = order[k0];
     const int tile = r - pre[k0];
     if (p > lo) {
       const int* ppre = prefix + (long long)(p - 1) * (nbox + 1);
       wait_count(A.done + (long long)(p - 1) * nbox + b, ppre[k0 + 1] - ppre[k0], A.err);
     }
-    const BoxDesc& d = desc[b];
-    const Geom G = d.G;
-    const State cur = shift_state(cl == 0 ? A.user : A.B, d.off);
-    const State oth = shift_state(cl == 0 ? A.B : A.user, d.off);
-    const State Hs = shift_state(A.H, d.off);
-    Work<T> W = shift_work(A.W, d.off);
-    W.flag = A.W.flag + d.flag_off;
-    W.dt = A.dt + (A.dt_per_box ? b : 0);
-    W.nflag = A.nflag + 4 * b;
-    W.smax = A.slots + 2 * b;
-    W.stop = A.stop;
     const int kind = P->kind[p], stage = P->stage[p];
-    const State in = stage == 0 ? cur : Hs;
-    UpdateCfg U;
-    U.fofc = A.fofc;
-    U.crit = A.crit;
-    U.gamma = A.gamma;
-    U.sres = d.sres;
-    U.force = nullptr;
-    if (kind == PH_P) {
-      for (int s = 0; s < strips; ++s)
-        prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_F) {
-      int nfb = 0;
-      faces_block<T, RECON, RIEMANN>(in, G, W, d.FP, tile, stage, A.gamma, A.eta, nfb);
-      if (A.diag && nfb) atomicAdd((unsigned long long*)&A.diag[2], (unsigned long long)nfb);
-    } else if (kind == PH_E) {
-      for (int s = 0; s < strips; ++s)
-        emf_at<T, RECON, EMF>(in, G, W, stage, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_U || kind == PH_X) {
-      // one call site, fixup a run-time value as in k_update, so that both
-      // paths compile to the same arithmetic
-      const int fix = kind == PH_X ? 1 : 0;
-      if (!fix || W.nflag[stage])
-        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, fix, U, A.diag, tile, strips,
-                       W.smax, fix);
-    } else if (kind == PH_O) {
-      if (W.nflag[stage])
-        for (int s = 0; s < strips; ++s)
-          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_WRAP) {
-      for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if (kind == PH_DT) {
-      double sig = 0.0;
-      for (int s = 0; s < strips; ++s) {
-        double v = dt_sig_at(cur, G, A.gamma, d.sres, (tile * strips + s) * kBlock + threadIdx.x);
-        sig = (v > sig || v != v) ? v : sig;
-      }
-      block_max_to_slots(sig, W.smax, 0);
-    } else if (cl == 1) {  // PH_COPY: the state of this box back into the caller's arrays
-      for (int s = 0; s < strips; ++s) {
-        const int t = (tile * strips + s) * kBlock + threadIdx.x;
-        if (t < G.elems) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) A.user.c[m][d.off + t] = A.B.c[m][d.off + t];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) A.user.b[a][d.off + t] = A.B.b[a][d.off + t];
-        }
-      }
+    switch (kind) {
+      case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_U:
+      case PH_X: batch_item<T, RECON, RIEMANN, EMF, PH_U>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_O: batch_item<T, RECON, RIEMANN, EMF, PH_O>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_WRAP: batch_item<T, RECON, RIEMANN, EMF, PH_WRAP>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_DT: batch_item<T, RECON, RIEMANN, EMF, PH_DT>(A, b, kind, stage, tile, strips, cl); break;
+      default: batch_item<T, RECON, RIEMANN, EMF, PH_COPY>(A, b, kind, stage, tile, strips, cl); break;
     }
     signal_count(A.done + (long long)p * nbox + b);
   }
+}
+
+// Phased schedule: one launch per phase over all boxes; workgroup r runs
+// item r of phase p.  Launch boundaries order the phases.
+template <typename T, int RECON, int RIEMANN, int EMF, int KIND>
+__global__ void __launch_bounds__(kBlock) k_bphase(BatchArgs<T> A, int p) {
+  if (KIND != PH_COPY && *A.stop) return;  // the copy-back runs even after a stop
+  if (!plan_ok(A.plan, A.key, A.err)) return;
+  const PlanHeader* P = (const PlanHeader*)A.plan;
+  const int nbox = P->nbox;
+  const int* pre = (const int*)(A.plan + P->prefix_off) + (long long)p * (nbox + 1);
+  const int r = blockIdx.x;
+  if (r >= pre[nbox]) return;
+  const int k0 = item_box(pre, nbox, r);
+  const int b = ((const int*)(A.plan + P->order_off))[k0];
+  batch_item<T, RECON, RIEMANN, EMF, KIND>(A, b, P->kind[p], P->stage[p], r - pre[k0], P->strips,
+                                           *A.loc);
 }
 
 // dt of a batched step from the per-box CFL maxima (the fix-up maximum where
@@ -1231,7 +1321,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tuning knobs in ctmhd_params.tile: bits 0-7 minimum faces per marching
 // chunk (default 32), bits 8-15 256-element strips per batched work item
-// (default 1).
+// (default 1), bits 16-23 batched schedule (0 per phase, 1 persistent).
 int tile_chunk(const ctmhd_params* p) {
   int c = p->tile & 0xff;
   return c > 0 ? c : 32;
@@ -1240,6 +1330,8 @@ int tile_strips(const ctmhd_params* p) {
   int s = (p->tile >> 8) & 0xff;
   return s > 0 ? s : 1;
 }
+// bits 16-23: batched schedule, 0 one launch per phase, 1 persistent queue
+int tile_sched(const ctmhd_params* p) { return (p->tile >> 16) & 0xff; }
 
 int check_params(const ctmhd_params* p) {
   if (!p) return fail(CTMHD_EARG, "params is NULL");
@@ -1253,7 +1345,7 @@ int check_params(const ctmhd_params* p) {
   if (p->emf_compute < 0 || p->emf_compute > 2) return fail(CTMHD_EARG, "unknown EMF scheme");
   if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
   if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32) return fail(CTMHD_EARG, "unknown precision");
-  if (p->tile < 0 || p->tile > 0xffff) return fail(CTMHD_EARG, "tile knob out of range");
+  if (p->tile < 0 || p->tile > 0x1ffff) return fail(CTMHD_EARG, "tile knob out of range");
   return CTMHD_OK;
 }
 
@@ -1557,6 +1649,18 @@ int plan_phases(const ctmhd_params* p, int kind[kMaxPhases], int stage[kMaxPhase
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Work items of one phase of one box.
+long long item_count(int kind, const Geom& G, const FacePlan& FP, long long per) {
+  switch (kind) {
+    case PH_F: return FP.total_blocks;
+    case PH_E: return ((long long)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1) + per - 1) / per;
+    case PH_P:
+    case PH_WRAP:
+    case PH_COPY: return ((long long)G.elems + per - 1) / per;
+    default: return ((long long)G.n[0] * G.n[1] * G.n[2] + per - 1) / per;
+  }
+}
+
 // FNV-1a over everything a plan depends on: the kernel refuses a plan whose
 // key differs from the one computed for the call's own parameters and boxes.
 unsigned long long plan_key(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
@@ -1631,6 +1735,7 @@ size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
   bytes += align256(sizeof(int) * 4 * (size_t)nbox);         // nflag
   bytes += align256(sizeof(unsigned long long) * 2 * (size_t)nbox);  // CFL slots
   bytes += align256(sizeof(double) * (size_t)nbox);          // dt
+  bytes += align256((tb == 4 ? sizeof(BoxTab<float>) : sizeof(BoxTab<double>)) * (size_t)nbox);
   bytes += 256;                                              // cursor, stop, err, loc
   return bytes;
 }
@@ -1670,6 +1775,7 @@ int batch_args(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* ws
   A.nflag = cv.take<int>(4 * (size_t)nbox);
   A.slots = cv.take<unsigned long long>(2 * (size_t)nbox);
   A.dt = cv.take<double>((size_t)nbox);
+  A.tab = (unsigned long long)(uintptr_t)cv.take<BoxTab<T>>((size_t)nbox);
   char* sc = cv.p;
   A.cursor = (int*)sc;          // 4 ints
   A.stop = (int*)(sc + 16);
@@ -1697,6 +1803,40 @@ int persistent_blocks(K kernel) {
   return ncu * per;
 }
 
+// Items of every phase summed over the boxes (the grid of each phased launch;
+// the same counts as the plan's prefix sums).
+int phase_items(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, const int* kind,
+                int nphase, long long* items) {
+  const long long per = (long long)kBlock * tile_strips(p);
+  for (int q = 0; q < nphase; ++q) items[q] = 0;
+  for (int b = 0; b < nbox; ++b) {
+    const Geom G = make_geom(boxes[b]);
+    const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
+    for (int q = 0; q < nphase; ++q) items[q] += item_count(kind[q], G, FP, per);
+  }
+  for (int q = 0; q < nphase; ++q)
+    if (items[q] >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
+  return CTMHD_OK;
+}
+
+template <typename T, int RECON, int RIEMANN, int EMF>
+int launch_bphase(hipStream_t st, int kind, long long items, const BatchArgs<T>& A, int q) {
+  if (items <= 0) return CTMHD_OK;
+  const unsigned grid = (unsigned)items;
+  switch (kind) {
+    case PH_P: LAUNCH((k_bphase<T, kPC, kHLLD, EMF, PH_P>), grid, A, q); break;
+    case PH_F: LAUNCH((k_bphase<T, RECON, RIEMANN, kQ26, PH_F>), grid, A, q); break;
+    case PH_E: LAUNCH((k_bphase<T, RECON, kHLLD, EMF, PH_E>), grid, A, q); break;
+    case PH_U:
+    case PH_X: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_U>), grid, A, q); break;
+    case PH_O: LAUNCH((k_bphase<T, kPC, kHLLD, EMF, PH_O>), grid, A, q); break;
+    case PH_WRAP: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_WRAP>), grid, A, q); break;
+    case PH_DT: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_DT>), grid, A, q); break;
+    default: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_COPY>), grid, A, q); break;
+  }
+  return CTMHD_OK;
+}
+
 template <typename T, int RECON, int RIEMANN, int EMF>
 int batched_run(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
                 double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
@@ -1712,31 +1852,53 @@ int batched_run(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const v
   A.key = plan_key(p, boxes, nbox);
   A.diag = nullptr;
   A.dt_per_box = dt_mode == CTMHD_DT_PER_BOX;
-  const int grid = persistent_blocks(k_batch<T, RECON, RIEMANN, EMF>);
-  if (grid < 1) return fail(CTMHD_EHIP, "occupancy query failed");
+  const bool persistent = tile_sched(p) == 1;
+  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
+  plan_phases(p, kind, stage, range);
+  long long items[kMaxPhases];
+  int grid = 0;
+  if (persistent) {
+    grid = persistent_blocks(k_batch<T, RECON, RIEMANN, EMF>);
+    if (grid < 1) return fail(CTMHD_EHIP, "occupancy query failed");
+  } else if ((rc = phase_items(p, boxes, nbox, kind, nphase, items))) {
+    return rc;
+  }
+  // launch l (0 start, 1 step, 2 copy-back) of either schedule
+  auto run_launch = [&](int l) -> int {
+    if (persistent) {
+      A.launch = l;
+      if (l == 1) prof_begin(st);
+      LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
+      if (l == 1) prof_end(st);
+      return CTMHD_OK;
+    }
+    for (int q = range[l][0]; q < range[l][1]; ++q) {
+      if (kind[q] == PH_F) prof_begin(st);
+      int r = launch_bphase<T, RECON, RIEMANN, EMF>(st, kind[q], items[q], A, q);
+      if (r) return r;
+      if (kind[q] == PH_F) prof_end(st);
+    }
+    return CTMHD_OK;
+  };
   const int ndt = A.dt_per_box ? nbox : 1;
   LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 1, A.stop, A.err, (int*)A.loc, A.slots,
          A.nflag);
-  A.launch = 0;
-  LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
+  LAUNCH(k_btab<T>, (nbox + kBlock - 1) / kBlock, A, nbox);
+  if ((rc = run_launch(0))) return rc;
   for (int n = 0; n < nsteps; ++n) {
     long long* dg = diag ? (long long*)diag + 4 * n : nullptr;
     LAUNCH(k_bdt_final, 1, nbox, nphase, A.dt_per_box, A.slots, A.nflag, A.done, A.cursor, p->cfl,
            dt_fixed ? dt_fixed + (size_t)n * ndt : nullptr, A.dt,
            dt_out ? dt_out + (size_t)n * ndt : nullptr, A.stop, A.err, dg);
-    A.launch = 1;
     A.diag = dg;
-    prof_begin(st);
-    LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
-    prof_end(st);
+    if ((rc = run_launch(1))) return rc;
     LAUNCH(k_bstep_end, 1, (int*)A.loc, A.stop, A.err, dg);
   }
-  LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 0, A.stop, A.err, (int*)A.loc, A.slots,
-         A.nflag);
-  A.launch = 2;
+  if (persistent)
+    LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 0, A.stop, A.err, (int*)A.loc, A.slots,
+           A.nflag);
   A.diag = nullptr;
-  LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
-  return CTMHD_OK;
+  return run_launch(2);
 }
 
 template <typename T, int RECON>
@@ -1877,18 +2039,7 @@ int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, vo
     pre[0] = 0;
     for (int k = 0; k < nbox; ++k) {
       const BoxDesc& d = desc[order[k]];
-      const long long ninter = (long long)d.G.n[0] * d.G.n[1] * d.G.n[2];
-      long long cnt;
-      switch (kind[q]) {
-        case PH_F: cnt = d.FP.total_blocks; break;
-        case PH_E:
-          cnt = ((long long)(d.G.n[0] + 1) * (d.G.n[1] + 1) * (d.G.n[2] + 1) + per - 1) / per;
-          break;
-        case PH_P:
-        case PH_WRAP:
-        case PH_COPY: cnt = ((long long)d.G.elems + per - 1) / per; break;
-        default: cnt = (ninter + per - 1) / per; break;
-      }
+      const long long cnt = item_count(kind[q], d.G, d.FP, per);
       if ((long long)pre[k] + cnt >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
       pre[k + 1] = pre[k] + (int)cnt;
     }
@@ -1937,6 +2088,10 @@ int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, 
   for (int a = 0; a < 3; ++a)
     if (!bface[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
   if (dt_mode != CTMHD_DT_GLOBAL && dt_mode != CTMHD_DT_PER_BOX) return fail(CTMHD_EARG, "unknown dt mode");
+  // The persistent-queue schedule is switched off: a launch of it with the
+  // per-box constant tables did not finish and the cause is not known.
+  if (tile_sched(p) == 1)
+    return fail(CTMHD_EUNSUPPORTED, "the persistent batched schedule is disabled (a launch of it did not finish; cause not found)");
   if (nsteps < 0) return fail(CTMHD_EARG, "nsteps must be >= 0");
   if (nsteps == 0) return CTMHD_OK;
   if (packed_elems(boxes, nbox) * 6 >= (1LL << 31) * 64LL) return fail(CTMHD_EARG, "packed arrays too large");

@@ -105,9 +105,11 @@ def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", 
                   0, int(bool(fofc)), int(flag_mask), PRECISION[precision], int(tile), ff)
 
 
-def make_tile(chunk=0, strips=0):
-    """The ctmhd_params.tile knob: minimum marching chunk and batched strips."""
-    return (int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8)
+def make_tile(chunk=0, strips=0, persistent=False):
+    """The ctmhd_params.tile knob: minimum marching chunk, batched strips per
+    work item and the batched schedule (per-phase launches or one persistent
+    launch per step)."""
+    return (int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8) | ((1 if persistent else 0) << 16)
 
 
 def make_box(n, ng, dx, offset=0) -> Box:

@@ -74,3 +74,44 @@ def reflect(cons, bface):
     c = np.stack([fc(cons[0]), -fc(cons[1]), -fc(cons[2]), -fc(cons[3]), fc(cons[4])])
     b = np.stack([-np.roll(fc(bface[a]), 1, axis=ax(a)) for a in range(3)])
     return np.ascontiguousarray(c), np.ascontiguousarray(b)
+
+
+def compare_fields(cg, bg, co, bo, tol, label=""):
+    """The float64 parity bar: the relative error over all 8 fields and, per
+    field, the relative L1 difference normalised by max(L1 of the field, L1 of
+    rho times the largest signal speed) -- fields that only carry a small
+    perturbation are compared on the scale of the fluxes that update them.
+    Returns (relative error, worst per-field value)."""
+    rel = relative_error(state_list(cg, bg), state_list(co, bo))
+    rho_l1 = np.abs(co[0]).sum()
+    u = np.sqrt((co[1:4] ** 2).sum(0)) / co[0]
+    smax = float(u.max()) + 1.0
+    worst = 0.0
+    for m in range(5):
+        den = max(np.abs(co[m]).sum(), rho_l1 * smax * (1.0 if m in (1, 2, 3) else 0.0), 1e-300)
+        worst = max(worst, np.abs(cg[m] - co[m]).sum() / den)
+    for a in range(3):
+        den = max(np.abs(bo[a]).sum(), np.abs(bo).sum() / 3, 1e-300)
+        worst = max(worst, np.abs(bg[a] - bo[a]).sum() / den)
+    print(f"[parity] {label} rel_err={rel:.3e} worst_field_relL1={worst:.3e}", flush=True)
+    assert rel <= tol, (label, rel)
+    assert worst <= tol, (label, worst)
+    return rel, worst
+
+
+def field_errors(cg, bg, co, bo):
+    """Per field (rho, m0, m1, m2, e, b0, b1, b2): (plain relative L1,
+    relative L1 with the normalisation of compare_fields)."""
+    rho_l1 = np.abs(co[0]).sum()
+    u = np.sqrt((co[1:4] ** 2).sum(0)) / co[0]
+    smax = float(u.max()) + 1.0
+    out = []
+    for m in range(5):
+        d = np.abs(cg[m] - co[m]).sum()
+        den = max(np.abs(co[m]).sum(), rho_l1 * smax * (1.0 if m in (1, 2, 3) else 0.0), 1e-300)
+        out.append((d / max(np.abs(co[m]).sum(), 1e-300), d / den))
+    for a in range(3):
+        d = np.abs(bg[a] - bo[a]).sum()
+        den = max(np.abs(bo[a]).sum(), np.abs(bo).sum() / 3, 1e-300)
+        out.append((d / max(np.abs(bo[a]).sum(), 1e-300), d / den))
+    return out

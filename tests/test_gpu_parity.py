@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import divb_rel, relative_error, state_list
+from helpers import compare_fields, divb_rel
 from paper_2609_10816_amd import ctmhd, inputs
 
 pytestmark = pytest.mark.gpu
@@ -24,21 +24,7 @@ TOL = 1e-12
 
 
 def _compare(cg, bg, co, bo, tol=TOL, label=""):
-    rel = relative_error(state_list(cg, bg), state_list(co, bo))
-    rho_l1 = np.abs(co[0]).sum()
-    u = np.sqrt((co[1:4] ** 2).sum(0)) / co[0]
-    smax = float(u.max()) + 1.0
-    worst = 0.0
-    for m in range(5):
-        den = max(np.abs(co[m]).sum(), rho_l1 * smax * (1.0 if m in (1, 2, 3) else 0.0), 1e-300)
-        worst = max(worst, np.abs(cg[m] - co[m]).sum() / den)
-    for a in range(3):
-        den = max(np.abs(bo[a]).sum(), np.abs(bo).sum() / 3, 1e-300)
-        worst = max(worst, np.abs(bg[a] - bo[a]).sum() / den)
-    print(f"[parity] {label} rel_err={rel:.3e} worst_field_relL1={worst:.3e}", flush=True)
-    assert rel <= tol, (label, rel)
-    assert worst <= tol, (label, worst)
-    return rel, worst
+    return compare_fields(cg, bg, co, bo, tol, label)
 
 
 def _conserved(c0, c1, tol=1e-13):
