@@ -14,8 +14,8 @@ default workload (the 128^3 Mach-5 turbulent box, PPM + HLLD + Q26 + LD04).
 roofline: the dominant kernel is the face kernel (reconstruction + HLLD at
 every x_a face of one stage).  Its algorithmic work is face_flops (from
 tests/golden/flops_per_unit.json, the oracle's operation count with each
-reconstruction charged once) times the n^3 interior faces one launch
-resolves; its duration is measured with HIP events recorded by the library
+reconstruction charged once) times the 3 n^3 interior faces (all three
+directions) one launch resolves; its duration is measured with HIP events recorded by the library
 around every launch inside the timed region.  The path is bound by FP64
 vector ALU throughput (peak 78.6 TFLOP/s on MI355X), not by HBM.
 traffic: HBM bytes per launch from the committed rocprofv3 counter summary
@@ -54,14 +54,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# the files the face kernel is compiled from
+FACE_KERNEL_SOURCES = ("ctmhd.hip", "ctmhd_device.h", "ctmhd_host.h", "ctmhd_math.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2609_10816_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in FACE_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -110,7 +110,9 @@ int ctmhd_required_ghosts(const ctmhd_params* p);
 /* Elements (not bytes) of one field array of a box: prod(n_d + 2 ng). */
 int64_t ctmhd_box_elems(const ctmhd_box* box);
 
-/* Workspace bytes for ctmhd_step (nbox = 1) or ctmhd_step_batched (nbox > 1). */
+/* Workspace bytes (device memory, 256-byte aligned, owned by the caller) for
+ * ctmhd_step or ctmhd_step_batched on these boxes; with nbox = 1 the size
+ * serves either entry point.  0 for bad arguments. */
 size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox);
 
 /* Advance one box by `nsteps` RK2 steps (Sec. 2.5).

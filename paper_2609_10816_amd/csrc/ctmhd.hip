@@ -20,1474 +20,14 @@
 //   k_update     again (fix-up mode), only when something was flagged
 // Face arrays hold the x_a face on the lower side of each cell, edge arrays
 // the edge at the lower corner in the two transverse directions.
-#include <hip/hip_runtime.h>
+#include "ctmhd_host.h"
 
-#include <cstdint>
-#include <cstdio>
-#include <cstring>
-
-#include "ctmhd.h"
-#include "ctmhd_math.h"
-
-using namespace ctmhd;
-
-namespace {
-
-// ---------------------------------------------------------------------------
-// Geometry of one ghosted box.
-// ---------------------------------------------------------------------------
-struct Geom {
-  int n[3];    // interior cells
-  int g;       // ghost layers
-  int N[3];    // n + 2g
-  int st[3];   // strides: 1, N0, N0*N1
-  int elems;   // N0*N1*N2
-  double dx[3];
-  double idx[3];
-};
-
-Geom make_geom(const ctmhd_box& b) {
-  Geom G;
-  for (int d = 0; d < 3; ++d) {
-    G.n[d] = b.n[d];
-    G.N[d] = b.n[d] + 2 * b.ng;
-    G.dx[d] = b.dx[d];
-    G.idx[d] = 1.0 / b.dx[d];
-  }
-  G.g = b.ng;
-  G.st[0] = 1;
-  G.st[1] = G.N[0];
-  G.st[2] = G.N[0] * G.N[1];
-  G.elems = G.N[0] * G.N[1] * G.N[2];
-  return G;
-}
-
-__device__ __forceinline__ int gidx() { return blockIdx.x * blockDim.x + threadIdx.x; }
-
-struct State {
-  double* c[5];
-  double* b[3];
-};
-
-constexpr int kBlock = 256;
-constexpr int kMaxSlots = 64;  // spread of the CFL maximum over atomics
-
-template <typename T>
-struct Work {
-  T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2 (B25a / FS18 only)
-  T* ecell[3];      // cell-centred ideal EMF (B25a)
-  T* F[2][3][5];    // per stage, direction, component (global momentum order)
-  T* ap[3];
-  T* am[3];
-  T* us[3];
-  T* E[2][3];       // per stage, edge EMFs
-  uint8_t* flag;    // interior cells
-  // CFL maxima (bits of non-negative doubles), kMaxSlots each: [0] fused into
-  // the stage-2 update, [1] recomputed by a stage-2 fix-up
-  unsigned long long* smax;
-  double* dt;       // the step's dt
-  int* stop;        // 1 once a non-finite dt was seen
-  int* nflag;       // flagged cells of stage 0 / 1; nflag[2]: stage-2 fix-up ran
-};
-
-inline int nblocks(long long n) { return (int)((n + kBlock - 1) / kBlock); }
-
-// ---------------------------------------------------------------------------
-// Small kernels
-// ---------------------------------------------------------------------------
-__global__ void k_init(int* stop, unsigned long long* smax, int* nflag) {
-  int t = threadIdx.x;
-  if (blockIdx.x != 0) return;
-  if (t == 0) {
-    *stop = 0;
-    nflag[0] = nflag[1] = nflag[2] = 0;
-  }
-  if (t < 2 * kMaxSlots) smax[t] = 0ull;
-}
-
-__device__ __forceinline__ int pwrap(int s, int g, int n) {
-  int q = (s - g) % n;
-  if (q < 0) q += n;
-  return q + g;
-}
-
-// Periodic ghost fill of all 8 fields (faces follow the same rule: the face at
-// storage index s is the lower face of cell s).  Used on the caller's state at
-// the start of a call; later states get their ghost images from k_update.
-__device__ __forceinline__ void wrap_at(const State& S, const Geom& G, int t) {
-  if (t >= G.elems) return;
-  int i = t % G.N[0];
-  int q = t / G.N[0];
-  int j = q % G.N[1];
-  int k = q / G.N[1];
-  bool inter = i >= G.g && i < G.g + G.n[0] && j >= G.g && j < G.g + G.n[1] && k >= G.g &&
-               k < G.g + G.n[2];
-  if (inter) return;
-  int src = pwrap(i, G.g, G.n[0]) + G.st[1] * pwrap(j, G.g, G.n[1]) + G.st[2] * pwrap(k, G.g, G.n[2]);
-#pragma unroll
-  for (int m = 0; m < 5; ++m) S.c[m][t] = S.c[m][src];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) S.b[a][t] = S.b[a][src];
-}
-
-__global__ void k_wrap(State S, Geom G, const int* stop) {
-  if (*stop) return;
-  wrap_at(S, G, gidx());
-}
-
-__global__ void k_copy(State dst, State src, int elems, const int* only_if_stop) {
-  if (only_if_stop && !*only_if_stop) return;
-  int t = gidx();
-  if (t >= elems) return;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) dst.c[m][t] = src.c[m][t];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) dst.b[a][t] = src.b[a][t];
-}
-
-// ---------------------------------------------------------------------------
-// Cell primitives from the conserved state (eq. state:primitive), FP64.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void cell_prim(const State& S, const Geom& G, int s, double gamma,
-                                          double& rho, double u[3], double& p, double bc[3]) {
-  rho = S.c[0][s];
-  double ir = 1.0 / rho;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    u[d] = S.c[1 + d][s] * ir;
-    bc[d] = 0.5 * (S.b[d][s] + S.b[d][s + G.st[d]]);
-  }
-  p = (gamma - 1.0) * (S.c[4][s] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
-                       0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
-}
-
-// CFL signal speed of one cell (eq. resistivity:cfl; the resistive term
-// enters as the speed 2 eta / dx_min, i.e. 2 eta / dx_min^2 per unit length).
-// NaN propagates.
-__device__ __forceinline__ double cfl_signal(double rho, const double u[3], double p,
-                                             const double bc[3], const Geom& G, double gamma,
-                                             double sres) {
-  double s = sres;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double cf = fast_speed<double>(rho, p, bc[d], bc[(d + 1) % 3], bc[(d + 2) % 3], gamma);
-    double sd = (fabs(u[d]) + cf) * G.idx[d];
-    s = (sd > s || sd != sd) ? sd : s;
-  }
-  return s;
-}
-
-// Block maximum of a non-negative (or NaN) double, folded into one of
-// kMaxSlots device slots by an atomic max on its bit pattern (a NaN has
-// larger bits than +inf as an unsigned integer).  All threads must call.
-__device__ __forceinline__ void block_max_to_slots(double s, unsigned long long* slots, int slot) {
-  __shared__ unsigned long long red[kBlock / 64];
-  unsigned long long bits = (unsigned long long)__double_as_longlong(s);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long ob = __shfl_xor(bits, o, 64);
-    bits = ob > bits ? ob : bits;
-  }
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = bits;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long m = 0;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = red[q] > m ? red[q] : m;
-    atomicMax(&slots[slot], m);
-  }
-}
-
-// CFL signal of interior cell t (0 for t outside the box).
-__device__ __forceinline__ double dt_sig_at(const State& S, const Geom& G, double gamma,
-                                            double sres, int t) {
-  int ninter = G.n[0] * G.n[1] * G.n[2];
-  if (t >= ninter) return 0.0;
-  int i = t % G.n[0] + G.g;
-  int q = t / G.n[0];
-  int j = q % G.n[1] + G.g;
-  int k = q / G.n[1] + G.g;
-  int c = i + G.st[1] * j + G.st[2] * k;
-  double rho, u[3], p, bc[3];
-  cell_prim(S, G, c, gamma, rho, u, p, bc);
-  return cfl_signal(rho, u, p, bc, G, gamma, sres);
-}
-
-// CFL maximum of a whole state (start of a call).
-__global__ void __launch_bounds__(kBlock) k_dt(State S, Geom G, double gamma, double sres,
-                                               unsigned long long* slots, const int* stop) {
-  if (*stop) return;
-  int ninter = G.n[0] * G.n[1] * G.n[2];
-  double s = 0.0;
-  for (int t = gidx(); t < ninter; t += gridDim.x * blockDim.x) {
-    double v = dt_sig_at(S, G, gamma, sres, t);
-    s = (v > s || v != v) ? v : s;
-  }
-  block_max_to_slots(s, slots, blockIdx.x % kMaxSlots);
-}
-
-// dt of a step.  smax[0..kMaxSlots) holds the CFL maximum of the step's
-// starting state unless the previous step's second stage was fixed up
-// (nflag[2]), whose recomputed maximum is in smax[kMaxSlots..).  Resets the
-// slots, the flag counters and this step's diagnostics.
-__global__ void k_dt_final(unsigned long long* smax, int* nflag, double cfl,
-                           const double* dt_fixed, double* dt, double* dt_out, int* stop,
-                           long long* diag) {
-  int t = threadIdx.x;
-  __shared__ unsigned long long m;
-  if (t == 0) {
-    const unsigned long long* src = nflag[2] ? smax + kMaxSlots : smax;
-    unsigned long long v = 0;
-    for (int q = 0; q < kMaxSlots; ++q) v = src[q] > v ? src[q] : v;
-    m = v;
-  }
-  __syncthreads();
-  if (t < 2 * kMaxSlots) smax[t] = 0ull;
-  if (t != 0) return;
-  nflag[0] = nflag[1] = nflag[2] = 0;
-  if (diag) {
-    diag[0] = diag[1] = diag[2] = 0;
-    diag[3] = *stop ? 1 : 0;
-  }
-  if (*stop) {
-    *dt = 0.0;
-    if (dt_out) *dt_out = 0.0;
-    return;
-  }
-  double v = dt_fixed ? *dt_fixed : cfl / __longlong_as_double((long long)m);
-  if (!(v > 0.0) || !__builtin_isfinite(v)) {
-    *stop = 1;
-    if (diag) diag[3] = 1;
-  }
-  *dt = v;
-  if (dt_out) *dt_out = v;
-}
-
-// ---------------------------------------------------------------------------
-// Cell-centred fields for the two-step EMF schemes (B25a: ideal EMF; FS18:
-// velocity), over cells whose upper faces are stored.
-// ---------------------------------------------------------------------------
-template <typename T, int EMF>
-__device__ __forceinline__ void prim_at(const State& S, const Geom& G, const Work<T>& W,
-                                        double gamma, int t) {
-  if (t >= G.elems) return;
-  int i = t % G.N[0];
-  int q = t / G.N[0];
-  int j = q % G.N[1];
-  int k = q / G.N[1];
-  if (i >= G.N[0] - 1 || j >= G.N[1] - 1 || k >= G.N[2] - 1) return;
-  double rho, u[3], p, b[3];
-  cell_prim(S, G, t, gamma, rho, u, p, b);
-  if (EMF == kB25A) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      int a = (c + 1) % 3, bb = (c + 2) % 3;
-      // eq. emf:b25a-emf-centre in the stencil type
-      W.ecell[c][t] = -(T)u[a] * (T)b[bb] + (T)u[bb] * (T)b[a];
-    }
-  } else {
-    W.prim[1][t] = (T)u[0];
-    W.prim[2][t] = (T)u[1];
-    W.prim[3][t] = (T)u[2];
-  }
-}
-
-template <typename T, int EMF>
-__global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, double gamma,
-                                                 const int* stop) {
-  if (*stop) return;
-  prim_at<T, EMF>(S, G, W, gamma, gidx());
-}
-
-// eta j_c at the edge stored at s (lower corner in a and b), eq.
-// resistivity:current-stencil.
-template <typename T>
-__device__ __forceinline__ T eta_j(const State& S, const Geom& G, int s, int c, T eta) {
-  int a = (c + 1) % 3, b = (c + 2) % 3;
-  double j = (S.b[b][s] - S.b[b][s - G.st[a]]) * G.idx[a] - (S.b[a][s] - S.b[a][s - G.st[b]]) * G.idx[b];
-  return eta * (T)j;
-}
-
-// Joule energy flux at the x_a face stored at s (Sec. 2.4): (eta j x b).n_a
-// with eta j averaged over the face's bounding edges and b the mean of the two
-// adjacent cells' cell-averaged field.
-template <typename T>
-__device__ __forceinline__ T joule(const State& S, const Geom& G, int s, int a, T eta) {
-  int b = (a + 1) % 3, c = (a + 2) % 3;
-  T eb = T(0.5) * (eta_j<T>(S, G, s, b, eta) + eta_j<T>(S, G, s + G.st[c], b, eta));
-  T ec = T(0.5) * (eta_j<T>(S, G, s, c, eta) + eta_j<T>(S, G, s + G.st[b], c, eta));
-  int l = s - G.st[a];
-  T bbl = (T)(0.5 * (S.b[b][l] + S.b[b][l + G.st[b]]));
-  T bbr = (T)(0.5 * (S.b[b][s] + S.b[b][s + G.st[b]]));
-  T bcl = (T)(0.5 * (S.b[c][l] + S.b[c][l + G.st[c]]));
-  T bcr = (T)(0.5 * (S.b[c][s] + S.b[c][s + G.st[c]]));
-  return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
-}
-
-// ---------------------------------------------------------------------------
-// Face pass (Sec. 2.2, eqs. emf:alpha-pm, emf:q26-facevel).
-// ---------------------------------------------------------------------------
-// Face ranges of one stage.  Faces of direction a: s_a in [lo_a, lo_a +
-// nf_a), transverse coordinates in [tlo, tlo + tlen) on both axes.
-struct FacePlan {
-  int lo[3], nf[3];   // along the face normal
-  int tlo, tlen[3];   // transverse range start (same on every axis) and length per axis
-  int ulo[3], ulen[3];  // faces read by the update (Joule flux only there)
-  // x part: one wavefront per (row, segment)
-  int xseg, xnseg, xwaves, xblocks;
-  // y and z parts: lane blocks x chunks
-  int chunk[3], nchunk[3], lanes[3], lblocks[3], blocks[3];
-  int total_blocks;
-};
-
-// Face-local primitive of cell s for the face normal a (FP64 recovery, then T).
-template <typename T>
-__device__ __forceinline__ void face_local(const State& S, const Geom& G, int s, int a, double gamma,
-                                           T v[7]) {
-  double rho, u[3], p, bc[3];
-  cell_prim(S, G, s, gamma, rho, u, p, bc);
-  const int b = (a + 1) % 3, c = (a + 2) % 3;
-  v[0] = (T)rho;
-  v[1] = (T)u[a];
-  v[2] = (T)u[b];
-  v[3] = (T)u[c];
-  v[4] = (T)p;
-  v[5] = (T)bc[b];
-  v[6] = (T)bc[c];
-}
-
-template <typename T, int RIEMANN>
-__device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, const Work<T>& W,
-                                               const FacePlan& FP, int s, const int s3[3], int a,
-                                               int stage, const T qL[7], const T qR[7],
-                                               double gamma_d, double eta_d) {
-  const int b = (a + 1) % 3, c = (a + 2) % 3;
-  FState<T> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
-  FState<T> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
-  T bn = (T)S.b[a][s];
-  T F[5], ap, am;
-  int fb = 0;
-  if (RIEMANN == kHLLD) {
-    T SL, SR;
-    fb = hlld_flux(L, R, bn, (T)gamma_d, F, SL, SR);
-    ap = tmax(T(0), SR);
-    am = tmax(T(0), -SL);
-  } else {
-    ap = am = llf_flux(L, R, bn, (T)gamma_d, F);
-  }
-  if (eta_d > 0.0) {
-    // faces read by the update: [g, g+n] along the normal, [g, g+n) across
-    bool in_upd = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      in_upd = in_upd && s3[d] >= FP.ulo[d] && s3[d] < FP.ulo[d] + FP.ulen[d] + (d == a ? 1 : 0);
-    if (in_upd) F[4] += joule<T>(S, G, s, a, (T)eta_d);
-  }
-  W.F[stage][a][0][s] = F[0];
-  W.F[stage][a][1 + a][s] = F[1];
-  W.F[stage][a][1 + b][s] = F[2];
-  W.F[stage][a][1 + c][s] = F[3];
-  W.F[stage][a][4][s] = F[4];
-  W.ap[a][s] = ap;
-  W.am[a][s] = am;
-  W.us[a][s] = (ap * L.un + am * R.un) / (ap + am);
-  return fb;
-}
-
-template <typename T>
-__device__ __forceinline__ T lane_shfl(T v, int src) {
-  return __shfl(v, src, 64);
-}
-
-// x faces: one wavefront holds 64 consecutive cells of a row; lane l forms
-// the primitives, the limited slope and the upper interface value of its own
-// cell, neighbours come from cross-lane shuffles, and the face at lane l takes
-// the upper value of lane l-1.  Faces at lanes [r+1, 63-r] are resolved
-// (overlapping segments).
-template <int RECON, typename T>
-__device__ __forceinline__ void recon_lanes(T q, int lane, T& qm, T& qp) {
-  if constexpr (RECON == kPC) {
-    qm = q;
-    qp = q;
-  } else if constexpr (RECON == kPLM_MC || RECON == kPLM_MM) {
-    T s = T(0.5) * plm_slope<RECON>(lane_shfl(q, lane - 1), q, lane_shfl(q, lane + 1));
-    qm = q - s;
-    qp = q + s;
-  } else {
-    T qr = lane_shfl(q, lane + 1);
-    T dm = ppm_slope(lane_shfl(q, lane - 1), q, qr);
-    T ihi = ppm_iface(q, qr, dm, lane_shfl(dm, lane + 1));
-    T ilo = lane_shfl(ihi, lane - 1);
-    ppm_constrain(q, ilo, ihi);
-    qm = ilo;
-    qp = ihi;
-  }
-}
-
-template <typename T, int RECON, int RIEMANN>
-__device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const FacePlan& FP,
-                        int wave, int stage, double gamma, double eta, int& nfb) {
-  constexpr int r = recon_halfwidth(RECON);
-  const int lane = threadIdx.x & 63;
-  const int row = wave / FP.xnseg, seg = wave % FP.xnseg;
-  const int y = FP.tlo + row % FP.tlen[1];
-  const int z = FP.tlo + row / FP.tlen[1];
-  const int x = FP.lo[0] - (r + 1) + seg * FP.xseg + lane;
-  const int xc = x < 0 ? 0 : (x > G.N[0] - 2 ? G.N[0] - 2 : x);  // loads stay in the box
-  const int s = xc + G.st[1] * y + G.st[2] * z;
-  T v[7];
-  face_local<T>(S, G, s, 0, gamma, v);
-  T qm[7], qp[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], lane, qm[k], qp[k]);
-  T qL[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) qL[k] = lane_shfl(qp[k], lane - 1);
-  const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
-  if (face) {
-    const int s3[3] = {x, y, z};
-    nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, 0, stage, qL, qm, gamma, eta);
-  }
-}
-
-// y / z faces: lanes over the transverse plane (x fastest), each thread
-// marches along the face normal A through a chunk of faces, streaming the
-// cells through a reconstruction pipeline (one slope and one interface value
-// per cell); each cell is loaded and reconstructed once.
-template <typename T, int RECON, int RIEMANN, int A>
-__device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, const FacePlan& FP,
-                            int lblock, int chunk, int stage, double gamma, double eta, int& nfb) {
-  constexpr int r = recon_halfwidth(RECON);
-  const int lane = lblock * kBlock + threadIdx.x;
-  if (lane >= FP.lanes[A]) return;
-  const int C = A == 1 ? 2 : 1;  // transverse axes: x (fastest) and C
-  int s3[3];
-  s3[0] = FP.tlo + lane % FP.tlen[0];
-  s3[C] = FP.tlo + lane / FP.tlen[0];
-  const int f0 = FP.lo[A] + chunk * FP.chunk[A];
-  int f1 = f0 + FP.chunk[A];
-  if (f1 > FP.lo[A] + FP.nf[A]) f1 = FP.lo[A] + FP.nf[A];
-  const int sa = G.st[A];
-  const int base = s3[0] + G.st[C] * s3[C];
-  ReconStream<RECON, T> rs[7];
-  T qprev[7];
-  // warm-up: cells f0-1-r .. f0-2+r (outputs not yet complete)
-  for (int q = f0 - 1 - r; q < f0 - 1 + r; ++q) {
-    T v[7];
-    face_local<T>(S, G, base + q * sa, A, gamma, v);
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      T a0, a1;
-      rs[k].push(v[k], a0, a1);
-    }
-  }
-  for (int q = f0 - 1 + r; q <= f1 - 1 + r; ++q) {
-    T v[7];
-    face_local<T>(S, G, base + q * sa, A, gamma, v);
-    const int cell = q - r;  // completed by this push
-    T qm[7], qp[7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) rs[k].push(v[k], qm[k], qp[k]);
-    if (cell >= f0) {
-      s3[A] = cell;
-      const int s = base + cell * sa;
-      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, A, stage, qprev, qm, gamma, eta);
-    }
-#pragma unroll
-    for (int k = 0; k < 7; ++k) qprev[k] = qp[k];
-  }
-}
-
-// One virtual block (256 threads) of the face pass.
-template <typename T, int RECON, int RIEMANN>
-__device__ __forceinline__ void faces_block(const State& S, const Geom& G, const Work<T>& W,
-                                            const FacePlan& FP, int b, int stage, double gamma,
-                                            double eta, int& nfb) {
-  // long-running marching blocks first, the short x-face wavefronts fill in
-  if (b < FP.blocks[2]) {
-    faces_march<T, RECON, RIEMANN, 2>(S, G, W, FP, b / FP.nchunk[2], b % FP.nchunk[2], stage,
-                                      gamma, eta, nfb);
-  } else if ((b -= FP.blocks[2]) < FP.blocks[1]) {
-    faces_march<T, RECON, RIEMANN, 1>(S, G, W, FP, b / FP.nchunk[1], b % FP.nchunk[1], stage,
-                                      gamma, eta, nfb);
-  } else {
-    b -= FP.blocks[1];
-    const int wave = b * (kBlock / 64) + (threadIdx.x >> 6);
-    if (wave < FP.xwaves) faces_x<T, RECON, RIEMANN>(S, G, W, FP, wave, stage, gamma, eta, nfb);
-  }
-}
-
-template <typename T, int RECON, int RIEMANN>
-__global__ void __launch_bounds__(kBlock)
-    k_faces(State S, Geom G, Work<T> W, FacePlan FP, int stage, double gamma, double eta,
-            long long* diag, const int* stop) {
-  if (*stop) return;
-  int nfb = 0;
-  faces_block<T, RECON, RIEMANN>(S, G, W, FP, blockIdx.x, stage, gamma, eta, nfb);
-  if (diag && nfb) atomicAdd((unsigned long long*)&diag[2], (unsigned long long)nfb);
-}
-
-// ---------------------------------------------------------------------------
-// Edge pass (Sec. 2.3): face field reconstructed to the edge, four corner
-// EMFs of the chosen compute scheme, LD04 averaging, plus eta j.
-// ---------------------------------------------------------------------------
-template <int RECON, typename T>
-__device__ __forceinline__ void iface_along(const T* A, int s, int stride, T& lo, T& hi) {
-  T q[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) q[m] = stencil_uses<RECON>(m) ? A[s + (m - 3) * stride] : T(0);
-  recon_iface<RECON>(q, lo, hi);
-}
-
-template <int RECON, typename T>
-__device__ __forceinline__ void iface_along_d(const double* A, int s, int stride, T& lo, T& hi) {
-  T q[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) q[m] = stencil_uses<RECON>(m) ? (T)A[s + (m - 3) * stride] : T(0);
-  recon_iface<RECON>(q, lo, hi);
-}
-
-// Two-step reconstruction of a cell-centred field to the four corners of the
-// edge at s: first along d1 to the x_d1 face, then along d2 to the edge.
-// out[s1 + 2*s2] with s = 0 lower side, 1 upper side along each direction.
-template <int RECON, typename T>
-__device__ __forceinline__ void two_step(const T* A, int s, int st1, int st2, T out[4]) {
-  T seqlo[6], seqhi[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    if (!stencil_uses<RECON>(m)) {
-      seqlo[m] = seqhi[m] = T(0);
-    } else {
-      iface_along<RECON>(A, s + (m - 3) * st2, st1, seqlo[m], seqhi[m]);
-    }
-  }
-  T l0, l1, h0, h1;
-  recon_iface<RECON>(seqlo, l0, l1);
-  recon_iface<RECON>(seqhi, h0, h1);
-  out[0] = l0;  // (lower along d1, lower along d2)
-  out[1] = h0;  // (upper, lower)
-  out[2] = l1;  // (lower, upper)
-  out[3] = h1;  // (upper, upper)
-}
-
-template <typename T, int RECON, int EMF>
-__device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
-                                      double eta_d) {
-  const int a = (c + 1) % 3, b = (c + 2) % 3;
-  const int sa = G.st[a], sb = G.st[b];
-  T baB, baT, bbL, bbR;
-  iface_along_d<RECON>(S.b[a], s, sb, baB, baT);
-  iface_along_d<RECON>(S.b[b], s, sa, bbL, bbR);
-  T e[4];  // LB, RB, LT, RT
-  if (EMF == kQ26) {
-    T uaB, uaT, ubL, ubR;
-    iface_along<RECON>(W.us[a], s, sb, uaB, uaT);
-    iface_along<RECON>(W.us[b], s, sa, ubL, ubR);
-    e[0] = -uaB * bbL + ubL * baB;
-    e[1] = -uaB * bbR + ubR * baB;
-    e[2] = -uaT * bbL + ubL * baT;
-    e[3] = -uaT * bbR + ubR * baT;
-  } else if (EMF == kB25A) {
-    T ab[4], ba[4];
-    two_step<RECON>(W.ecell[c], s, sa, sb, ab);  // [x_a x_b]: index sa_side + 2 sb_side
-    two_step<RECON>(W.ecell[c], s, sb, sa, ba);  // [x_b x_a]: index sb_side + 2 sa_side
-    e[0] = T(0.5) * (ab[0] + ba[0]);
-    e[1] = T(0.5) * (ab[1] + ba[2]);
-    e[2] = T(0.5) * (ab[2] + ba[1]);
-    e[3] = T(0.5) * (ab[3] + ba[3]);
-  } else {
-    const T* ua = W.prim[1 + a];
-    const T* ub = W.prim[1 + b];
-    T ua_ab[4], ua_ba[4], ub_ab[4], ub_ba[4];
-    two_step<RECON>(ua, s, sa, sb, ua_ab);
-    two_step<RECON>(ua, s, sb, sa, ua_ba);
-    two_step<RECON>(ub, s, sa, sb, ub_ab);
-    two_step<RECON>(ub, s, sb, sa, ub_ba);
-    const int perm[4] = {0, 2, 1, 3};  // corner q = sa_side + 2 sb_side -> [x_b x_a] index
-    const T bbX[2] = {bbL, bbR}, baY[2] = {baB, baT};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      T u1 = T(0.5) * (ua_ab[q] + ua_ba[perm[q]]);
-      T u2 = T(0.5) * (ub_ab[q] + ub_ba[perm[q]]);
-      e[q] = -u1 * bbX[q & 1] + u2 * baY[q >> 1];
-    }
-  }
-  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
-  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
-  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
-  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
-  T eps = ld04(e[0], e[1], e[2], e[3], apa, ama, apb, amb, baB, baT, bbL, bbR);
-  if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
-  return eps;
-}
-
-// All three edge directions at the edge positions [g, g+n] on every axis
-// (an edge of direction c exists for s_c < g + n_c).
-template <typename T, int RECON, int EMF>
-__device__ __forceinline__ void emf_at(const State& S, const Geom& G, const Work<T>& W, int stage,
-                                       double eta_d, int t) {
-  const int L0 = G.n[0] + 1, L1 = G.n[1] + 1, L2 = G.n[2] + 1;
-  if (t >= L0 * L1 * L2) return;
-  int s3[3] = {G.g + t % L0, G.g + (t / L0) % L1, G.g + t / (L0 * L1)};
-  int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-    if (s3[c] < G.g + G.n[c]) W.E[stage][c][s] = edge_emf<T, RECON, EMF>(S, G, W, s, c, eta_d);
-}
-
-template <typename T, int RECON, int EMF>
-__global__ void __launch_bounds__(kBlock)
-    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
-  if (*stop) return;
-  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, gidx());
-}
-
-// ---------------------------------------------------------------------------
-// Update (eqs. rk:increment-state, rk:increment-bfield, rk1:update,
-// rk2:update).  stage 0: out = S^n + D^n.  stage 1: out = S^n + (D^n +
-// D^{n+1/2})/2.  Increments are formed in FP64 from the stored fluxes and
-// EMFs (which are single-valued per face and edge: conservation and div b
-// hold to FP64 round-off in both precision forms).
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ double dcons(const Geom& G, const Work<T>& W, int st, int s, int m,
-                                        double dt) {
-  double f = 0.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const T* Fa = W.F[st][a][m];
-    f += ((double)Fa[s] - (double)Fa[s + G.st[a]]) * G.idx[a];
-  }
-  return dt * f;
-}
-
-// increment of the face field b_a stored at s
-template <typename T>
-__device__ __forceinline__ double dface(const Geom& G, const Work<T>& W, int st, int s, int a,
-                                        double dt) {
-  const int b = (a + 1) % 3, c = (a + 2) % 3;
-  const T* Ec = W.E[st][c];
-  const T* Eb = W.E[st][b];
-  double circ = ((double)Ec[s] - (double)Ec[s + G.st[b]]) * G.idx[b] +
-                ((double)Eb[s + G.st[c]] - (double)Eb[s]) * G.idx[c];
-  return dt * circ;
-}
-
-// New face field.  stage 0: b^n + D^n.  stage 1, main pass: the SSP form
-// (b^n + b^{n+1/2} + D^{n+1/2}) / 2, which equals b^n + (D^n + D^{n+1/2}) / 2
-// up to round-off and does not re-read the first-stage EMFs; stage 1 after a
-// first-order replacement: b^n + (D^n + D^{n+1/2}) / 2 with the replaced
-// values of both stages.
-template <typename T>
-__device__ __forceinline__ double new_face(const State& base, const State& half, const Geom& G,
-                                           const Work<T>& W, int stage, int fixup, int s, int a,
-                                           double dt) {
-  if (stage == 0) return base.b[a][s] + dface(G, W, 0, s, a, dt);
-  if (!fixup) return 0.5 * (base.b[a][s] + half.b[a][s] + dface(G, W, 1, s, a, dt));
-  return base.b[a][s] + 0.5 * (dface(G, W, 0, s, a, dt) + dface(G, W, 1, s, a, dt));
-}
-
-struct UpdateCfg {
-  int fofc;          // flag the new state
-  int crit;          // CTMHD_FLAG_*
-  double gamma;
-  double sres;       // resistive signal speed term of the CFL maximum
-  const uint8_t* force;  // forced flags of this stage or null
-};
-
-// fixup = 0: main update (flags, and for stage 1 the CFL maximum into slot 0)
-// fixup = 1: after first-order replacement; runs only if this stage flagged
-//            cells; stage 1 recomputes the CFL maximum into slot 1.
-template <typename T>
-__device__ __forceinline__ void update_item(const State& base, const State& half, const State& out,
-                                            const Geom& G, const Work<T>& W, int stage, int fixup,
-                                            const UpdateCfg& U, long long* diag, int vb, int strips,
-                                            unsigned long long* slots, int slot) {
-  const int ninter = G.n[0] * G.n[1] * G.n[2];
-  const double dt = *W.dt;
-  double sigmax = 0.0;
-  for (int strip = 0; strip < strips; ++strip) {
-  const int t = (vb * strips + strip) * kBlock + (int)threadIdx.x;
-  const bool live = t < ninter;
-  int bad = 0;
-  double sig = 0.0;
-  if (live) {
-    const int i0 = t % G.n[0];
-    const int q = t / G.n[0];
-    const int j0 = q % G.n[1];
-    const int k0 = q / G.n[1];
-    const int p3[3] = {i0, j0, k0};
-    const int s = (i0 + G.g) + G.st[1] * (j0 + G.g) + G.st[2] * (k0 + G.g);
-    double c[5], bl[3];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      if (stage == 0)
-        c[m] = base.c[m][s] + dcons(G, W, 0, s, m, dt);
-      else if (!fixup)
-        c[m] = 0.5 * (base.c[m][s] + half.c[m][s] + dcons(G, W, 1, s, m, dt));
-      else
-        c[m] = base.c[m][s] + 0.5 * (dcons(G, W, 0, s, m, dt) + dcons(G, W, 1, s, m, dt));
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) bl[a] = new_face(base, half, G, W, stage, fixup, s, a, dt);
-    // periodic images: every storage position congruent to this cell
-    int mlo[3], mhi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int pos = p3[d] + G.g;
-      mlo[d] = -(pos / G.n[d]);
-      mhi[d] = (G.N[d] - 1 - pos) / G.n[d];
-    }
-    for (int mz = mlo[2]; mz <= mhi[2]; ++mz)
-      for (int my = mlo[1]; my <= mhi[1]; ++my)
-        for (int mx = mlo[0]; mx <= mhi[0]; ++mx) {
-          const int sw = s + mx * G.n[0] + my * G.n[1] * G.st[1] + mz * G.n[2] * G.st[2];
-#pragma unroll
-          for (int m = 0; m < 5; ++m) out.c[m][sw] = c[m];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) out.b[a][sw] = bl[a];
-        }
-    const bool need_state = (U.fofc && !fixup) || stage == 1;
-    if (need_state) {
-      // upper faces of this cell, recomputed with the same arithmetic as
-      // the neighbour that owns them
-      double bu[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) bu[a] = new_face(base, half, G, W, stage, fixup, s + G.st[a], a, dt);
-      const double rho = c[0];
-      double u[3], bc[3];
-      bool nonfin = false;
-#pragma unroll
-      for (int m = 0; m < 5; ++m) nonfin |= !__builtin_isfinite(c[m]);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        nonfin |= !__builtin_isfinite(bl[d]) || !__builtin_isfinite(bu[d]);
-        bc[d] = 0.5 * (bl[d] + bu[d]);
-        u[d] = c[1 + d] / rho;
-      }
-      const double p = (U.gamma - 1.0) * (c[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
-                                          0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
-      if (U.fofc && !fixup) {
-        if ((U.crit & CTMHD_FLAG_RHO) && !(rho > 0.0)) bad = 1;
-        if ((U.crit & CTMHD_FLAG_P) && !(p > 0.0)) bad = 1;
-        if ((U.crit & CTMHD_FLAG_NONFINITE) && (nonfin || !__builtin_isfinite(p))) bad = 1;
-        if (U.force && U.force[t]) bad = 1;
-        W.flag[t] = (uint8_t)bad;
-      }
-      if (stage == 1) sig = cfl_signal(rho, u, p, bc, G, U.gamma, U.sres);
-    }
-  }
-  if (U.fofc && !fixup) {
-    unsigned long long m = __ballot(bad);
-    if ((threadIdx.x & 63) == 0 && m) {
-      int cnt = __popcll(m);
-      atomicAdd(&W.nflag[stage], cnt);
-      if (diag) atomicAdd((unsigned long long*)&diag[stage], (unsigned long long)cnt);
-    }
-  }
-  sigmax = (sig > sigmax || sig != sig) ? sig : sigmax;
-  }
-  if (stage == 1) {
-    if (fixup && threadIdx.x == 0) W.nflag[2] = 1;
-    block_max_to_slots(sigmax, slots, slot);
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_update(State base, State half, State out, Geom G, Work<T> W, int stage, int fixup,
-             UpdateCfg U, long long* diag, const int* stop) {
-  if (*stop) return;
-  if (fixup && W.nflag[stage] == 0) return;
-  update_item<T>(base, half, out, G, W, stage, fixup, U, diag, blockIdx.x, 1,
-                 W.smax + (fixup ? kMaxSlots : 0), blockIdx.x % kMaxSlots);
-}
-
-// ---------------------------------------------------------------------------
-// First-order flux correction (Sec. 2.5): faces touching a flagged cell take
-// the PC + LLF flux of S^n, edges touching one the first-order EMF of S^n.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int interior_id(const Geom& G, int s0, int s1, int s2) {
-  int i = (s0 - G.g) % G.n[0];
-  if (i < 0) i += G.n[0];
-  int j = (s1 - G.g) % G.n[1];
-  if (j < 0) j += G.n[1];
-  int k = (s2 - G.g) % G.n[2];
-  if (k < 0) k += G.n[2];
-  return i + G.n[0] * (j + G.n[1] * k);
-}
-
-// First-order (PC + LLF) flux at the x_a face s; returns s_LLF and u*.
-template <typename T>
-__device__ __forceinline__ T fo_face(const State& S, const Geom& G, int s, int a, double gamma_d,
-                                     T F[5], T& ustar) {
-  const int b = (a + 1) % 3, c = (a + 2) % 3;
-  T vl[7], vr[7];
-  face_local<T>(S, G, s - G.st[a], a, gamma_d, vl);
-  face_local<T>(S, G, s, a, gamma_d, vr);
-  FState<T> L{vl[0], vl[1], vl[2], vl[3], vl[4], vl[5], vl[6]};
-  FState<T> R{vr[0], vr[1], vr[2], vr[3], vr[4], vr[5], vr[6]};
-  T Fl[5];
-  T sp = llf_flux(L, R, (T)S.b[a][s], (T)gamma_d, Fl);
-  F[0] = Fl[0];
-  F[1 + a] = Fl[1];
-  F[1 + b] = Fl[2];
-  F[1 + c] = Fl[3];
-  F[4] = Fl[4];
-  ustar = (sp * L.un + sp * R.un) / (sp + sp);
-  return sp;
-}
-
-template <typename T, int EMF>
-__device__ __forceinline__ T fo_corner_cell(const State& Sn, const Geom& G, int s, int a, int b,
-                                            double gamma, T baY, T bbX) {
-  // ideal EMF of a cell (PC): -u_a b_b + u_b b_a, from cell-centred values
-  double rho, u[3], p, bc[3];
-  cell_prim(Sn, G, s, gamma, rho, u, p, bc);
-  if (EMF == kB25A) return -(T)u[a] * (T)bc[b] + (T)u[b] * (T)bc[a];
-  return -(T)u[a] * bbX + (T)u[b] * baY;  // FS18 with PC: cell velocity, edge field
-}
-
-// One thread per interior cell position s: its three lower faces and the
-// three edges at its lower corner.  Stage 1 writes both stored flux sets so
-// that their RK average is the first-order value.  Periodic images of the
-// upper boundary faces / edges are written as well (the update reads them).
-template <typename T, int EMF>
-__device__ __forceinline__ void fo_at(const State& Sn, const Geom& G, const Work<T>& W, int stage,
-                                      double gamma, double eta_d, int t) {
-  int nf = G.n[0] * G.n[1] * G.n[2];
-  if (t >= nf) return;
-  const int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
-  const int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-  const bool f0 = W.flag[t] != 0;
-  for (int a = 0; a < 3; ++a) {
-    int l3[3] = {s3[0], s3[1], s3[2]};
-    l3[a] -= 1;
-    if (!f0 && !W.flag[interior_id(G, l3[0], l3[1], l3[2])]) continue;
-    T F[5], us;
-    fo_face<T>(Sn, G, s, a, gamma, F, us);
-    if (eta_d > 0.0) F[4] += joule<T>(Sn, G, s, a, (T)eta_d);
-    for (int rep = 0; rep < 2; ++rep) {
-      if (rep && s3[a] != G.g) break;
-      const int sw = s + (rep ? G.n[a] * G.st[a] : 0);
-      for (int m = 0; m < 5; ++m) {
-        W.F[stage][a][m][sw] = F[m];
-        if (stage == 1) W.F[0][a][m][sw] = F[m];
-      }
-    }
-  }
-  for (int c = 0; c < 3; ++c) {
-    const int a = (c + 1) % 3, b = (c + 2) % 3;
-    int fl = 0;
-    for (int q = 0; q < 4; ++q) {
-      int p3[3] = {s3[0], s3[1], s3[2]};
-      p3[a] -= (q & 1);
-      p3[b] -= (q >> 1);
-      fl |= W.flag[interior_id(G, p3[0], p3[1], p3[2])];
-    }
-    if (!fl) continue;
-    const int sa = G.st[a], sb = G.st[b];
-    T F[5];
-    T usaB, usaT, usbL, usbR;
-    T apB = fo_face<T>(Sn, G, s - sb, a, gamma, F, usaB);
-    T apT = fo_face<T>(Sn, G, s, a, gamma, F, usaT);
-    T bpL = fo_face<T>(Sn, G, s - sa, b, gamma, F, usbL);
-    T bpR = fo_face<T>(Sn, G, s, b, gamma, F, usbR);
-    T baB = (T)Sn.b[a][s - sb], baT = (T)Sn.b[a][s];
-    T bbL = (T)Sn.b[b][s - sa], bbR = (T)Sn.b[b][s];
-    T e[4];
-    if (EMF == kQ26) {
-      e[0] = -usaB * bbL + usbL * baB;
-      e[1] = -usaB * bbR + usbR * baB;
-      e[2] = -usaT * bbL + usbL * baT;
-      e[3] = -usaT * bbR + usbR * baT;
-    } else {
-      // corner XY is the cell on side X along a and side Y along b
-      e[0] = fo_corner_cell<T, EMF>(Sn, G, s - sa - sb, a, b, gamma, baB, bbL);
-      e[1] = fo_corner_cell<T, EMF>(Sn, G, s - sb, a, b, gamma, baB, bbR);
-      e[2] = fo_corner_cell<T, EMF>(Sn, G, s - sa, a, b, gamma, baT, bbL);
-      e[3] = fo_corner_cell<T, EMF>(Sn, G, s, a, b, gamma, baT, bbR);
-    }
-    T aa = tmax(apB, apT), ab = tmax(bpL, bpR);
-    T eps = ld04(e[0], e[1], e[2], e[3], aa, aa, ab, ab, baB, baT, bbL, bbR);
-    if (eta_d > 0.0) eps += eta_j<T>(Sn, G, s, c, (T)eta_d);
-    for (int qa = 0; qa < 2; ++qa)
-      for (int qb = 0; qb < 2; ++qb) {
-        if ((qa && s3[a] != G.g) || (qb && s3[b] != G.g)) continue;
-        const int sw = s + (qa ? G.n[a] * sa : 0) + (qb ? G.n[b] * sb : 0);
-        W.E[stage][c][sw] = eps;
-        if (stage == 1) W.E[0][c][sw] = eps;
-      }
-  }
-}
-
-template <typename T, int EMF>
-__global__ void __launch_bounds__(kBlock)
-    k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
-  if (*stop) return;
-  if (W.nflag[stage] == 0) return;
-  fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, gidx());
-}
-
-// ---------------------------------------------------------------------------
-// Batched boxes: one persistent launch per step drains a work queue of
-// (phase, box, tile) items.  Items are ordered phase-major (largest boxes
-// first inside a phase), so an item only ever waits for items that precede
-// it in the queue (the previous phase of its own box): with workgroups that
-// claim an item only after finishing the last one, the queue always drains.
-// Each box is a periodic box of its own (ghosts wrapped per box); no data
-// crosses boxes.
-// ---------------------------------------------------------------------------
-enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P };
-constexpr int kMaxPhases = 16;
-
-struct BoxDesc {
-  Geom G;
-  FacePlan FP;
-  long long off;       // element offset of the box in the packed field arrays
-  long long flag_off;  // offset of the box in the packed flag array
-  double sres;         // resistive term of the CFL maximum (depends on dx)
-};
-
-struct PlanHeader {
-  int nbox, nphase, strips, magic;
-  unsigned long long key;    // hash of the parameters and boxes the plan was built for
-  int kind[kMaxPhases];      // PH_*
-  int stage[kMaxPhases];     // RK stage of F/E/U/O/X phases
-  int item_off[kMaxPhases];  // first queue index of each phase inside its launch
-  int range[3][2];           // phase ranges [lo, hi) of the start, step and copy launches
-  int range_items[3];        // items of each launch
-  long long order_off, prefix_off, desc_off;  // byte offsets of the arrays below
-  // int order[nbox]; int prefix[nphase][nbox + 1]; BoxDesc desc[nbox]
-};
-constexpr int kPlanMagic = 0x43544d48;
-
-template <typename T>
-struct BatchArgs {
-  State user, B, H;   // packed states (box offsets from the plan)
-  Work<T> W;          // packed stencil arrays; per-box scalars below
-  const char* plan;
-  int* cursor;        // queue cursor of this launch
-  int* done;          // [nphase][nbox] finished items
-  int* nflag;         // [nbox][4]: flagged cells stage 0 / 1, stage-1 fix-up ran
-  unsigned long long* slots;  // [nbox][2]: CFL maximum (main pass, fix-up)
-  double* dt;         // [nbox] (per-box dt) or [1]
-  int* stop;
-  int* err;           // set when a dependency wait times out
-  long long* diag;    // this step's counters or null
-  int dt_per_box;
-  const int* loc;     // where the current state lives: 0 `user`, 1 B (flipped by each step that ran)
-  int launch;         // 0 start (wrap + CFL), 1 step, 2 copy-back
-  unsigned long long key;  // must equal the plan's key
-  unsigned long long tab;  // device address of BoxTab<T>[nbox]
-  double gamma, eta;
-  int fofc, crit;
-};
-
-// Everything one box needs, with its pointers already shifted to the box:
-// built once per batched call by k_btab in the workspace and read through the
-// constant address space (uniform scalar loads that may be indexed at run
-// time, as kernel arguments are in the single-box kernels).
-template <typename T>
-struct BoxTab {
-  State su, sb, sh;  // the box in the caller's arrays, in B, in H
-  Work<T> w;         // its stencil arrays and per-box scalars
-  Geom G;
-  FacePlan FP;
-  double sres;
-};
-#define CTMHD_CONST __attribute__((address_space(4)))
-
-__device__ __forceinline__ State shift_state(const State& S, long long off) {
-  State R;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) R.c[m] = S.c[m] + off;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) R.b[a] = S.b[a] + off;
-  return R;
-}
-
-template <typename T>
-__device__ __forceinline__ Work<T> shift_work(const Work<T>& W0, long long off) {
-  Work<T> W = W0;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) W.prim[v] = W0.prim[v] ? W0.prim[v] + off : nullptr;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) W.ecell[c] = W0.ecell[c] ? W0.ecell[c] + off : nullptr;
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-      for (int m = 0; m < 5; ++m) W.F[st][a][m] = W0.F[st][a][m] + off;
-      W.E[st][a] = W0.E[st][a] + off;
-    }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    W.ap[a] = W0.ap[a] + off;
-    W.am[a] = W0.am[a] + off;
-    W.us[a] = W0.us[a] + off;
-  }
-  return W;
-}
-
-// Wait until *cnt >= need.  Thread 0 polls with relaxed loads (an acquire
-// per poll would invalidate the XCD's L2 on every iteration and starve the
-// working workgroups), then acquires once.  Bounded by wall-clock time
-// (100 MHz counter, about 1 s): on a timeout the error flag is raised and
-// every later wait returns at once.
-__device__ __forceinline__ void wait_count(const int* cnt, int need, int* err) {
-  if (threadIdx.x == 0) {
-    const unsigned long long t0 = wall_clock64();
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-      __builtin_amdgcn_s_sleep(8);
-      if (wall_clock64() - t0 > 100000000ull) {
-        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-    // the producer may sit on another XCD (another L2): one acquire for the
-    // workgroup's CU and XCD caches
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-}
-
-// Every wave releases its own stores at agent scope before thread 0 counts
-// the item as done.
-__device__ __forceinline__ void signal_count(int* cnt) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One work item of a batched step: phase kind `kind` (run-time; KIND is its
-// compile-time class: PH_U covers PH_U and PH_X, so that the main and the
-// fix-up update share one call site as in k_update) of box b, tile `tile`.
-template <typename T, int RECON, int RIEMANN, int EMF, int KIND>
-__device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kind, int stage,
-                                           int tile, int strips, int cl) {
-  const BoxTab<T>& tb = *(const BoxTab<T>*)((const CTMHD_CONST BoxTab<T>*)A.tab + b);
-  const Geom& G = tb.G;
-  const State& cur = cl == 0 ? tb.su : tb.sb;
-  if constexpr (KIND == PH_COPY) {  // the state of this box back into the caller's arrays
-    if (cl == 1)
-      for (int s = 0; s < strips; ++s) {
-        const int t = (tile * strips + s) * kBlock + threadIdx.x;
-        if (t < G.elems) {
-#pragma unroll
-          for (int m = 0; m < 5; ++m) tb.su.c[m][t] = tb.sb.c[m][t];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) tb.su.b[a][t] = tb.sb.b[a][t];
-        }
-      }
-    return;
-  } else {
-    const Work<T>& W = tb.w;
-    const State& Hs = tb.sh;
-    const State& in = stage == 0 ? cur : Hs;
-    if constexpr (KIND == PH_P) {
-      for (int s = 0; s < strips; ++s)
-        prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if constexpr (KIND == PH_F) {
-      int nfb = 0;
-      faces_block<T, RECON, RIEMANN>(in, G, W, tb.FP, tile, stage, A.gamma, A.eta, nfb);
-      if (A.diag && nfb) atomicAdd((unsigned long long*)&A.diag[2], (unsigned long long)nfb);
-    } else if constexpr (KIND == PH_E) {
-      for (int s = 0; s < strips; ++s)
-        emf_at<T, RECON, EMF>(in, G, W, stage, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if constexpr (KIND == PH_U) {
-      const State& oth = cl == 0 ? tb.sb : tb.su;
-      UpdateCfg U;
-      U.fofc = A.fofc;
-      U.crit = A.crit;
-      U.gamma = A.gamma;
-      U.sres = tb.sres;
-      U.force = nullptr;
-      const int fix = kind == PH_X ? 1 : 0;
-      if (!fix || W.nflag[stage])
-        update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, fix, U, A.diag, tile, strips,
-                       W.smax, fix);
-    } else if constexpr (KIND == PH_O) {
-      if (W.nflag[stage])
-        for (int s = 0; s < strips; ++s)
-          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if constexpr (KIND == PH_WRAP) {
-      for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if constexpr (KIND == PH_DT) {
-      double sig = 0.0;
-      for (int s = 0; s < strips; ++s) {
-        double v = dt_sig_at(cur, G, A.gamma, tb.sres, (tile * strips + s) * kBlock + threadIdx.x);
-        sig = (v > sig || v != v) ? v : sig;
-      }
-      block_max_to_slots(sig, W.smax, 0);
-    }
-  }
-}
-
-// Per-box tables of a batched call (one thread per box).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_btab(BatchArgs<T> A, int nbox) {
-  const PlanHeader* P = (const PlanHeader*)A.plan;
-  if (P->magic != kPlanMagic || P->key != A.key) return;  // refused by the step kernels
-  const int b = blockIdx.x * kBlock + threadIdx.x;
-  if (b >= nbox) return;
-  const BoxDesc& d = ((const BoxDesc*)(A.plan + P->desc_off))[b];
-  BoxTab<T>* tb = (BoxTab<T>*)A.tab + b;
-  tb->su = shift_state(A.user, d.off);
-  tb->sb = shift_state(A.B, d.off);
-  tb->sh = shift_state(A.H, d.off);
-  Work<T> W = shift_work(A.W, d.off);
-  W.flag = A.W.flag + d.flag_off;
-  W.dt = A.dt + (A.dt_per_box ? b : 0);
-  W.nflag = A.nflag + 4 * b;
-  W.smax = A.slots + 2 * b;
-  W.stop = A.stop;
-  tb->w = W;
-  tb->G = d.G;
-  tb->FP = d.FP;
-  tb->sres = d.sres;
-}
-
-// Plan lookup shared by both schedules: true if the plan was built for the
-// call's parameters and boxes.
-__device__ __forceinline__ bool plan_ok(const char* plan, unsigned long long key, int* err) {
-  const PlanHeader* P = (const PlanHeader*)plan;
-  if (P->magic == kPlanMagic && P->key == key) return true;
-  if (threadIdx.x == 0) atomicOr(err, 2);
-  return false;
-}
-
-// Box (index into `order`, largest k with pre[k] <= r) of item r of a phase.
-__device__ __forceinline__ int item_box(const int* pre, int nbox, int r) {
-  int k0 = 0, k1 = nbox;
-  while (k1 - k0 > 1) {
-    int mid = (k0 + k1) >> 1;
-    if (pre[mid] <= r) k0 = mid; else k1 = mid;
-  }
-  return k0;
-}
-
-// Persistent schedule: one launch per step (plus a start and a copy-back
-// launch).  Workgroups claim queue items in phase-major order; an item waits
-// only for all items of the previous phase of its own box.
-template <typename T, int RECON, int RIEMANN, int EMF>
-__global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
-  if (*A.stop && A.launch != 2) return;  // the copy-back runs even after a stop
-  if (!plan_ok(A.plan, A.key, A.err)) return;
-  const PlanHeader* P = (const PlanHeader*)A.plan;
-  const int* order = (const int*)(A.plan + P->order_off);
-  const int* prefix = (const int*)(A.plan + P->prefix_off);
-  const int nbox = P->nbox;
-  const int lo = P->range[A.launch][0], hi = P->range[A.launch][1];
-  const int total = P->range_items[A.launch];
-  const int strips = P->strips;
-  const int cl = *A.loc;  // fixed for the whole launch
-  __shared__ int item_s;
-  for (;;) {
-    if (threadIdx.x == 0) item_s = atomicAdd(A.cursor, 1);
-    __syncthreads();
-    const int q = item_s;
-    __syncthreads();
-    if (q >= total) break;
-    int p = lo;
-    while (p + 1 < hi && P->item_off[p + 1] <= q) ++p;
-    const int* pre = prefix + (long long)p * (nbox + 1);
-    const int r = q - P->item_off[p];
-    const int k0 = item_box(pre, nbox, r);
-    const int b = order[k0];
-    const int tile = r - pre[k0];
-    if (p > lo) {
-      const int* ppre = prefix + (long long)(p - 1) * (nbox + 1);
-      wait_count(A.done + (long long)(p - 1) * nbox + b, ppre[k0 + 1] - ppre[k0], A.err);
-    }
-    const int kind = P->kind[p], stage = P->stage[p];
-    switch (kind) {
-      case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_U:
-      case PH_X: batch_item<T, RECON, RIEMANN, EMF, PH_U>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_O: batch_item<T, RECON, RIEMANN, EMF, PH_O>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_WRAP: batch_item<T, RECON, RIEMANN, EMF, PH_WRAP>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_DT: batch_item<T, RECON, RIEMANN, EMF, PH_DT>(A, b, kind, stage, tile, strips, cl); break;
-      default: batch_item<T, RECON, RIEMANN, EMF, PH_COPY>(A, b, kind, stage, tile, strips, cl); break;
-    }
-    signal_count(A.done + (long long)p * nbox + b);
-  }
-}
-
-// Phased schedule: one launch per phase over all boxes; workgroup r runs
-// item r of phase p.  Launch boundaries order the phases.
-template <typename T, int RECON, int RIEMANN, int EMF, int KIND>
-__global__ void __launch_bounds__(kBlock) k_bphase(BatchArgs<T> A, int p) {
-  if (KIND != PH_COPY && *A.stop) return;  // the copy-back runs even after a stop
-  if (!plan_ok(A.plan, A.key, A.err)) return;
-  const PlanHeader* P = (const PlanHeader*)A.plan;
-  const int nbox = P->nbox;
-  const int* pre = (const int*)(A.plan + P->prefix_off) + (long long)p * (nbox + 1);
-  const int r = blockIdx.x;
-  if (r >= pre[nbox]) return;
-  const int k0 = item_box(pre, nbox, r);
-  const int b = ((const int*)(A.plan + P->order_off))[k0];
-  batch_item<T, RECON, RIEMANN, EMF, KIND>(A, b, P->kind[p], P->stage[p], r - pre[k0], P->strips,
-                                           *A.loc);
-}
-
-// dt of a batched step from the per-box CFL maxima (the fix-up maximum where
-// a box's second stage was fixed up); resets the per-step counters.
-__global__ void __launch_bounds__(kBlock)
-    k_bdt_final(int nbox, int nphase, int dt_per_box, unsigned long long* slots, int* nflag,
-                int* done, int* cursor, double cfl, const double* dt_fixed, double* dt,
-                double* dt_out, int* stop, const int* err, long long* diag) {
-  __shared__ unsigned long long red[kBlock];
-  const int t = threadIdx.x;
-  unsigned long long mx = 0;
-  const bool stopped = *stop != 0;
-  for (int b = t; b < nbox; b += kBlock) {
-    unsigned long long v = nflag[4 * b + 2] ? slots[2 * b + 1] : slots[2 * b];
-    mx = v > mx ? v : mx;
-    if (dt_per_box) {
-      double x = stopped ? 0.0 : (dt_fixed ? dt_fixed[b] : cfl / __longlong_as_double((long long)v));
-      if (!stopped && (!(x > 0.0) || !__builtin_isfinite(x))) atomicExch(stop, 1);
-      dt[b] = x;
-      if (dt_out) dt_out[b] = x;
-    }
-  }
-  red[t] = mx;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if (t < o) red[t] = red[t + o] > red[t] ? red[t + o] : red[t];
-    __syncthreads();
-  }
-  if (t == 0 && !dt_per_box) {
-    double x = stopped ? 0.0 : (dt_fixed ? dt_fixed[0] : cfl / __longlong_as_double((long long)red[0]));
-    if (!stopped && (!(x > 0.0) || !__builtin_isfinite(x))) *stop = 1;
-    dt[0] = x;
-    if (dt_out) dt_out[0] = x;
-  }
-  for (int b = t; b < nbox; b += kBlock) {
-    slots[2 * b] = slots[2 * b + 1] = 0ull;
-    nflag[4 * b] = nflag[4 * b + 1] = nflag[4 * b + 2] = nflag[4 * b + 3] = 0;
-  }
-  for (int i = t; i < nphase * nbox; i += kBlock) done[i] = 0;
-  if (t < 4) cursor[t] = 0;
-  __syncthreads();
-  if (t == 0 && diag) {
-    diag[0] = diag[1] = diag[2] = 0;
-    diag[3] = (*stop ? 1 : 0) | (*err << 1);
-  }
-}
-
-// Reset before a launch of the queue (start / copy launches); init = 1 at the
-// start of a call also clears the stop / error flags, the state location and
-// the per-box CFL slots.
-__global__ void k_breset(int nbox, int nphase, int* done, int* cursor, int init, int* stop,
-                         int* err, int* loc, unsigned long long* slots, int* nflag) {
-  for (int i = threadIdx.x; i < nphase * nbox; i += kBlock) done[i] = 0;
-  if (threadIdx.x < 4) cursor[threadIdx.x] = 0;
-  if (!init) return;
-  for (int b = threadIdx.x; b < nbox; b += kBlock) {
-    slots[2 * b] = slots[2 * b + 1] = 0ull;
-    nflag[4 * b] = nflag[4 * b + 1] = nflag[4 * b + 2] = nflag[4 * b + 3] = 0;
-  }
-  if (threadIdx.x == 0) {
-    *stop = 0;
-    *err = 0;
-    *loc = 0;
-  }
-}
-
-// After a batched step: the new state is in the other buffer unless the step
-// was stopped (non-finite dt), which leaves it where it was.
-__global__ void k_bstep_end(int* loc, const int* stop, const int* err, long long* diag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (diag) diag[3] |= *err << 1;
-  if (!*stop) *loc ^= 1;
-}
-
-// ---------------------------------------------------------------------------
-// Host side
-// ---------------------------------------------------------------------------
 thread_local char g_err[256] = "";
-
-int fail(int code, const char* msg) {
-  snprintf(g_err, sizeof(g_err), "%s", msg);
-  return code;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Tuning knobs in ctmhd_params.tile: bits 0-7 minimum faces per marching
-// chunk (default 32), bits 8-15 256-element strips per batched work item
-// (default 1), bits 16-23 batched schedule (0 per phase, 1 persistent).
-int tile_chunk(const ctmhd_params* p) {
-  int c = p->tile & 0xff;
-  return c > 0 ? c : 32;
-}
-int tile_strips(const ctmhd_params* p) {
-  int s = (p->tile >> 8) & 0xff;
-  return s > 0 ? s : 1;
-}
-// bits 16-23: batched schedule, 0 one launch per phase, 1 persistent queue
-int tile_sched(const ctmhd_params* p) { return (p->tile >> 16) & 0xff; }
-
-int check_params(const ctmhd_params* p) {
-  if (!p) return fail(CTMHD_EARG, "params is NULL");
-  if (!(p->gamma > 1.0)) return fail(CTMHD_EARG, "gamma must be > 1");
-  if (!(p->eta >= 0.0)) return fail(CTMHD_EARG, "eta must be >= 0");
-  if (!(p->cfl > 0.0 && p->cfl < 1.0)) return fail(CTMHD_EARG, "cfl must be in (0, 1)");
-  if (p->eta > 0.0 && !(p->cfl < 1.0 / 3.0))
-    return fail(CTMHD_EARG, "cfl must be < 1/3 with eta > 0 (3D diffusive limit)");
-  if (p->recon < 0 || p->recon > 3) return fail(CTMHD_EARG, "unknown reconstruction");
-  if (p->riemann < 0 || p->riemann > 1) return fail(CTMHD_EARG, "unknown Riemann solver");
-  if (p->emf_compute < 0 || p->emf_compute > 2) return fail(CTMHD_EARG, "unknown EMF scheme");
-  if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
-  if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32) return fail(CTMHD_EARG, "unknown precision");
-  if (p->tile < 0 || p->tile > 0x1ffff) return fail(CTMHD_EARG, "tile knob out of range");
-  return CTMHD_OK;
-}
-
-int check_box(const ctmhd_params* p, const ctmhd_box* b) {
-  if (!b) return fail(CTMHD_EARG, "box is NULL");
-  for (int d = 0; d < 3; ++d) {
-    if (b->n[d] < 1) return fail(CTMHD_EARG, "box dimensions must be >= 1");
-    if (!(b->dx[d] > 0.0)) return fail(CTMHD_EARG, "dx must be > 0");
-  }
-  if (b->ng < recon_halfwidth(p->recon) + 2) return fail(CTMHD_EARG, "too few ghost layers");
-  long long e = 1;
-  for (int d = 0; d < 3; ++d) e *= (long long)(b->n[d] + 2 * b->ng);
-  if (e * 6 >= (1LL << 31)) return fail(CTMHD_EARG, "box too large for 32-bit indexing");
-  return CTMHD_OK;
-}
-
-// Workspace of one box for the stencil type of `tbytes` bytes.
-size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, int emf) {
-  size_t e = 1;
-  for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
-  size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
-  size_t bytes = 0;
-  bytes += 2 * 8 * align256(e * 8);           // two state buffers
-  if (emf == CTMHD_EMF_B25A) bytes += 3 * align256(e * tbytes);  // cell EMF
-  if (emf == CTMHD_EMF_FS18) bytes += 3 * align256(e * tbytes);  // cell velocity
-  bytes += 2 * 15 * align256(e * tbytes);     // fluxes, two stages
-  bytes += 9 * align256(e * tbytes);          // alpha+, alpha-, u*
-  bytes += 6 * align256(e * tbytes);          // EMFs, two stages
-  bytes += align256(ninter);                  // flags
-  bytes += align256(2 * kMaxSlots * 8) + 256; // CFL slots + scalars
-  return bytes;
-}
-
-struct Carve {
-  char* p;
-  template <typename U>
-  U* take(size_t n) {
-    U* r = (U*)p;
-    p += align256(n * sizeof(U));
-    return r;
-  }
-};
-
-template <typename T>
-int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_box& b, Work<T>& W,
-               State& A2, State& H) {
-  size_t need = box_ws_bytes(b, sizeof(T), prm->emf_compute);
-  if (!ws || ws_bytes < need) return fail(CTMHD_EARG, "workspace too small");
-  if (((uintptr_t)ws & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
-  size_t e = 1;
-  for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
-  size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
-  Carve cv{(char*)ws};
-  for (int m = 0; m < 5; ++m) A2.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) A2.b[a] = cv.take<double>(e);
-  for (int m = 0; m < 5; ++m) H.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) H.b[a] = cv.take<double>(e);
-  for (int v = 0; v < 8; ++v) W.prim[v] = nullptr;
-  for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
-  if (prm->emf_compute == CTMHD_EMF_B25A)
-    for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-  if (prm->emf_compute == CTMHD_EMF_FS18)
-    for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
-  for (int st = 0; st < 2; ++st)
-    for (int a = 0; a < 3; ++a)
-      for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.ap[a] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.am[a] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.us[a] = cv.take<T>(e);
-  for (int st = 0; st < 2; ++st)
-    for (int c = 0; c < 3; ++c) W.E[st][c] = cv.take<T>(e);
-  W.flag = cv.take<uint8_t>(ninter);
-  W.smax = cv.take<unsigned long long>(2 * kMaxSlots);
-  char* sc = cv.p;
-  W.dt = (double*)sc;
-  W.stop = (int*)(sc + 8);
-  W.nflag = (int*)(sc + 16);
-  return CTMHD_OK;
-}
-
-// Timing hook state (host only).
 void* const* g_prof_events = nullptr;
 int g_prof_pairs = 0;
 int g_prof_used = 0;
 
-inline void prof_begin(hipStream_t st) {
-  if (g_prof_events && g_prof_used < g_prof_pairs)
-    (void)hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used], st);
-}
-inline void prof_end(hipStream_t st) {
-  if (g_prof_events && g_prof_used < g_prof_pairs) {
-    (void)hipEventRecord((hipEvent_t)g_prof_events[2 * g_prof_used + 1], st);
-    ++g_prof_used;
-  }
-}
-
-#define LAUNCH(kern, blocks, ...)                                                  \
-  do {                                                                             \
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, st, __VA_ARGS__);      \
-    if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: " #kern); \
-  } while (0)
-
-// Face plan: ranges and launch shape of the fused face kernel.
-FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min) {
-  FacePlan P;
-  const int r = recon_halfwidth(recon);
-  const int g = G.g;
-  // Q26 reconstructs u* along the transverse axes to the edges, which needs
-  // faces r+1 beyond the edge range [g, g+n]; the other schemes only need
-  // alpha on the faces next to the edges.
-  const int tlo = emf == CTMHD_EMF_Q26 ? g - 1 - r : g - 1;
-  P.tlo = tlo;
-  for (int d = 0; d < 3; ++d) {
-    P.lo[d] = g;
-    P.nf[d] = G.n[d] + 1;  // faces g .. g+n read by the update and the edges
-    P.tlen[d] = (emf == CTMHD_EMF_Q26 ? g + G.n[d] + r : g + G.n[d]) - tlo + 1;
-    P.ulo[d] = g;
-    P.ulen[d] = G.n[d];
-  }
-  // x part
-  P.xseg = 64 - 2 * r - 1;
-  P.xnseg = (P.nf[0] + P.xseg - 1) / P.xseg;
-  P.xwaves = P.xnseg * P.tlen[1] * P.tlen[2];
-  P.xblocks = (P.xwaves + kBlock / 64 - 1) / (kBlock / 64);
-  // y and z parts: enough chunks along the march for ~8192 waves in flight
-  P.total_blocks = P.xblocks;
-  for (int A = 1; A <= 2; ++A) {
-    const int C = A == 1 ? 2 : 1;
-    P.lanes[A] = P.tlen[0] * P.tlen[C];
-    P.lblocks[A] = (P.lanes[A] + kBlock - 1) / kBlock;
-    int want = (8192 * 64 / kBlock) / (P.lblocks[A] > 0 ? P.lblocks[A] : 1);
-    int maxch = (P.nf[A] + chunk_min - 1) / chunk_min;  // chunk >= chunk_min faces (warm-up 2r+1)
-    if (want > maxch) want = maxch;
-    if (want < 1) want = 1;
-    P.chunk[A] = (P.nf[A] + want - 1) / want;
-    P.nchunk[A] = (P.nf[A] + P.chunk[A] - 1) / P.chunk[A];
-    P.blocks[A] = P.lblocks[A] * P.nchunk[A];
-    P.total_blocks += P.blocks[A];
-  }
-  P.chunk[0] = P.nchunk[0] = P.lanes[0] = P.lblocks[0] = P.blocks[0] = 0;
-  return P;
-}
+namespace {
 
 template <typename T, int RECON>
 int launch_faces(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
@@ -1610,332 +150,6 @@ int step_box_t(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
 }
 
 
-// ---------------------------------------------------------------------------
-// Batched boxes (host): plan, workspace and launch sequence.
-// ---------------------------------------------------------------------------
-long long box_elems_ll(const ctmhd_box& b) {
-  long long e = 1;
-  for (int d = 0; d < 3; ++d) e *= (long long)(b.n[d] + 2 * b.ng);
-  return e;
-}
-long long box_inter_ll(const ctmhd_box& b) { return (long long)b.n[0] * b.n[1] * b.n[2]; }
-
-// Phase lists: start launch (wrap, CFL), step launch, copy-back launch.
-int plan_phases(const ctmhd_params* p, int kind[kMaxPhases], int stage[kMaxPhases], int range[3][2]) {
-  int n = 0;
-  range[0][0] = n;
-  kind[n] = PH_WRAP; stage[n++] = 0;
-  kind[n] = PH_DT; stage[n++] = 0;
-  range[0][1] = n;
-  range[1][0] = n;
-  for (int st = 0; st < 2; ++st) {
-    if (p->emf_compute != CTMHD_EMF_Q26) {
-      kind[n] = PH_P; stage[n++] = st;
-    }
-    kind[n] = PH_F; stage[n++] = st;
-    kind[n] = PH_E; stage[n++] = st;
-    kind[n] = PH_U; stage[n++] = st;
-    if (p->fofc) {
-      kind[n] = PH_O; stage[n++] = st;
-      kind[n] = PH_X; stage[n++] = st;
-    }
-  }
-  range[1][1] = n;
-  range[2][0] = n;
-  kind[n] = PH_COPY; stage[n++] = 0;
-  range[2][1] = n;
-  return n;
-}
-
-size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-
-// Work items of one phase of one box.
-long long item_count(int kind, const Geom& G, const FacePlan& FP, long long per) {
-  switch (kind) {
-    case PH_F: return FP.total_blocks;
-    case PH_E: return ((long long)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1) + per - 1) / per;
-    case PH_P:
-    case PH_WRAP:
-    case PH_COPY: return ((long long)G.elems + per - 1) / per;
-    default: return ((long long)G.n[0] * G.n[1] * G.n[2] + per - 1) / per;
-  }
-}
-
-// FNV-1a over everything a plan depends on: the kernel refuses a plan whose
-// key differs from the one computed for the call's own parameters and boxes.
-unsigned long long plan_key(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  unsigned long long h = 0xcbf29ce484222325ull;
-  auto mix = [&h](const void* v, size_t n) {
-    const unsigned char* c = (const unsigned char*)v;
-    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
-  };
-  const int f[6] = {p->recon, p->emf_compute, p->fofc, tile_strips(p), tile_chunk(p), nbox};
-  mix(f, sizeof(f));
-  for (int b = 0; b < nbox; ++b) {
-    mix(boxes[b].n, sizeof(boxes[b].n));
-    mix(&boxes[b].ng, sizeof(boxes[b].ng));
-    mix(boxes[b].dx, sizeof(boxes[b].dx));
-    mix(&boxes[b].offset, sizeof(boxes[b].offset));
-  }
-  return h;
-}
-
-size_t plan_layout(int nbox, int nphase, long long* order_off, long long* prefix_off,
-                   long long* desc_off) {
-  size_t o = align16(sizeof(PlanHeader));
-  *order_off = (long long)o;
-  o = align16(o + sizeof(int) * (size_t)nbox);
-  *prefix_off = (long long)o;
-  o = align16(o + sizeof(int) * (size_t)nphase * (nbox + 1));
-  *desc_off = (long long)o;
-  o += sizeof(BoxDesc) * (size_t)nbox;
-  return o;
-}
-
-int check_boxes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  if (!boxes || nbox < 1) return fail(CTMHD_EARG, "no boxes");
-  for (int b = 0; b < nbox; ++b) {
-    int rc = check_box(p, &boxes[b]);
-    if (rc) return rc;
-    if (boxes[b].offset < 0) return fail(CTMHD_EARG, "negative box offset");
-  }
-  // boxes must not overlap in the packed arrays
-  for (int b = 0; b < nbox; ++b) {
-    const long long b0 = boxes[b].offset, b1 = b0 + box_elems_ll(boxes[b]);
-    for (int c = b + 1; c < nbox; ++c) {
-      const long long c0 = boxes[c].offset, c1 = c0 + box_elems_ll(boxes[c]);
-      if (b0 < c1 && c0 < b1) return fail(CTMHD_EARG, "boxes overlap in the packed arrays");
-    }
-  }
-  return CTMHD_OK;
-}
-
-long long packed_elems(const ctmhd_box* boxes, int nbox) {
-  long long m = 0;
-  for (int b = 0; b < nbox; ++b) {
-    long long e = boxes[b].offset + box_elems_ll(boxes[b]);
-    m = e > m ? e : m;
-  }
-  return m;
-}
-
-size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  const size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
-  const size_t e = (size_t)packed_elems(boxes, nbox);
-  long long ninter = 0;
-  for (int b = 0; b < nbox; ++b) ninter += box_inter_ll(boxes[b]);
-  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
-  const int nphase = plan_phases(p, kind, stage, range);
-  size_t bytes = 0;
-  bytes += 2 * 8 * align256(e * 8);  // B and H states
-  if (p->emf_compute != CTMHD_EMF_Q26) bytes += 3 * align256(e * tb);
-  bytes += (2 * 15 + 9 + 6) * align256(e * tb);
-  bytes += align256((size_t)ninter);                         // flags
-  bytes += align256(sizeof(int) * (size_t)nphase * nbox);    // done
-  bytes += align256(sizeof(int) * 4 * (size_t)nbox);         // nflag
-  bytes += align256(sizeof(unsigned long long) * 2 * (size_t)nbox);  // CFL slots
-  bytes += align256(sizeof(double) * (size_t)nbox);          // dt
-  bytes += align256((tb == 4 ? sizeof(BoxTab<float>) : sizeof(BoxTab<double>)) * (size_t)nbox);
-  bytes += 256;                                              // cursor, stop, err, loc
-  return bytes;
-}
-
-template <typename T>
-int batch_args(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* ws, size_t ws_bytes,
-               BatchArgs<T>& A, int& nphase) {
-  if (!ws || ws_bytes < batch_ws_bytes(p, boxes, nbox)) return fail(CTMHD_EARG, "workspace too small");
-  if (((uintptr_t)ws & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
-  const size_t e = (size_t)packed_elems(boxes, nbox);
-  long long ninter = 0;
-  for (int b = 0; b < nbox; ++b) ninter += box_inter_ll(boxes[b]);
-  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
-  nphase = plan_phases(p, kind, stage, range);
-  Carve cv{(char*)ws};
-  for (int m = 0; m < 5; ++m) A.B.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) A.B.b[a] = cv.take<double>(e);
-  for (int m = 0; m < 5; ++m) A.H.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) A.H.b[a] = cv.take<double>(e);
-  Work<T>& W = A.W;
-  for (int v = 0; v < 8; ++v) W.prim[v] = nullptr;
-  for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
-  if (p->emf_compute == CTMHD_EMF_B25A)
-    for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-  if (p->emf_compute == CTMHD_EMF_FS18)
-    for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
-  for (int st = 0; st < 2; ++st)
-    for (int a = 0; a < 3; ++a)
-      for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.ap[a] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.am[a] = cv.take<T>(e);
-  for (int a = 0; a < 3; ++a) W.us[a] = cv.take<T>(e);
-  for (int st = 0; st < 2; ++st)
-    for (int c = 0; c < 3; ++c) W.E[st][c] = cv.take<T>(e);
-  W.flag = cv.take<uint8_t>((size_t)ninter);
-  A.done = cv.take<int>((size_t)nphase * nbox);
-  A.nflag = cv.take<int>(4 * (size_t)nbox);
-  A.slots = cv.take<unsigned long long>(2 * (size_t)nbox);
-  A.dt = cv.take<double>((size_t)nbox);
-  A.tab = (unsigned long long)(uintptr_t)cv.take<BoxTab<T>>((size_t)nbox);
-  char* sc = cv.p;
-  A.cursor = (int*)sc;          // 4 ints
-  A.stop = (int*)(sc + 16);
-  A.err = (int*)(sc + 20);
-  A.loc = (const int*)(sc + 24);
-  W.dt = A.dt;
-  W.nflag = A.nflag;
-  W.smax = A.slots;
-  W.stop = A.stop;
-  A.gamma = p->gamma;
-  A.eta = p->eta;
-  A.fofc = p->fofc;
-  A.crit = p->flag_criteria;
-  return CTMHD_OK;
-}
-
-// Persistent grid: every workgroup that can be resident at once.
-template <typename K>
-int persistent_blocks(K kernel) {
-  int dev = 0, ncu = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) return 0;
-  if (per < 1) per = 1;
-  return ncu * per;
-}
-
-// Items of every phase summed over the boxes (the grid of each phased launch;
-// the same counts as the plan's prefix sums).
-int phase_items(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, const int* kind,
-                int nphase, long long* items) {
-  const long long per = (long long)kBlock * tile_strips(p);
-  for (int q = 0; q < nphase; ++q) items[q] = 0;
-  for (int b = 0; b < nbox; ++b) {
-    const Geom G = make_geom(boxes[b]);
-    const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
-    for (int q = 0; q < nphase; ++q) items[q] += item_count(kind[q], G, FP, per);
-  }
-  for (int q = 0; q < nphase; ++q)
-    if (items[q] >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
-  return CTMHD_OK;
-}
-
-template <typename T, int RECON, int RIEMANN, int EMF>
-int launch_bphase(hipStream_t st, int kind, long long items, const BatchArgs<T>& A, int q) {
-  if (items <= 0) return CTMHD_OK;
-  const unsigned grid = (unsigned)items;
-  switch (kind) {
-    case PH_P: LAUNCH((k_bphase<T, kPC, kHLLD, EMF, PH_P>), grid, A, q); break;
-    case PH_F: LAUNCH((k_bphase<T, RECON, RIEMANN, kQ26, PH_F>), grid, A, q); break;
-    case PH_E: LAUNCH((k_bphase<T, RECON, kHLLD, EMF, PH_E>), grid, A, q); break;
-    case PH_U:
-    case PH_X: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_U>), grid, A, q); break;
-    case PH_O: LAUNCH((k_bphase<T, kPC, kHLLD, EMF, PH_O>), grid, A, q); break;
-    case PH_WRAP: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_WRAP>), grid, A, q); break;
-    case PH_DT: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_DT>), grid, A, q); break;
-    default: LAUNCH((k_bphase<T, kPC, kHLLD, kQ26, PH_COPY>), grid, A, q); break;
-  }
-  return CTMHD_OK;
-}
-
-template <typename T, int RECON, int RIEMANN, int EMF>
-int batched_run(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
-                double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
-                const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
-                hipStream_t st) {
-  BatchArgs<T> A;
-  int nphase = 0;
-  int rc = batch_args<T>(p, boxes, nbox, ws, ws_bytes, A, nphase);
-  if (rc) return rc;
-  for (int m = 0; m < 5; ++m) A.user.c[m] = cons[m];
-  for (int a = 0; a < 3; ++a) A.user.b[a] = bface[a];
-  A.plan = (const char*)plan;
-  A.key = plan_key(p, boxes, nbox);
-  A.diag = nullptr;
-  A.dt_per_box = dt_mode == CTMHD_DT_PER_BOX;
-  const bool persistent = tile_sched(p) == 1;
-  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
-  plan_phases(p, kind, stage, range);
-  long long items[kMaxPhases];
-  int grid = 0;
-  if (persistent) {
-    grid = persistent_blocks(k_batch<T, RECON, RIEMANN, EMF>);
-    if (grid < 1) return fail(CTMHD_EHIP, "occupancy query failed");
-  } else if ((rc = phase_items(p, boxes, nbox, kind, nphase, items))) {
-    return rc;
-  }
-  // launch l (0 start, 1 step, 2 copy-back) of either schedule
-  auto run_launch = [&](int l) -> int {
-    if (persistent) {
-      A.launch = l;
-      if (l == 1) prof_begin(st);
-      LAUNCH((k_batch<T, RECON, RIEMANN, EMF>), grid, A);
-      if (l == 1) prof_end(st);
-      return CTMHD_OK;
-    }
-    for (int q = range[l][0]; q < range[l][1]; ++q) {
-      if (kind[q] == PH_F) prof_begin(st);
-      int r = launch_bphase<T, RECON, RIEMANN, EMF>(st, kind[q], items[q], A, q);
-      if (r) return r;
-      if (kind[q] == PH_F) prof_end(st);
-    }
-    return CTMHD_OK;
-  };
-  const int ndt = A.dt_per_box ? nbox : 1;
-  LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 1, A.stop, A.err, (int*)A.loc, A.slots,
-         A.nflag);
-  LAUNCH(k_btab<T>, (nbox + kBlock - 1) / kBlock, A, nbox);
-  if ((rc = run_launch(0))) return rc;
-  for (int n = 0; n < nsteps; ++n) {
-    long long* dg = diag ? (long long*)diag + 4 * n : nullptr;
-    LAUNCH(k_bdt_final, 1, nbox, nphase, A.dt_per_box, A.slots, A.nflag, A.done, A.cursor, p->cfl,
-           dt_fixed ? dt_fixed + (size_t)n * ndt : nullptr, A.dt,
-           dt_out ? dt_out + (size_t)n * ndt : nullptr, A.stop, A.err, dg);
-    A.diag = dg;
-    if ((rc = run_launch(1))) return rc;
-    LAUNCH(k_bstep_end, 1, (int*)A.loc, A.stop, A.err, dg);
-  }
-  if (persistent)
-    LAUNCH(k_breset, 1, nbox, nphase, A.done, A.cursor, 0, A.stop, A.err, (int*)A.loc, A.slots,
-           A.nflag);
-  A.diag = nullptr;
-  return run_launch(2);
-}
-
-template <typename T, int RECON>
-int batched_emf(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
-                double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
-                const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
-                hipStream_t st) {
-#define CTMHD_BATCH(RI, EM) \
-  batched_run<T, RECON, RI, EM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st)
-  if (p->riemann == CTMHD_RIEMANN_HLLD) {
-    if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kHLLD, kQ26);
-    if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kHLLD, kB25A);
-    return CTMHD_BATCH(kHLLD, kFS18);
-  }
-  if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kLLF, kQ26);
-  if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kLLF, kB25A);
-  return CTMHD_BATCH(kLLF, kFS18);
-#undef CTMHD_BATCH
-}
-
-template <typename T>
-int batched_t(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
-              double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
-              const double* dt_fixed, double* dt_out, int64_t* diag, void* ws, size_t ws_bytes,
-              hipStream_t st) {
-  switch (p->recon) {
-    case CTMHD_RECON_PC:
-      return batched_emf<T, kPC>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
-    case CTMHD_RECON_PLM_MC:
-      return batched_emf<T, kPLM_MC>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
-    case CTMHD_RECON_PLM_MINMOD:
-      return batched_emf<T, kPLM_MM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
-    default:
-      return batched_emf<T, kPPM>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st);
-  }
-}
-
 }  // namespace
 
 extern "C" {
@@ -1951,103 +165,6 @@ int64_t ctmhd_box_elems(const ctmhd_box* b) {
   int64_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (int64_t)(b->n[d] + 2 * b->ng);
   return e;
-}
-
-size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  if (check_params(p) || !boxes || nbox < 1) return 0;
-  size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
-  if (nbox == 1) return box_ws_bytes(boxes[0], tb, p->emf_compute);
-  return batch_ws_bytes(p, boxes, nbox);
-}
-
-size_t ctmhd_batch_plan_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  if (check_params(p) || check_boxes(p, boxes, nbox)) return 0;
-  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
-  const int nphase = plan_phases(p, kind, stage, range);
-  long long a, b, c;
-  return plan_layout(nbox, nphase, &a, &b, &c);
-}
-
-int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* host_plan,
-                     size_t bytes) {
-  g_err[0] = 0;
-  int rc = check_params(p);
-  if (rc) return rc;
-  if ((rc = check_boxes(p, boxes, nbox))) return rc;
-  int kind[kMaxPhases], stage[kMaxPhases], range[3][2];
-  const int nphase = plan_phases(p, kind, stage, range);
-  long long order_off, prefix_off, desc_off;
-  const size_t need = plan_layout(nbox, nphase, &order_off, &prefix_off, &desc_off);
-  if (!host_plan || bytes < need) return fail(CTMHD_EARG, "plan buffer too small");
-  char* base = (char*)host_plan;
-  memset(base, 0, need);
-  PlanHeader* P = (PlanHeader*)base;
-  int* order = (int*)(base + order_off);
-  int* prefix = (int*)(base + prefix_off);
-  BoxDesc* desc = (BoxDesc*)(base + desc_off);
-  P->nbox = nbox;
-  P->nphase = nphase;
-  P->strips = tile_strips(p);
-  P->magic = kPlanMagic;
-  P->key = plan_key(p, boxes, nbox);
-  for (int q = 0; q < nphase; ++q) {
-    P->kind[q] = kind[q];
-    P->stage[q] = stage[q];
-  }
-  for (int l = 0; l < 3; ++l) {
-    P->range[l][0] = range[l][0];
-    P->range[l][1] = range[l][1];
-  }
-  P->order_off = order_off;
-  P->prefix_off = prefix_off;
-  P->desc_off = desc_off;
-  // largest boxes first (stable), so that the longest items start early
-  for (int b = 0; b < nbox; ++b) order[b] = b;
-  for (int i = 1; i < nbox; ++i) {
-    int v = order[i], j = i;
-    long long ev = box_inter_ll(boxes[v]);
-    while (j > 0 && box_inter_ll(boxes[order[j - 1]]) < ev) {
-      order[j] = order[j - 1];
-      --j;
-    }
-    order[j] = v;
-  }
-  const int strips = P->strips;
-  const long long per = (long long)kBlock * strips;
-  long long flag_off = 0;
-  for (int b = 0; b < nbox; ++b) {
-    const ctmhd_box& bx = boxes[b];
-    BoxDesc& d = desc[b];
-    d.G = make_geom(bx);
-    d.FP = make_face_plan(d.G, p->recon, p->emf_compute, tile_chunk(p));
-    d.off = bx.offset;
-    d.flag_off = flag_off;
-    flag_off += box_inter_ll(bx);
-    double dxmin = fmin(bx.dx[0], fmin(bx.dx[1], bx.dx[2]));
-    d.sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
-  }
-  long long items_in_launch = 0;
-  int launch = 0;
-  for (int q = 0; q < nphase; ++q) {
-    while (launch < 2 && q >= range[launch][1]) {
-      P->range_items[launch] = (int)items_in_launch;
-      ++launch;
-      items_in_launch = 0;
-    }
-    P->item_off[q] = (int)items_in_launch;
-    int* pre = prefix + (long long)q * (nbox + 1);
-    pre[0] = 0;
-    for (int k = 0; k < nbox; ++k) {
-      const BoxDesc& d = desc[order[k]];
-      const long long cnt = item_count(kind[q], d.G, d.FP, per);
-      if ((long long)pre[k] + cnt >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
-      pre[k + 1] = pre[k] + (int)cnt;
-    }
-    items_in_launch += pre[nbox];
-    if (items_in_launch >= (1LL << 31)) return fail(CTMHD_EARG, "work queue too long");
-  }
-  P->range_items[launch] = (int)items_in_launch;
-  return CTMHD_OK;
 }
 
 int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
@@ -2070,47 +187,6 @@ int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
                              ws_bytes, st);
   return step_box_t<double>(p, box, cons, bface, nsteps, dt_fixed, dt_out, diag, workspace,
                             ws_bytes, st);
-}
-
-int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const void* plan,
-                       double* const cons[5], double* const bface[3], int nsteps, int dt_mode,
-                       const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
-                       size_t ws_bytes, void* stream) {
-  g_err[0] = 0;
-  int rc = check_params(p);
-  if (rc) return rc;
-  if ((rc = check_boxes(p, boxes, nbox))) return rc;
-  if (p->force_flags) return fail(CTMHD_EARG, "force_flags is a single-box test hook");
-  if (!plan) return fail(CTMHD_EARG, "plan is NULL");
-  if (!cons || !bface) return fail(CTMHD_EARG, "state pointers are NULL");
-  for (int m = 0; m < 5; ++m)
-    if (!cons[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
-  for (int a = 0; a < 3; ++a)
-    if (!bface[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
-  if (dt_mode != CTMHD_DT_GLOBAL && dt_mode != CTMHD_DT_PER_BOX) return fail(CTMHD_EARG, "unknown dt mode");
-  // The persistent-queue schedule is switched off: a launch of it with the
-  // per-box constant tables did not finish and the cause is not known.
-  if (tile_sched(p) == 1)
-    return fail(CTMHD_EUNSUPPORTED, "the persistent batched schedule is disabled (a launch of it did not finish; cause not found)");
-  if (nsteps < 0) return fail(CTMHD_EARG, "nsteps must be >= 0");
-  if (nsteps == 0) return CTMHD_OK;
-  if (packed_elems(boxes, nbox) * 6 >= (1LL << 31) * 64LL) return fail(CTMHD_EARG, "packed arrays too large");
-  hipStream_t st = (hipStream_t)stream;
-  if (p->precision == CTMHD_FP32)
-    return batched_t<float>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out,
-                            diag, workspace, ws_bytes, st);
-  return batched_t<double>(p, nbox, boxes, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out,
-                           diag, workspace, ws_bytes, st);
-}
-
-int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],
-                       const double* const bface_n[3], const double* dt,
-                       const double* const g_cons[5], const double* const g_bface[3],
-                       double* const g_cons_out[5], double* const g_bface_out[3], void* workspace,
-                       size_t ws_bytes, void* stream) {
-  (void)p; (void)box; (void)cons_n; (void)bface_n; (void)dt; (void)g_cons; (void)g_bface;
-  (void)g_cons_out; (void)g_bface_out; (void)workspace; (void)ws_bytes; (void)stream;
-  return fail(CTMHD_EUNSUPPORTED, "ctmhd_step_adjoint is not built yet");
 }
 
 int ctmhd_profile_events(void* const* events, int npairs) {
