@@ -8,6 +8,10 @@
 
 #include <hip/hip_runtime.h>
 
+// per-point arithmetic is callable from device and host code (the host
+// instances serve CPU checks of the derivative code)
+#define CTMHD_HD __host__ __device__ __forceinline__
+
 namespace ctmhd {
 
 enum : int { kPC = 0, kPLM_MC = 1, kPLM_MM = 2, kPPM = 3 };
@@ -22,18 +26,18 @@ __host__ __device__ constexpr int recon_halfwidth(int m) {
 // abs / min / max / sign transfer as single instructions (v_max_f64 etc.);
 // on non-NaN operands they return the same values as the comparisons
 // a >= b ? a : b and x < 0 ? -x : x (up to the sign of a zero).
-__device__ __forceinline__ double tabs(double x) { return __builtin_fabs(x); }
-__device__ __forceinline__ float tabs(float x) { return __builtin_fabsf(x); }
-__device__ __forceinline__ double tmax(double a, double b) { return __builtin_fmax(a, b); }
-__device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
-__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
-__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
-__device__ __forceinline__ double tsign(double mag, double s) { return __builtin_copysign(mag, s); }
-__device__ __forceinline__ float tsign(float mag, float s) { return __builtin_copysignf(mag, s); }
-__device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
-__device__ __forceinline__ bool tfinite(double x) { return __builtin_isfinite(x); }
-__device__ __forceinline__ bool tfinite(float x) { return __builtin_isfinite(x); }
+CTMHD_HD double tabs(double x) { return __builtin_fabs(x); }
+CTMHD_HD float tabs(float x) { return __builtin_fabsf(x); }
+CTMHD_HD double tmax(double a, double b) { return __builtin_fmax(a, b); }
+CTMHD_HD float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
+CTMHD_HD double tmin(double a, double b) { return __builtin_fmin(a, b); }
+CTMHD_HD float tmin(float a, float b) { return __builtin_fminf(a, b); }
+CTMHD_HD double tsign(double mag, double s) { return __builtin_copysign(mag, s); }
+CTMHD_HD float tsign(float mag, float s) { return __builtin_copysignf(mag, s); }
+CTMHD_HD double tsqrt(double x) { return __builtin_sqrt(x); }
+CTMHD_HD float tsqrt(float x) { return __builtin_sqrtf(x); }
+CTMHD_HD bool tfinite(double x) { return __builtin_isfinite(x); }
+CTMHD_HD bool tfinite(float x) { return __builtin_isfinite(x); }
 
 // ---------------------------------------------------------------------------
 // 1D reconstruction (Sec. 2.2).  q[0..4] centred on q[2]; returns the values
@@ -42,7 +46,7 @@ __device__ __forceinline__ bool tfinite(float x) { return __builtin_isfinite(x);
 // limited-slope interface value and their monotonicity constraints.
 // ---------------------------------------------------------------------------
 template <int M, typename T>
-__device__ __forceinline__ T plm_slope(T qm, T q0, T qp) {
+CTMHD_HD T plm_slope(T qm, T q0, T qp) {
   T dl = q0 - qm, dr = qp - q0;
   T s;
   if (M == kPLM_MC)
@@ -54,7 +58,7 @@ __device__ __forceinline__ T plm_slope(T qm, T q0, T qp) {
 }
 
 template <typename T>
-__device__ __forceinline__ T ppm_slope(T qm, T q0, T qp) {
+CTMHD_HD T ppm_slope(T qm, T q0, T qp) {
   T dl = q0 - qm, dr = qp - q0;
   T dc = T(0.5) * (qp - qm);
   T s = tmin(tabs(dc), T(2) * tmin(tabs(dl), tabs(dr)));
@@ -65,14 +69,14 @@ __device__ __forceinline__ T ppm_slope(T qm, T q0, T qp) {
 // PPM interface value between cells with values qa, qb and limited slopes
 // da, db (Colella-Woodward).
 template <typename T>
-__device__ __forceinline__ T ppm_iface(T qa, T qb, T da, T db) {
+CTMHD_HD T ppm_iface(T qa, T qb, T da, T db) {
   return T(0.5) * (qa + qb) - (db - da) * (T(1) / T(6));
 }
 
 // Colella-Woodward monotonicity constraints on a cell with centre value q0
 // and face values qL, qR (in place).
 template <typename T>
-__device__ __forceinline__ void ppm_constrain(T q0, T& qL, T& qR) {
+CTMHD_HD void ppm_constrain(T q0, T& qL, T& qR) {
   const T sixth = T(1) / T(6);
   if ((qR - q0) * (q0 - qL) <= T(0)) {
     qL = q0;
@@ -89,7 +93,7 @@ __device__ __forceinline__ void ppm_constrain(T q0, T& qL, T& qR) {
 }
 
 template <int M, typename T>
-__device__ __forceinline__ void recon_cell(const T* q, T& qm, T& qp) {
+CTMHD_HD void recon_cell(const T* q, T& qm, T& qp) {
   if constexpr (M == kPC) {
     qm = q[2];
     qp = q[2];
@@ -118,7 +122,7 @@ struct ReconStream {
   T q1 = T(0), q2 = T(0);  // the previous two cells (q1 newest)
   T dm1 = T(0);            // PPM: limited slope of the cell behind q1
   T ilo = T(0);            // PPM: interface below the cell completed next
-  __device__ __forceinline__ void push(T v, T& qm, T& qp) {
+  CTMHD_HD void push(T v, T& qm, T& qp) {
     if constexpr (M == kPC) {
       qm = v;
       qp = v;
@@ -156,7 +160,7 @@ __host__ __device__ constexpr bool stencil_uses(int m) {
 // six-point sequence q[0..5]: lo = upper value of cell 2, hi = lower value of
 // cell 3.
 template <int M, typename T>
-__device__ __forceinline__ void recon_iface(const T* q, T& lo, T& hi) {
+CTMHD_HD void recon_iface(const T* q, T& lo, T& hi) {
   if constexpr (M == kPPM) {
     // cells 2 and 3 share slopes d2, d3 and the interface between them
     T d1 = ppm_slope(q[0], q[1], q[2]);
@@ -182,7 +186,7 @@ __device__ __forceinline__ void recon_iface(const T* q, T& lo, T& hi) {
 // Fast magnetosonic speed along the face normal (eq. waves:fast-speed).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
+CTMHD_HD T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
   T irho = T(1) / rho;
   T gp = gamma * p;
   T a = (gp + bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
@@ -198,7 +202,7 @@ template <typename T> struct FState { T rho, un, ut1, ut2, p, bt1, bt2; };
 // Conserved state and ideal-MHD flux normal to a face (eq.
 // mhd:conservation-laws), (rho, m_n, m_t1, m_t2, e_tot) only.
 template <typename T>
-__device__ __forceinline__ void phys_flux(const FState<T>& s, T bn, T gm1inv, T* U, T* F, T& pT) {
+CTMHD_HD void phys_flux(const FState<T>& s, T bn, T gm1inv, T* U, T* F, T& pT) {
   T b2 = bn * bn + s.bt1 * s.bt1 + s.bt2 * s.bt2;
   T v2 = s.un * s.un + s.ut1 * s.ut1 + s.ut2 * s.ut2;
   T e = s.p * gm1inv + T(0.5) * (s.rho * v2 + b2);
@@ -219,7 +223,7 @@ __device__ __forceinline__ void phys_flux(const FState<T>& s, T bn, T gm1inv, T*
 
 // Local Lax-Friedrichs flux; returns the signal speed s used as alpha^{+/-}.
 template <typename T>
-__device__ __forceinline__ T llf_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
+CTMHD_HD T llf_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
                                       T* F) {
   const T gm1inv = T(1) / (gamma - T(1));
   T UL[5], FL[5], UR[5], FR[5], pL, pR;
@@ -238,7 +242,7 @@ __device__ __forceinline__ T llf_flux(const FState<T>& L, const FState<T>& R, T 
 // (rho* <= 0, p_T* <= 0, S_M outside (S_L, S_R), non-finite values) falls
 // back to HLL with the same outer speeds.  Returns 1 on fallback.
 template <typename T>
-__device__ __forceinline__ int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
+CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
                                          T* F, T& SL, T& SR) {
   T gm1inv = T(1) / (gamma - T(1));
   T UL[5], FL[5], UR[5], FR[5], pTL, pTR;
@@ -366,7 +370,7 @@ __device__ __forceinline__ int hlld_flux(const FState<T>& L, const FState<T>& R,
 // LD04 averaging (eq. emf:ld04) of four corner EMFs (LB, RB, LT, RT) with the
 // edge wavespeeds of eq. emf:alpha-edge and the edge-reconstructed fields.
 template <typename T>
-__device__ __forceinline__ T ld04(T eLB, T eRB, T eLT, T eRT, T apa, T ama, T apb, T amb, T baB,
+CTMHD_HD T ld04(T eLB, T eRB, T eLT, T eRT, T apa, T ama, T apb, T amb, T baB,
                                   T baT, T bbL, T bbR) {
   T sa = apa + ama, sb = apb + amb;
   T iab = T(1) / (sa * sb);
