@@ -167,13 +167,27 @@ int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, 
                        const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* Workspace bytes for ctmhd_step_adjoint on this machine (0 for bad arguments or
+ * an unsupported configuration). */
+size_t ctmhd_adjoint_workspace_bytes(const ctmhd_params* p, const ctmhd_box* box);
+
 /* Reverse-mode derivative (vector-Jacobian product) of ONE step of
- * ctmhd_step with a frozen dt and no flux correction taken:
- * given S^n (cons_n, bface_n; ghosts need not be filled) and dL/dS^{n+1}
- * (g_cons, g_bface, interior values; ghosts ignored), writes dL/dS^n into
- * g_cons_out / g_bface_out (interior; ghosts zeroed).  dt: device scalar.
- * Supports FP64 and FP32 forms with PC / PLM reconstruction, HLLD or LLF,
- * Q26, LD04 and eta >= 0. */
+ * ctmhd_step (Sec. 2.5: RK2-SSP, eqs. rk1:update and rk2:update) with a
+ * frozen dt and no flux correction taken (params->fofc is ignored):
+ *   cons_n, bface_n : device, the box's state S^n in the ctmhd_step layout
+ *                     (ghosts need not be filled)
+ *   dt              : device, one double, the dt of the step (> 0, finite)
+ *   g_cons, g_bface : device, dL/dS^{n+1} (interior values; ghosts ignored)
+ *   g_cons_out, g_bface_out : device, written with dL/dS^n (interior; ghosts
+ *                     zeroed); may not alias the inputs
+ *   workspace       : device, >= ctmhd_adjoint_workspace_bytes(), 256-byte
+ *                     aligned, caller-owned
+ * The derivative is taken on the branches the forward step takes at S^n
+ * (limiter cases, Riemann-fan regions, min / max selections).  Built for the
+ * FP64 form with PC / PLM (MC or minmod) reconstruction, HLLD or LLF, Q26 and
+ * LD04, eta >= 0; other configurations return CTMHD_EUNSUPPORTED.  A
+ * non-finite dt writes NaN.  Deterministic except for the Ohmic terms (eta >
+ * 0), whose face-field adjoints are accumulated with atomics. */
 int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,
                        const double* const cons_n[5], const double* const bface_n[3],
                        const double* dt, const double* const g_cons[5],

@@ -1,17 +1,591 @@
-// ctmhd_adjoint.hip -- reverse-mode derivative of one CT-MHD step (C ABI
-// entry point ctmhd_step_adjoint).
+// ctmhd_adjoint.hip -- reverse-mode derivative (vector-Jacobian product) of
+// one CT-MHD step: the C ABI entry point ctmhd_step_adjoint.
+//
+// One RK2-SSP step with a frozen dt and no flux correction (eqs. rk1:update,
+// rk2:update) is
+//   S1 = S0 + D(S0),   S2 = (S0 + S1 + D(S1)) / 2,
+// where D(S) is dt times the flux divergence of the cell fields and the CT
+// curl of the edge EMFs for the face fields.  Given g2 = dL/dS2,
+//   g1 = g2 / 2 + D'(S1)^T (g2 / 2),   g0 = g2 / 2 + g1 + D'(S0)^T g1.
+//
+// D'(S)^T v is formed in five passes over the ghosted box, each gathering
+// (no two threads write one value, except the small Ohmic terms, which use
+// atomics):
+//   edges  the EMF adjoint from v (transposed curl), then LD04 and the Q26
+//          corners in reverse: adjoints of the edge-reconstructed u*, face
+//          fields and edge speeds, stored per edge
+//   faces  the flux adjoint from v (transposed divergence); the adjoints of
+//          u*, alpha+-, and of the face field gathered from the edges that
+//          read them (through the reverse of their reconstructions); the
+//          Riemann solver in reverse: adjoints of the two face-local states
+//          and of the normal field; Joule flux and eta j in reverse
+//   cells  face-local state adjoints gathered through the reverse of the
+//          cell reconstructions, then primitive -> conserved (Sec. 2.2,
+//          eq. state:primitive)
+//   fields cell-centred field adjoints onto the two faces of each cell
+//   fold   every ghost copy's adjoint added to its interior cell or face
+// The forward face arrays (alpha+-, u*) of the state being differentiated come
+// from the forward face kernel.
+#include "ctmhd_adjoint_math.h"
 #include "ctmhd_host.h"
 
+namespace {
+
+struct AdjArrays {
+  double* v[8];        // adjoint of D: 5 cell fields, 3 face fields; 0 outside the interior
+  double* prim[8];     // rho, u0, u1, u2, p, bc0, bc1, bc2 of the state
+  double* ea[3][13];   // per edge direction: adjoints of uaB uaT ubL ubR baB baT bbL bbR
+                       // apa ama apb amb and of the edge EMF
+  double* fa[3][14];   // per face direction: adjoints of the left and right face states
+  double* bn[3];       // face-field adjoint, gathered per face
+  double* bj[3];       // face-field adjoint of the Ohmic terms (atomic accumulation)
+  double* ca[5];       // conserved-field adjoint per cell
+  double* cb[3];       // cell-centred field adjoint per cell
+};
+
+__device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
+  s3[0] = t % G.N[0];
+  const int q = t / G.N[0];
+  s3[1] = q % G.N[1];
+  s3[2] = q / G.N[1];
+}
+
+// ---------------------------------------------------------------------------
+// Cell primitives of the state (FP64, as cell_prim); 0 on the last layer of
+// each axis, which has no upper face.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+    k_adj_prim(State S, Geom G, AdjArrays X, double gamma, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  double rho = 0.0, u[3] = {0.0, 0.0, 0.0}, p = 0.0, bc[3] = {0.0, 0.0, 0.0};
+  if (s3[0] < G.N[0] - 1 && s3[1] < G.N[1] - 1 && s3[2] < G.N[2] - 1)
+    cell_prim(S, G, t, gamma, rho, u, p, bc);
+  X.prim[0][t] = rho;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    X.prim[1 + d][t] = u[d];
+    X.prim[5 + d][t] = bc[d];
+  }
+  X.prim[4][t] = p;
+}
+
+// Adjoint coef of j_c = (b_b[s] - b_b[s - st_a]) / dx_a - (b_a[s] - b_a[s - st_b]) / dx_b
+// (eq. resistivity:current-stencil; a = c+1, b = c+2) onto the face fields.
+__device__ __forceinline__ void etaj_adj(double* const bj[3], const Geom& G, int s, int c,
+                                         double coef) {
+  const int a = (c + 1) % 3, b = (c + 2) % 3;
+  atomicAdd(&bj[b][s], coef * G.idx[a]);
+  atomicAdd(&bj[b][s - G.st[a]], -coef * G.idx[a]);
+  atomicAdd(&bj[a][s], -coef * G.idx[b]);
+  atomicAdd(&bj[a][s - G.st[b]], coef * G.idx[b]);
+}
+
+// ---------------------------------------------------------------------------
+// Edges: EMF adjoint and the reverse of LD04 + Q26 (edge_emf).
+// ---------------------------------------------------------------------------
+template <int RECON>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_edge(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  const double dt = *W.dt;
+  int s3[3];
+  decode(G, t, s3);
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inside = inside && s3[d] >= G.g && s3[d] <= G.g + G.n[d];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!inside || s3[c] >= G.g + G.n[c]) {
+#pragma unroll
+      for (int q = 0; q < 13; ++q) X.ea[c][q][t] = 0.0;
+      continue;
+    }
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    const int sa = G.st[a], sb = G.st[b];
+    // the EMF enters the new face fields b_a at t, t - sb and b_b at t, t - sa
+    const double Eb = dt * ((X.v[5 + a][t] - X.v[5 + a][t - sb]) * G.idx[b] -
+                            (X.v[5 + b][t] - X.v[5 + b][t - sa]) * G.idx[a]);
+    double u[4], bv[4], al[4];
+    iface_along_d<RECON>(S.b[a], t, sb, bv[0], bv[1]);  // baB, baT
+    iface_along_d<RECON>(S.b[b], t, sa, bv[2], bv[3]);  // bbL, bbR
+    iface_along<RECON>(W.us[a], t, sb, u[0], u[1]);     // uaB, uaT
+    iface_along<RECON>(W.us[b], t, sa, u[2], u[3]);     // ubL, ubR
+    al[0] = tmax(W.ap[a][t - sb], W.ap[a][t]);
+    al[1] = tmax(W.am[a][t - sb], W.am[a][t]);
+    al[2] = tmax(W.ap[b][t - sa], W.ap[b][t]);
+    al[3] = tmax(W.am[b][t - sa], W.am[b][t]);
+    double ub[4] = {0.0, 0.0, 0.0, 0.0}, bb[4] = {0.0, 0.0, 0.0, 0.0};
+    double alb[4] = {0.0, 0.0, 0.0, 0.0};
+    q26_ld04_adj(u, bv, al, Eb, ub, bb, alb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      X.ea[c][q][t] = ub[q];
+      X.ea[c][4 + q][t] = bb[q];
+      X.ea[c][8 + q][t] = alb[q];
+    }
+    X.ea[c][12][t] = Eb;
+    if (eta > 0.0) etaj_adj(X.bj, G, t, c, eta * Eb);
+  }
+}
+
+// Adjoint of X[f] through the reconstructions along axis d that produce the
+// edge values whose adjoints are UP (upper value of the cell below the edge,
+// stored at the edge) and LO (lower value of the cell above the edge): the
+// cells f - st, f, f + st are the centres that read X[f].
+template <int RECON>
+__device__ __forceinline__ double gather_along(const double* Xv, const double* UP, const double* LO,
+                                               const Geom& G, const int s3[3], int f, int d) {
+  const int st = G.st[d], x0 = s3[d], N = G.N[d];
+  double acc = 0.0;
+#pragma unroll
+  for (int k = -1; k <= 1; ++k) {
+    const int cx = x0 + k;
+    const double up = (cx + 1 >= 0 && cx + 1 < N) ? UP[f + (k + 1) * st] : 0.0;
+    const double lo = (cx >= 0 && cx < N) ? LO[f + k * st] : 0.0;
+    if (up == 0.0 && lo == 0.0) continue;
+    if (k == 0) acc += up + lo;
+    if constexpr (RECON == kPLM_MC || RECON == kPLM_MM) {
+      if (cx - 1 < 0 || cx + 1 >= N) continue;
+      double dm, d0, dp;
+      plm_slope_partials<RECON>(Xv[f + (k - 1) * st], Xv[f + k * st], Xv[f + (k + 1) * st], dm, d0,
+                                dp);
+      acc += 0.5 * (up - lo) * (k == -1 ? dp : (k == 0 ? d0 : dm));
+    }
+  }
+  return acc;
+}
+
+// Adjoint of a face value v[f] read as one of the two arguments of an edge
+// speed max(v[e - st], v[e]) at the edges e = f + st and e = f (axis d).
+__device__ __forceinline__ double gather_max(const double* V, const double* AB, const Geom& G,
+                                             const int s3[3], int f, int d) {
+  const int st = G.st[d];
+  double acc = 0.0;
+  if (s3[d] + 1 < G.N[d]) {
+    const double g = AB[f + st];
+    if (g != 0.0 && V[f] >= V[f + st]) acc += g;  // first argument at edge f + st
+  }
+  if (s3[d] >= 1) {
+    const double g = AB[f];
+    if (g != 0.0 && !(V[f - st] >= V[f])) acc += g;  // second argument at edge f
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Faces: flux adjoint, gathered u* / alpha / face-field adjoints, Riemann
+// solver in reverse, Joule flux in reverse.
+// ---------------------------------------------------------------------------
+template <int RECON, int RIEMANN>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_face(State S, Geom G, Work<double> W, AdjArrays X, double gamma, double eta,
+               const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  const double dt = *W.dt;
+  int s3[3];
+  decode(G, t, s3);
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const int sa = G.st[a];
+    // faces read by the update: [g, g+n] along the normal, [g, g+n) across
+    const bool upd = s3[a] >= G.g && s3[a] <= G.g + G.n[a] && s3[b] >= G.g &&
+                     s3[b] < G.g + G.n[b] && s3[c] >= G.g && s3[c] < G.g + G.n[c];
+    double Fb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (upd) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Fb[m] = dt * G.idx[a] * (X.v[m][t] - X.v[m][t - sa]);
+    }
+    // edges of direction c read this face's arrays along b, those of
+    // direction b read them along c
+    const double usb = gather_along<RECON>(W.us[a], X.ea[c][0], X.ea[c][1], G, s3, t, b) +
+                       gather_along<RECON>(W.us[a], X.ea[b][2], X.ea[b][3], G, s3, t, c);
+    const double bfb = gather_along<RECON>(S.b[a], X.ea[c][4], X.ea[c][5], G, s3, t, b) +
+                       gather_along<RECON>(S.b[a], X.ea[b][6], X.ea[b][7], G, s3, t, c);
+    const double apb = gather_max(W.ap[a], X.ea[c][8], G, s3, t, b) +
+                       gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
+    const double amb = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
+                       gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
+    FState<double> Lb, Rb;
+    fstate_zero(Lb);
+    fstate_zero(Rb);
+    double bnb = 0.0;
+    const bool any = Fb[0] != 0.0 || Fb[1] != 0.0 || Fb[2] != 0.0 || Fb[3] != 0.0 ||
+                     Fb[4] != 0.0 || usb != 0.0 || apb != 0.0 || amb != 0.0;
+    constexpr int r = recon_halfwidth(RECON);
+    if (any && s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1) {
+      // face-local states as the forward face kernel forms them
+      const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+      double qL[7], qR[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        const double* P = X.prim[vmap[q]];
+        double w[5], lo, hi;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) w[k] = 0.0;
+        // upper value of cell t - sa from (t - 2sa, t - sa, t)
+        w[1] = r ? P[t - 2 * sa] : 0.0;
+        w[2] = P[t - sa];
+        w[3] = r ? P[t] : 0.0;
+        recon_cell<RECON>(w, lo, hi);
+        qL[q] = hi;
+        // lower value of cell t from (t - sa, t, t + sa)
+        w[1] = r ? P[t - sa] : 0.0;
+        w[2] = P[t];
+        w[3] = r ? P[t + sa] : 0.0;
+        recon_cell<RECON>(w, lo, hi);
+        qR[q] = lo;
+      }
+      const FState<double> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
+      const FState<double> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
+      const double Fl[5] = {Fb[0], Fb[1 + a], Fb[1 + b], Fb[1 + c], Fb[4]};
+      face_outputs_adj<RIEMANN>(L, R, S.b[a][t], gamma, Fl, apb, amb, usb, Lb, Rb, bnb);
+    }
+    X.fa[a][0][t] = Lb.rho;
+    X.fa[a][1][t] = Lb.un;
+    X.fa[a][2][t] = Lb.ut1;
+    X.fa[a][3][t] = Lb.ut2;
+    X.fa[a][4][t] = Lb.p;
+    X.fa[a][5][t] = Lb.bt1;
+    X.fa[a][6][t] = Lb.bt2;
+    X.fa[a][7][t] = Rb.rho;
+    X.fa[a][8][t] = Rb.un;
+    X.fa[a][9][t] = Rb.ut1;
+    X.fa[a][10][t] = Rb.ut2;
+    X.fa[a][11][t] = Rb.p;
+    X.fa[a][12][t] = Rb.bt1;
+    X.fa[a][13][t] = Rb.bt2;
+    X.bn[a][t] = bnb + bfb;
+    if (eta > 0.0 && upd && Fb[4] != 0.0) {
+      // Joule flux (joule): J = eb (bcl + bcr)/2 - ec (bbl + bbr)/2
+      const double Jb = Fb[4];
+      const int sb = G.st[b], sc = G.st[c], l = t - sa;
+      const double eb = 0.5 * (eta_j<double>(S, G, t, b, eta) + eta_j<double>(S, G, t + sc, b, eta));
+      const double ec = 0.5 * (eta_j<double>(S, G, t, c, eta) + eta_j<double>(S, G, t + sb, c, eta));
+      const double bbl = 0.5 * (S.b[b][l] + S.b[b][l + sb]), bbr = 0.5 * (S.b[b][t] + S.b[b][t + sb]);
+      const double bcl = 0.5 * (S.b[c][l] + S.b[c][l + sc]), bcr = 0.5 * (S.b[c][t] + S.b[c][t + sc]);
+      const double ebb = Jb * 0.5 * (bcl + bcr), ecb = -Jb * 0.5 * (bbl + bbr);
+      const double qc = 0.25 * Jb * eb, qb = -0.25 * Jb * ec;
+      atomicAdd(&X.bj[c][l], qc);
+      atomicAdd(&X.bj[c][l + sc], qc);
+      atomicAdd(&X.bj[c][t], qc);
+      atomicAdd(&X.bj[c][t + sc], qc);
+      atomicAdd(&X.bj[b][l], qb);
+      atomicAdd(&X.bj[b][l + sb], qb);
+      atomicAdd(&X.bj[b][t], qb);
+      atomicAdd(&X.bj[b][t + sb], qb);
+      etaj_adj(X.bj, G, t, b, eta * 0.5 * ebb);
+      etaj_adj(X.bj, G, t + sc, b, eta * 0.5 * ebb);
+      etaj_adj(X.bj, G, t, c, eta * 0.5 * ecb);
+      etaj_adj(X.bj, G, t + sb, c, eta * 0.5 * ecb);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cells: face-state adjoints through the reverse of the reconstructions, then
+// primitive -> conserved.
+// ---------------------------------------------------------------------------
+template <int RECON>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_cell(State S, Geom G, AdjArrays X, double gamma, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  double pb[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+      // the left state of face e is the upper value of cell e - st, the right
+      // state the lower value of cell e
+      pb[vmap[q]] += gather_along<RECON>(X.prim[vmap[q]], X.fa[a][q], X.fa[a][7 + q], G, s3, t, a);
+  }
+  const bool valid = s3[0] < G.N[0] - 1 && s3[1] < G.N[1] - 1 && s3[2] < G.N[2] - 1;
+  if (!valid) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) X.ca[m][t] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X.cb[d][t] = 0.0;
+    return;
+  }
+  // p = (gamma - 1) (e - rho |u|^2 / 2 - |bc|^2 / 2), u = m / rho
+  const double rho = X.prim[0][t], p_b = pb[4], gm1 = gamma - 1.0;
+  const double u[3] = {X.prim[1][t], X.prim[2][t], X.prim[3][t]};
+  const double bc[3] = {X.prim[5][t], X.prim[6][t], X.prim[7][t]};
+  double rb = pb[0] + 0.5 * gm1 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * p_b;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rb -= pb[1 + d] * u[d] / rho;
+    X.ca[1 + d][t] = pb[1 + d] / rho - gm1 * p_b * u[d];
+    X.cb[d][t] = pb[5 + d] - gm1 * p_b * bc[d];
+  }
+  X.ca[0][t] = rb;
+  X.ca[4][t] = gm1 * p_b;
+}
+
+// Face-field adjoint: gathered + Ohmic + half of each adjacent cell's
+// cell-centred adjoint (bc_a = (b_a[lower] + b_a[upper]) / 2).
+__global__ void __launch_bounds__(kBlock) k_adj_bsum(Geom G, AdjArrays X, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    X.bn[a][t] += X.bj[a][t] + 0.5 * (X.cb[a][t] + (s3[a] >= 1 ? X.cb[a][t - G.st[a]] : 0.0));
+}
+
+// Load v = scale * g (interior values; 0 on ghost positions).
+__global__ void __launch_bounds__(kBlock)
+    k_adj_load(Geom G, State v, State g, double scale, const int* stop) {
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  bool inter = !*stop;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inter = inter && s3[d] >= G.g && s3[d] < G.g + G.n[d];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) v.c[m][t] = inter ? scale * g.c[m][t] : 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v.b[a][t] = inter ? scale * g.b[a][t] : 0.0;
+}
+
+// out = c2 g2 + c1 g1 + (sum over all periodic copies of the interior
+// position of the cell / face adjoints) on interior positions, 0 elsewhere.
+// A stopped call (non-finite dt) writes NaN.
+__global__ void __launch_bounds__(kBlock)
+    k_adj_fold(Geom G, State out, State g2, double c2, State g1, double c1, AdjArrays X,
+               const int* stop) {
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  bool inter = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) inter = inter && s3[d] >= G.g && s3[d] < G.g + G.n[d];
+  double vc[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0};
+  if (inter) {
+    if (*stop) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) vc[m] = __builtin_nan("");
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vb[a] = __builtin_nan("");
+    } else {
+      int mlo[3], mhi[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        mlo[d] = -(s3[d] / G.n[d]);
+        mhi[d] = (G.N[d] - 1 - s3[d]) / G.n[d];
+      }
+      for (int mz = mlo[2]; mz <= mhi[2]; ++mz)
+        for (int my = mlo[1]; my <= mhi[1]; ++my)
+          for (int mx = mlo[0]; mx <= mhi[0]; ++mx) {
+            const int w = t + mx * G.n[0] + my * G.n[1] * G.st[1] + mz * G.n[2] * G.st[2];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) vc[m] += X.ca[m][w];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) vb[a] += X.bn[a][w];
+          }
+#pragma unroll
+      for (int m = 0; m < 5; ++m) vc[m] += c2 * g2.c[m][t] + (c1 != 0.0 ? c1 * g1.c[m][t] : 0.0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vb[a] += c2 * g2.b[a][t] + (c1 != 0.0 ? c1 * g1.b[a][t] : 0.0);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) out.c[m][t] = vc[m];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out.b[a][t] = vb[a];
+}
+
+__global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
+  const int t = gidx();
+  if (t >= G.elems) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) X.bj[a][t] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3;  // V, G1, prim, ea, fa, bn, bj, ca, cb
+
+size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
+  size_t e = 1;
+  for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
+  return box_ws_bytes(b, 8, p->emf_compute) + (size_t)kAdjArrays * align256(e * 8);
+}
+
+int check_adjoint(const ctmhd_params* p) {
+  if (p->precision != CTMHD_FP64)
+    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the FP64 form only");
+  if (p->recon != CTMHD_RECON_PC && p->recon != CTMHD_RECON_PLM_MC &&
+      p->recon != CTMHD_RECON_PLM_MINMOD)
+    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for PC and PLM reconstruction only");
+  if (p->emf_compute != CTMHD_EMF_Q26)
+    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the Q26 EMF only");
+  return CTMHD_OK;
+}
+
+// D'(S)^T v into X.ca / X.bn (ghosted), given the forward face arrays of S in W.
+template <int RECON, int RIEMANN>
+int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<double>& W,
+          const AdjArrays& X) {
+  const int nb = nblocks(G.elems);
+  LAUNCH(k_adj_zero3, nb, G, X);
+  LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
+  LAUNCH(k_adj_edge<RECON>, nb, S, G, W, X, p->eta, W.stop);
+  LAUNCH((k_adj_face<RECON, RIEMANN>), nb, S, G, W, X, p->gamma, p->eta, W.stop);
+  LAUNCH(k_adj_cell<RECON>, nb, S, G, X, p->gamma, W.stop);
+  LAUNCH(k_adj_bsum, nb, G, X, W.stop);
+  return CTMHD_OK;
+}
+
+template <int RECON, int RIEMANN>
+int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* const cons_n[5],
+                const double* const bface_n[3], const double* dt, const double* const g_cons[5],
+                const double* const g_bface[3], double* const g_cons_out[5],
+                double* const g_bface_out[3], void* ws, size_t ws_bytes, hipStream_t st) {
+  ctmhd_params pp = *p_in;
+  pp.fofc = 0;  // the differentiated step takes no flux correction
+  const ctmhd_params* p = &pp;
+  const Geom G = make_geom(*box);
+  if (!ws || ws_bytes < adj_ws_bytes(p, *box)) return fail(CTMHD_EARG, "workspace too small");
+  Work<double> W;
+  State A, H;
+  int rc = build_work<double>(p, ws, ws_bytes, *box, W, A, H);
+  if (rc) return rc;
+  const size_t e = (size_t)G.elems;
+  Carve cv{(char*)ws + box_ws_bytes(*box, 8, p->emf_compute)};
+  State V, G1;
+  AdjArrays X;
+  for (int m = 0; m < 5; ++m) V.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) V.b[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) G1.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) G1.b[a] = cv.take<double>(e);
+  for (int v = 0; v < 8; ++v) X.prim[v] = cv.take<double>(e);
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 13; ++q) X.ea[c][q] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a)
+    for (int q = 0; q < 14; ++q) X.fa[a][q] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) X.bn[a] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) X.bj[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) X.ca[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
+
+  State S0, Gin, Gout;
+  for (int m = 0; m < 5; ++m) {
+    S0.c[m] = const_cast<double*>(cons_n[m]);
+    Gin.c[m] = const_cast<double*>(g_cons[m]);
+    Gout.c[m] = g_cons_out[m];
+  }
+  for (int a = 0; a < 3; ++a) {
+    S0.b[a] = const_cast<double*>(bface_n[a]);
+    Gin.b[a] = const_cast<double*>(g_bface[a]);
+    Gout.b[a] = g_bface_out[a];
+  }
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
+  const int ninter = G.n[0] * G.n[1] * G.n[2];
+  const int nb = nblocks(G.elems);
+  UpdateCfg U;
+  U.fofc = 0;
+  U.crit = p->flag_criteria;
+  U.gamma = p->gamma;
+  U.sres = 0.0;
+  U.force = nullptr;
+
+  // forward: S0 with ghosts, the caller's dt, stage 1 into H = S1
+  LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
+  LAUNCH(k_copy, nb, A, S0, G.elems, (const int*)nullptr);
+  LAUNCH(k_wrap, nb, A, G, W.stop);
+  LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, (double*)nullptr, W.stop,
+         (long long*)nullptr);
+  if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
+  if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
+  LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
+  // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
+  if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
+  LAUNCH(k_adj_load, nb, G, V, Gin, 0.5, W.stop);
+  for (int m = 0; m < 5; ++m) X.v[m] = V.c[m];
+  for (int a = 0; a < 3; ++a) X.v[5 + a] = V.b[a];
+  if ((rc = vjp_d<RECON, RIEMANN>(st, p, H, G, W, X))) return rc;
+  LAUNCH(k_adj_fold, nb, G, G1, Gin, 0.5, Gin, 0.0, X, W.stop);
+  // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
+  if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
+  for (int m = 0; m < 5; ++m) X.v[m] = G1.c[m];
+  for (int a = 0; a < 3; ++a) X.v[5 + a] = G1.b[a];
+  if ((rc = vjp_d<RECON, RIEMANN>(st, p, A, G, W, X))) return rc;
+  LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, G1, 1.0, X, W.stop);
+  return CTMHD_OK;
+}
+
+template <int RECON>
+int adjoint_riemann(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],
+                    const double* const bface_n[3], const double* dt,
+                    const double* const g_cons[5], const double* const g_bface[3],
+                    double* const g_cons_out[5], double* const g_bface_out[3], void* ws,
+                    size_t ws_bytes, hipStream_t st) {
+  if (p->riemann == CTMHD_RIEMANN_HLLD)
+    return adjoint_box<RECON, kHLLD>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                     g_bface_out, ws, ws_bytes, st);
+  return adjoint_box<RECON, kLLF>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                  g_bface_out, ws, ws_bytes, st);
+}
+
+}  // namespace
+
 extern "C" {
+
+size_t ctmhd_adjoint_workspace_bytes(const ctmhd_params* p, const ctmhd_box* box) {
+  if (check_params(p) || check_adjoint(p) || check_box(p, box)) return 0;
+  return adj_ws_bytes(p, *box);
+}
 
 int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],
                        const double* const bface_n[3], const double* dt,
                        const double* const g_cons[5], const double* const g_bface[3],
                        double* const g_cons_out[5], double* const g_bface_out[3], void* workspace,
                        size_t ws_bytes, void* stream) {
-  (void)p; (void)box; (void)cons_n; (void)bface_n; (void)dt; (void)g_cons; (void)g_bface;
-  (void)g_cons_out; (void)g_bface_out; (void)workspace; (void)ws_bytes; (void)stream;
-  return fail(CTMHD_EUNSUPPORTED, "ctmhd_step_adjoint is not built yet");
+  g_err[0] = 0;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_adjoint(p))) return rc;
+  if ((rc = check_box(p, box))) return rc;
+  if (!cons_n || !bface_n || !g_cons || !g_bface || !g_cons_out || !g_bface_out || !dt)
+    return fail(CTMHD_EARG, "a pointer argument is NULL");
+  for (int m = 0; m < 5; ++m)
+    if (!cons_n[m] || !g_cons[m] || !g_cons_out[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!bface_n[a] || !g_bface[a] || !g_bface_out[a])
+      return fail(CTMHD_EARG, "a bface pointer is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  switch (p->recon) {
+    case CTMHD_RECON_PC:
+      return adjoint_riemann<kPC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                  g_bface_out, workspace, ws_bytes, st);
+    case CTMHD_RECON_PLM_MC:
+      return adjoint_riemann<kPLM_MC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                      g_bface_out, workspace, ws_bytes, st);
+    default:
+      return adjoint_riemann<kPLM_MM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                      g_bface_out, workspace, ws_bytes, st);
+  }
 }
 
 }  // extern "C"

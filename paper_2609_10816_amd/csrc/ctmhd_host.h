@@ -190,4 +190,31 @@ FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min) {
   return P;
 }
 
+template <typename T, int RECON>
+int launch_faces(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
+                 const FacePlan& FP, int stage, long long* diag) {
+  prof_begin(st);
+  if (p->riemann == CTMHD_RIEMANN_HLLD)
+    LAUNCH((k_faces<T, RECON, kHLLD>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta, diag,
+           W.stop);
+  else
+    LAUNCH((k_faces<T, RECON, kLLF>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta, diag,
+           W.stop);
+  prof_end(st);
+  return CTMHD_OK;
+}
+
+template <typename T, int RECON>
+int launch_emf(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
+               int stage) {
+  const int cnt = (G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
+  if (p->emf_compute == CTMHD_EMF_Q26)
+    LAUNCH((k_emf3<T, RECON, kQ26>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
+  else if (p->emf_compute == CTMHD_EMF_B25A)
+    LAUNCH((k_emf3<T, RECON, kB25A>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
+  else
+    LAUNCH((k_emf3<T, RECON, kFS18>), nblocks(cnt), S, G, W, stage, p->eta, W.stop);
+  return CTMHD_OK;
+}
+
 }  // namespace

@@ -74,6 +74,8 @@ def lib():
         L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
                                          _vp, ctypes.c_size_t, _vp]
         L.ctmhd_step_adjoint.restype = ctypes.c_int
+        L.ctmhd_adjoint_workspace_bytes.argtypes = [_P, _B]
+        L.ctmhd_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.ctmhd_profile_events.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
         L.ctmhd_profile_events.restype = ctypes.c_int
         L.ctmhd_profile_recorded.argtypes = []
@@ -86,7 +88,7 @@ def lib():
 
 EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
             "ctmhd_batch_plan_bytes", "ctmhd_batch_plan", "ctmhd_step_batched",
-            "ctmhd_step_adjoint", "ctmhd_profile_events",
+            "ctmhd_step_adjoint", "ctmhd_adjoint_workspace_bytes", "ctmhd_profile_events",
             "ctmhd_profile_recorded", "ctmhd_last_error")
 
 
@@ -174,6 +176,10 @@ def ctmhd_step_batched(params: Params, boxes, plan, cons, bface, nsteps, dt_mode
                                   int(nsteps), int(dt_mode), _p(dt_fixed), _p(dt_out), _p(diag),
                                   _p(ws), ws.numel() if ws is not None else 0, _stream(stream))
     return _check(rc)
+
+
+def adjoint_workspace_bytes(params: Params, box: Box) -> int:
+    return int(lib().ctmhd_adjoint_workspace_bytes(ctypes.byref(params), ctypes.byref(box)))
 
 
 def ctmhd_step_adjoint(params: Params, box: Box, cons_n, bface_n, dt, g_cons, g_bface,

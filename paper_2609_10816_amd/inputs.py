@@ -336,3 +336,40 @@ def amr_like_boxes(nbox=2000, seed=4, dx=1.0 / 64.0, sizes=(8, 16, 32, 64), gamm
         p = np.full(rho.shape, p0)
         out.append((from_primitives(rho, u, p, bf, gamma), bf, (dx, dx, dx)))
     return out
+
+
+def smooth_modes_box(n, amp=0.05, beta=1.0, seed=5, nmodes=3, L=(1.0, 1.0, 1.0), gamma=GAMMA):
+    """A smooth periodic box for the derivative workload: rho = 1 + amp S,
+    u_d = amp S_d, p = p0 (1 + amp S_p) with p0 = 1/gamma (sound speed 1),
+    b = b0 x + curl A with |b0| = sqrt(2 p0 / beta) and
+    A_c = amp |b0| L_min / (2 pi) S_Ac, where each S is a sum of `nmodes` sine
+    modes with integer wave vectors whose components are all non-zero (each
+    +-1 or +-2) and uniform random phases.  Every field varies along every
+    axis, so no limiter or min/max of the step sits exactly at a tie (a field
+    constant along an axis puts every limiter along it at dl = dr = 0, where
+    the derivative of the step is not unique).  Returns (cons, bface, info)."""
+    n = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    L = tuple(float(v) for v in L)
+    rng = np.random.default_rng(seed)
+
+    def modes():
+        ks = [rng.integers(1, 3, size=3) * rng.choice([-1, 1], size=3) for _ in range(nmodes)]
+        return ks, rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+
+    def series(ks, ph, x):
+        return sum(np.sin(2.0 * np.pi * (k[0] * x[0] / L[0] + k[1] * x[1] / L[1] +
+                                         k[2] * x[2] / L[2]) + f) for k, f in zip(ks, ph))
+
+    xc = _coords(n, L)
+    rho = 1.0 + amp * series(*modes(), xc)
+    u = np.stack([amp * series(*modes(), xc) for _ in range(3)])
+    p0 = 1.0 / gamma
+    p = p0 * (1.0 + amp * series(*modes(), xc))
+    bmag = math.sqrt(2.0 * p0 / beta)
+    dx = [L[d] / n[d] for d in range(3)]
+    A = np.zeros((3, n[2], n[1], n[0]))
+    for c in range(3):
+        A[c] = amp * bmag * min(L) / (2.0 * np.pi) * series(*modes(), edge_coords(n, c, L))
+    bf = curl_edges(A, dx)
+    bf[0] += bmag
+    return from_primitives(rho, u, p, bf, gamma), bf, {"dx": dx, "b0": bmag}
