@@ -2,7 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb128|turb256|turb512]
                 [--precision fp64|fp32] [--emf q26|b25a|fs18] [--no-cpu-baseline]
-                [--no-fp32] [--copy-calibration]
+                [--no-fp32] [--no-batched] [--no-adjoint] [--copy-calibration]
 
 Prints ONE JSON line.  A step is one full RK2-SSP step with first-order flux
 correction on a seeded synthetic state already resident in HBM: CFL dt
@@ -20,6 +20,13 @@ around every launch inside the timed region.  The path is bound by FP64
 vector ALU throughput (peak 78.6 TFLOP/s on MI355X), not by HBM.
 traffic: HBM bytes per launch from the committed rocprofv3 counter summary
 of the same kernel source, or null if the kernel source has changed since.
+
+Beside the headline line's FP64 value the same JSON line carries the other
+forms: fp32_form (the same workload in the FP32 form), batched_form (2000
+AMR-like boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against
+one ctmhd_step call per box) and adjoint_form (64^3 gradient of the kinetic
+energy after 20 steps through the hand-written adjoint, backward / forward
+time).
 """
 from __future__ import annotations
 
@@ -220,20 +227,80 @@ def run_batched_form(K, W, log_tune=True):
     return out
 
 
-def cpu_baseline(cfg, emf, state):
-    """The oracle (plain FP64 C++, OpenMP over z-planes) on one step of the
-    same state."""
+def run_adjoint_form(nsteps=20, every=5, reps=2):
+    """The derivative workload: 64^3 smooth periodic box (3 sine modes of
+    amplitude 0.05 per field, beta = 1), PLM-MC + HLLD + Q26 + LD04, FP64, no
+    flux correction; loss = total kinetic energy after `nsteps` steps; the
+    gradient with respect to the initial velocity and face field through the
+    hand-written adjoint with a checkpoint every `every` steps.  Times the
+    forward rollout alone and the backward pass (recomputation + adjoint
+    steps); the last of `reps` repetitions is reported."""
+    import numpy as np
+    import torch
+
+    from paper_2609_10816_amd import autograd as ad
+    from paper_2609_10816_amd import ctmhd, inputs
+
+    n = 64
+    cons, bf, info = inputs.smooth_modes_box(n, amp=0.05, beta=1.0, seed=5)
+    dx = info["dx"]
+    dev = "cuda"
+    rho = torch.tensor(cons[0], device=dev)
+    u0 = torch.tensor(cons[1:4] / cons[0], device=dev)
+    bc = np.stack([0.5 * (bf[a] + np.roll(bf[a], -1, axis=2 - a)) for a in range(3)])
+    p = torch.tensor((5.0 / 3.0 - 1.0) * (cons[4] - 0.5 * (cons[1:4] ** 2).sum(0) / cons[0] -
+                                          0.5 * (bc ** 2).sum(0)), device=dev)
+    b0 = torch.tensor(bf, device=dev)
+    P = ctmhd.make_params(recon="plm", riemann="hlld", emf="q26", eta=0.0, fofc=False)
+    res = {}
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.no_grad():
+            ad.rollout(ad.conserved_from_primitives(rho, u0, p, b0), b0, P, dx, nsteps, every=every)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        u = u0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, nsteps, every=every)
+        ke = ad.kinetic_energy(c, dx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ke.backward()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t1
+        res = {"forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "ratio": tb / tf,
+               "grad_norm_u": float(u.grad.norm()), "grad_norm_b": float(b.grad.norm())}
+    log(f"adjoint form: forward {res['forward_ms']:.1f} ms, backward {res['backward_ms']:.1f} ms "
+        f"(ratio {res['ratio']:.2f})")
+    return {"workload": "smooth-64^3-amp0.05-beta1-plm-hlld-q26-ld04", "dtype": "f64",
+            "steps": nsteps, "checkpoint_every": every,
+            "loss": "total kinetic energy after the steps",
+            "gradient": "d loss / d (initial velocity, initial face field)",
+            "forward_ms": res["forward_ms"], "backward_ms": res["backward_ms"],
+            "ratio_backward_to_forward": res["ratio"],
+            "grad_norm_u": res["grad_norm_u"], "grad_norm_b": res["grad_norm_b"]}
+
+
+def cpu_baseline(cfg, emf, state, min_seconds=10.0, max_steps=20):
+    """The oracle (plain FP64 C++, OpenMP over z-planes) on the same state,
+    one step at a time until at least `min_seconds` of CPU work (at most
+    `max_steps` steps)."""
     import oracle
     cons, bf, info = state
     Q = oracle.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3)
-    t0 = time.perf_counter()
-    oracle.step(Q, cons, bf, info["dx"], nsteps=1)
-    el = time.perf_counter() - t0
     n3 = cfg["n"] ** 3
-    return {"value": n3 / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+    el, steps = 0.0, 0
+    c, b = cons, bf
+    while el < min_seconds and steps < max_steps:
+        t0 = time.perf_counter()
+        c, b, _, _ = oracle.step(Q, c, b, info["dx"], nsteps=1)
+        el += time.perf_counter() - t0
+        steps += 1
+    return {"value": n3 * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"1 step of the full {cfg['n']}^3 box ({n3 / 1e6:.2f} M cell-updates), "
-                      f"{el:.1f} s"}
+            "sample": f"{steps} steps of the full {cfg['n']}^3 box "
+                      f"({n3 * steps / 1e6:.2f} M cell-updates), {el:.1f} s"}
 
 
 def main():
@@ -248,6 +315,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -289,7 +357,7 @@ def main():
                    "cfl": 0.3, "eta": cfg["eta"], "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "face (reconstruction + Riemann, one direction, one stage)",
+                     "kernel": "face (reconstruction + Riemann, all three directions, one stage)",
                      "kernel_ms": res["kernel_ms"], "flops_per_face": face_flops,
                      "faces_per_launch": 3 * n3},
         "step_alu_frac": value * 1e6 * cell_update_flops / (PEAK_FP64_TFLOPS * 1e12),
@@ -308,6 +376,8 @@ def main():
         bf["speedup_fp32_vs_fp64_single_box_step"] = bf["fp32"]["value"] / value
         bf["speedup_vs_per_box_loop"] = bf["fp32"]["value"] / bf["per_box_loop_fp32"]["value"]
         out["batched_form"] = bf
+    if not args.no_adjoint:
+        out["adjoint_form"] = run_adjoint_form()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.emf, state)
     print(json.dumps(out), flush=True)

@@ -413,6 +413,18 @@ __global__ void __launch_bounds__(kBlock)
   for (int a = 0; a < 3; ++a) out.b[a][t] = vb[a];
 }
 
+// Copy of the forward face arrays alpha+, alpha-, u* (3 directions each).
+__global__ void __launch_bounds__(kBlock) k_adj_save9(Geom G, Work<double> W, Work<double> D) {
+  const int t = gidx();
+  if (t >= G.elems) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    D.ap[a][t] = W.ap[a][t];
+    D.am[a][t] = W.am[a][t];
+    D.us[a][t] = W.us[a][t];
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
   const int t = gidx();
   if (t >= G.elems) return;
@@ -423,7 +435,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3;  // V, G1, prim, ea, fa, bn, bj, ca, cb
+// V, G1, prim, ea, fa, bn, bj, ca, cb, saved face arrays of S0
+constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3 + 9;
 
 size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
   size_t e = 1;
@@ -487,6 +500,12 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   for (int a = 0; a < 3; ++a) X.bj[a] = cv.take<double>(e);
   for (int m = 0; m < 5; ++m) X.ca[m] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
+  Work<double> W0 = W;  // W with the face arrays of S0 (saved after its face pass)
+  for (int a = 0; a < 3; ++a) {
+    W0.ap[a] = cv.take<double>(e);
+    W0.am[a] = cv.take<double>(e);
+    W0.us[a] = cv.take<double>(e);
+  }
 
   State S0, Gin, Gout;
   for (int m = 0; m < 5; ++m) {
@@ -516,6 +535,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, (double*)nullptr, W.stop,
          (long long*)nullptr);
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
+  LAUNCH(k_adj_save9, nb, G, W, W0);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
@@ -526,10 +546,9 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   if ((rc = vjp_d<RECON, RIEMANN>(st, p, H, G, W, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, G1, Gin, 0.5, Gin, 0.0, X, W.stop);
   // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
-  if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   for (int m = 0; m < 5; ++m) X.v[m] = G1.c[m];
   for (int a = 0; a < 3; ++a) X.v[5 + a] = G1.b[a];
-  if ((rc = vjp_d<RECON, RIEMANN>(st, p, A, G, W, X))) return rc;
+  if ((rc = vjp_d<RECON, RIEMANN>(st, p, A, G, W0, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, G1, 1.0, X, W.stop);
   return CTMHD_OK;
 }

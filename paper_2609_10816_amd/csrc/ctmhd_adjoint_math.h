@@ -658,8 +658,10 @@ template <int RIEMANN, typename T>
 CTMHD_HD void face_outputs_adj(const FState<T>& L, const FState<T>& R, T bn, T gamma, const T Fb[5],
                                T apb, T amb, T usb, FState<T>& Lb, FState<T>& Rb, T& bnb) {
   if (RIEMANN == kHLLD) {
-    T F[5], SL, SR;
-    hlld_flux(L, R, bn, gamma, F, SL, SR);
+    // the outer speeds with the operations of hlld_flux (eq. emf:alpha-pm)
+    const T cmax = tmax(fast_speed(L.rho, L.p, bn, L.bt1, L.bt2, gamma),
+                        fast_speed(R.rho, R.p, bn, R.bt1, R.bt2, gamma));
+    const T SL = tmin(L.un, R.un) - cmax, SR = tmax(L.un, R.un) + cmax;
     const T ap = tmax(T(0), SR), am = tmax(T(0), -SL);
     const T isum = T(1) / (ap + am);
     const T us = (ap * L.un + am * R.un) * isum;
