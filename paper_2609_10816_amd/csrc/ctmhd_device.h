@@ -46,6 +46,19 @@ Geom make_geom(const ctmhd_box& b) {
 
 __device__ __forceinline__ int gidx() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Workgroups are dispatched to the 8 XCDs of the chip round-robin (workgroup
+// i on XCD i mod 8), and each XCD has its own L2.  This permutation of the
+// tiles of a launch gives each XCD a contiguous run of them, so that the
+// neighbouring rows and planes a stencil reads were brought into the same
+// L2.  It is a bijection on [0, gridDim.x): results do not depend on it.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile() {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int per = nb / kXcds;
+  if (b >= per * kXcds) return b;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 struct State {
   double* c[5];
   double* b[3];
@@ -621,7 +634,7 @@ template <typename T, int RECON, int EMF>
 __global__ void __launch_bounds__(kBlock)
     k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
   if (*stop) return;
-  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, gidx());
+  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, xcd_tile() * kBlock + (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,7 +794,7 @@ __global__ void __launch_bounds__(kBlock)
              UpdateCfg U, long long* diag, const int* stop) {
   if (*stop) return;
   if (fixup && W.nflag[stage] == 0) return;
-  update_item<T>(base, half, out, G, W, stage, fixup, U, diag, blockIdx.x, 1,
+  update_item<T>(base, half, out, G, W, stage, fixup, U, diag, xcd_tile(), 1,
                  W.smax + (fixup ? kMaxSlots : 0), blockIdx.x % kMaxSlots);
 }
 
