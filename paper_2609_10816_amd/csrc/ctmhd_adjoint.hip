@@ -179,21 +179,23 @@ __device__ __forceinline__ double gather_max(const double* V, const double* AB, 
 }
 
 // ---------------------------------------------------------------------------
-// Faces: flux adjoint, gathered u* / alpha / face-field adjoints, Riemann
-// solver in reverse, Joule flux in reverse.
+// Faces, part 1 (direction blockIdx.y): flux adjoint from v (transposed
+// divergence), the u* / alpha / face-field adjoints gathered from the edges
+// that read them, and the Joule flux in reverse.  The inputs of the reverse Riemann solve are left in
+// fa[a][0..7] (5 local flux components, alpha+, alpha-, u*); the gathered
+// face-field adjoint goes to bn.
 // ---------------------------------------------------------------------------
-template <int RECON, int RIEMANN>
+template <int RECON>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_face(State S, Geom G, Work<double> W, AdjArrays X, double gamma, double eta,
-               const int* stop) {
+    k_adj_fgather(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
   const double dt = *W.dt;
   int s3[3];
   decode(G, t, s3);
-#pragma unroll 1
-  for (int a = 0; a < 3; ++a) {
+  {
+    const int a = (int)blockIdx.y;
     const int b = (a + 1) % 3, c = (a + 2) % 3;
     const int sa = G.st[a];
     // faces read by the update: [g, g+n] along the normal, [g, g+n) across
@@ -206,64 +208,19 @@ __global__ void __launch_bounds__(kBlock)
     }
     // edges of direction c read this face's arrays along b, those of
     // direction b read them along c
-    const double usb = gather_along<RECON>(W.us[a], X.ea[c][0], X.ea[c][1], G, s3, t, b) +
-                       gather_along<RECON>(W.us[a], X.ea[b][2], X.ea[b][3], G, s3, t, c);
-    const double bfb = gather_along<RECON>(S.b[a], X.ea[c][4], X.ea[c][5], G, s3, t, b) +
-                       gather_along<RECON>(S.b[a], X.ea[b][6], X.ea[b][7], G, s3, t, c);
-    const double apb = gather_max(W.ap[a], X.ea[c][8], G, s3, t, b) +
-                       gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
-    const double amb = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
-                       gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
-    FState<double> Lb, Rb;
-    fstate_zero(Lb);
-    fstate_zero(Rb);
-    double bnb = 0.0;
-    const bool any = Fb[0] != 0.0 || Fb[1] != 0.0 || Fb[2] != 0.0 || Fb[3] != 0.0 ||
-                     Fb[4] != 0.0 || usb != 0.0 || apb != 0.0 || amb != 0.0;
-    constexpr int r = recon_halfwidth(RECON);
-    if (any && s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1) {
-      // face-local states as the forward face kernel forms them
-      const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
-      double qL[7], qR[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) {
-        const double* P = X.prim[vmap[q]];
-        double w[5], lo, hi;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) w[k] = 0.0;
-        // upper value of cell t - sa from (t - 2sa, t - sa, t)
-        w[1] = r ? P[t - 2 * sa] : 0.0;
-        w[2] = P[t - sa];
-        w[3] = r ? P[t] : 0.0;
-        recon_cell<RECON>(w, lo, hi);
-        qL[q] = hi;
-        // lower value of cell t from (t - sa, t, t + sa)
-        w[1] = r ? P[t - sa] : 0.0;
-        w[2] = P[t];
-        w[3] = r ? P[t + sa] : 0.0;
-        recon_cell<RECON>(w, lo, hi);
-        qR[q] = lo;
-      }
-      const FState<double> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
-      const FState<double> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
-      const double Fl[5] = {Fb[0], Fb[1 + a], Fb[1 + b], Fb[1 + c], Fb[4]};
-      face_outputs_adj<RIEMANN>(L, R, S.b[a][t], gamma, Fl, apb, amb, usb, Lb, Rb, bnb);
-    }
-    X.fa[a][0][t] = Lb.rho;
-    X.fa[a][1][t] = Lb.un;
-    X.fa[a][2][t] = Lb.ut1;
-    X.fa[a][3][t] = Lb.ut2;
-    X.fa[a][4][t] = Lb.p;
-    X.fa[a][5][t] = Lb.bt1;
-    X.fa[a][6][t] = Lb.bt2;
-    X.fa[a][7][t] = Rb.rho;
-    X.fa[a][8][t] = Rb.un;
-    X.fa[a][9][t] = Rb.ut1;
-    X.fa[a][10][t] = Rb.ut2;
-    X.fa[a][11][t] = Rb.p;
-    X.fa[a][12][t] = Rb.bt1;
-    X.fa[a][13][t] = Rb.bt2;
-    X.bn[a][t] = bnb + bfb;
+    X.fa[a][0][t] = Fb[0];
+    X.fa[a][1][t] = Fb[1 + a];
+    X.fa[a][2][t] = Fb[1 + b];
+    X.fa[a][3][t] = Fb[1 + c];
+    X.fa[a][4][t] = Fb[4];
+    X.fa[a][5][t] = gather_max(W.ap[a], X.ea[c][8], G, s3, t, b) +
+                    gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
+    X.fa[a][6][t] = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
+                    gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
+    X.fa[a][7][t] = gather_along<RECON>(W.us[a], X.ea[c][0], X.ea[c][1], G, s3, t, b) +
+                    gather_along<RECON>(W.us[a], X.ea[b][2], X.ea[b][3], G, s3, t, c);
+    X.bn[a][t] = gather_along<RECON>(S.b[a], X.ea[c][4], X.ea[c][5], G, s3, t, b) +
+                 gather_along<RECON>(S.b[a], X.ea[b][6], X.ea[b][7], G, s3, t, c);
     if (eta > 0.0 && upd && Fb[4] != 0.0) {
       // Joule flux (joule): J = eb (bcl + bcr)/2 - ec (bbl + bbr)/2
       const double Jb = Fb[4];
@@ -288,6 +245,78 @@ __global__ void __launch_bounds__(kBlock)
       etaj_adj(X.bj, G, t + sb, c, eta * 0.5 * ecb);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Faces, part 2: the Riemann solver in reverse, one face of direction
+// blockIdx.y per thread.  Reads its inputs from fa[a][0..7], writes the
+// adjoints of the left and right face-local states to fa[a][0..13] and adds
+// the normal-field adjoint to bn.
+// ---------------------------------------------------------------------------
+template <int RECON, int RIEMANN>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_friemann(State S, Geom G, AdjArrays X, double gamma, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  const int a = (int)blockIdx.y;
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const int sa = G.st[a];
+  int s3[3];
+  decode(G, t, s3);
+  double Fl[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Fl[m] = X.fa[a][m][t];
+  const double apb = X.fa[a][5][t], amb = X.fa[a][6][t], usb = X.fa[a][7][t];
+  FState<double> Lb, Rb;
+  fstate_zero(Lb);
+  fstate_zero(Rb);
+  double bnb = 0.0;
+  const bool any = Fl[0] != 0.0 || Fl[1] != 0.0 || Fl[2] != 0.0 || Fl[3] != 0.0 ||
+                   Fl[4] != 0.0 || usb != 0.0 || apb != 0.0 || amb != 0.0;
+  constexpr int r = recon_halfwidth(RECON);
+  if (any && s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1) {
+    // face-local states as the forward face kernel forms them
+    const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+    double qL[7], qR[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const double* P = X.prim[vmap[q]];
+      double w[5], lo, hi;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) w[k] = 0.0;
+      // upper value of cell t - sa from (t - 2sa, t - sa, t)
+      w[1] = r ? P[t - 2 * sa] : 0.0;
+      w[2] = P[t - sa];
+      w[3] = r ? P[t] : 0.0;
+      recon_cell<RECON>(w, lo, hi);
+      qL[q] = hi;
+      // lower value of cell t from (t - sa, t, t + sa)
+      w[1] = r ? P[t - sa] : 0.0;
+      w[2] = P[t];
+      w[3] = r ? P[t + sa] : 0.0;
+      recon_cell<RECON>(w, lo, hi);
+      qR[q] = lo;
+    }
+    const FState<double> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
+    const FState<double> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
+    face_outputs_adj<RIEMANN>(L, R, S.b[a][t], gamma, Fl, apb, amb, usb, Lb, Rb, bnb);
+  }
+  X.fa[a][0][t] = Lb.rho;
+  X.fa[a][1][t] = Lb.un;
+  X.fa[a][2][t] = Lb.ut1;
+  X.fa[a][3][t] = Lb.ut2;
+  X.fa[a][4][t] = Lb.p;
+  X.fa[a][5][t] = Lb.bt1;
+  X.fa[a][6][t] = Lb.bt2;
+  X.fa[a][7][t] = Rb.rho;
+  X.fa[a][8][t] = Rb.un;
+  X.fa[a][9][t] = Rb.ut1;
+  X.fa[a][10][t] = Rb.ut2;
+  X.fa[a][11][t] = Rb.p;
+  X.fa[a][12][t] = Rb.bt1;
+  X.fa[a][13][t] = Rb.bt2;
+  X.bn[a][t] += bnb;
 }
 
 // ---------------------------------------------------------------------------
@@ -463,7 +492,12 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   LAUNCH(k_adj_zero3, nb, G, X);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
   LAUNCH(k_adj_edge<RECON>, nb, S, G, W, X, p->eta, W.stop);
-  LAUNCH((k_adj_face<RECON, RIEMANN>), nb, S, G, W, X, p->gamma, p->eta, W.stop);
+  // both face kernels take the direction from blockIdx.y
+  hipLaunchKernelGGL((k_adj_fgather<RECON>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
+                     W.stop);
+  hipLaunchKernelGGL((k_adj_friemann<RECON, RIEMANN>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, X,
+                     p->gamma, W.stop);
+  if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint faces");
   LAUNCH(k_adj_cell<RECON>, nb, S, G, X, p->gamma, W.stop);
   LAUNCH(k_adj_bsum, nb, G, X, W.stop);
   return CTMHD_OK;
