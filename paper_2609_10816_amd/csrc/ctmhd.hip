@@ -81,7 +81,7 @@ int step_box(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
   for (int m = 0; m < 5; ++m) A.c[m] = cons[m];
   for (int a = 0; a < 3; ++a) A.b[a] = bface[a];
   const State user = A;
-  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
   double dxmin = fmin(G.dx[0], fmin(G.dx[1], G.dx[2]));
   double sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
   const int ninter = G.n[0] * G.n[1] * G.n[2];

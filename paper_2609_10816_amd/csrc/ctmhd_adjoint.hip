@@ -552,7 +552,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
     Gin.b[a] = const_cast<double*>(g_bface[a]);
     Gout.b[a] = g_bface_out[a];
   }
-  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
   const int ninter = G.n[0] * G.n[1] * G.n[2];
   const int nb = nblocks(G.elems);
   UpdateCfg U;

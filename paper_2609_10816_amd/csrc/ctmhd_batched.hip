@@ -64,7 +64,8 @@ unsigned long long plan_key(const ctmhd_params* p, const ctmhd_box* boxes, int n
     const unsigned char* c = (const unsigned char*)v;
     for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
   };
-  const int f[6] = {p->recon, p->emf_compute, p->fofc, tile_strips(p), tile_chunk(p), nbox};
+  const int f[7] = {p->recon, p->emf_compute, p->fofc, tile_strips(p), tile_chunk(p),
+                   tile_xrows(p), nbox};
   mix(f, sizeof(f));
   for (int b = 0; b < nbox; ++b) {
     mix(boxes[b].n, sizeof(boxes[b].n));
@@ -210,7 +211,7 @@ int phase_items(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, const i
   for (int q = 0; q < nphase; ++q) items[q] = 0;
   for (int b = 0; b < nbox; ++b) {
     const Geom G = make_geom(boxes[b]);
-    const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p));
+    const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
     for (int q = 0; q < nphase; ++q) items[q] += item_count(kind[q], G, FP, per);
   }
   for (int q = 0; q < nphase; ++q)
@@ -414,7 +415,7 @@ int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, vo
     const ctmhd_box& bx = boxes[b];
     BoxDesc& d = desc[b];
     d.G = make_geom(bx);
-    d.FP = make_face_plan(d.G, p->recon, p->emf_compute, tile_chunk(p));
+    d.FP = make_face_plan(d.G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
     d.off = bx.offset;
     d.flag_off = flag_off;
     flag_off += box_inter_ll(bx);

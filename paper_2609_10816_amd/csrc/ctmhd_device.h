@@ -143,17 +143,43 @@ __global__ void k_copy(State dst, State src, int elems, const int* only_if_stop)
 // ---------------------------------------------------------------------------
 // Cell primitives from the conserved state (eq. state:primitive), FP64.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void cell_prim(const State& S, const Geom& G, int s, double gamma,
-                                          double& rho, double u[3], double& p, double bc[3]) {
-  rho = S.c[0][s];
+// The eleven loads behind the primitives of one cell: the conserved state
+// and the two faces of the cell along each axis.  Split from the arithmetic
+// so that a marching thread can issue the loads of its next cell before the
+// stores of the current one (the compiler cannot move loads of the state
+// across stores to the workspace, which it must assume may alias).
+struct CellRaw {
+  double c[5], bl[3], bh[3];
+};
+
+__device__ __forceinline__ void cell_load(const State& S, const Geom& G, int s, CellRaw& R) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) R.c[m] = S.c[m][s];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    R.bl[d] = S.b[d][s];
+    R.bh[d] = S.b[d][s + G.st[d]];
+  }
+}
+
+__device__ __forceinline__ void raw_prim(const CellRaw& R, double gamma, double& rho, double u[3],
+                                         double& p, double bc[3]) {
+  rho = R.c[0];
   double ir = 1.0 / rho;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    u[d] = S.c[1 + d][s] * ir;
-    bc[d] = 0.5 * (S.b[d][s] + S.b[d][s + G.st[d]]);
+    u[d] = R.c[1 + d] * ir;
+    bc[d] = 0.5 * (R.bl[d] + R.bh[d]);
   }
-  p = (gamma - 1.0) * (S.c[4][s] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
+  p = (gamma - 1.0) * (R.c[4] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) -
                        0.5 * (bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]));
+}
+
+__device__ __forceinline__ void cell_prim(const State& S, const Geom& G, int s, double gamma,
+                                          double& rho, double u[3], double& p, double bc[3]) {
+  CellRaw R;
+  cell_load(S, G, s, R);
+  raw_prim(R, gamma, rho, u, p, bc);
 }
 
 // CFL signal speed of one cell (eq. resistivity:cfl; the resistive term
@@ -329,18 +355,17 @@ struct FacePlan {
   int tlo, tlen[3];   // transverse range start (same on every axis) and length per axis
   int ulo[3], ulen[3];  // faces read by the update (Joule flux only there)
   // x part: one wavefront per (row, segment)
-  int xseg, xnseg, xwaves, xblocks;
+  int xseg, xnseg, xwaves, xrows, xblocks;  // xwaves = items; xrows items per wavefront
   // y and z parts: lane blocks x chunks
   int chunk[3], nchunk[3], lanes[3], lblocks[3], blocks[3];
   int total_blocks;
 };
 
-// Face-local primitive of cell s for the face normal a (FP64 recovery, then T).
+// Face-local primitive of a cell for the face normal a (FP64 recovery, then T).
 template <typename T>
-__device__ __forceinline__ void face_local(const State& S, const Geom& G, int s, int a, double gamma,
-                                           T v[7]) {
+__device__ __forceinline__ void face_local_raw(const CellRaw& R, int a, double gamma, T v[7]) {
   double rho, u[3], p, bc[3];
-  cell_prim(S, G, s, gamma, rho, u, p, bc);
+  raw_prim(R, gamma, rho, u, p, bc);
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   v[0] = (T)rho;
   v[1] = (T)u[a];
@@ -351,15 +376,23 @@ __device__ __forceinline__ void face_local(const State& S, const Geom& G, int s,
   v[6] = (T)bc[c];
 }
 
+template <typename T>
+__device__ __forceinline__ void face_local(const State& S, const Geom& G, int s, int a, double gamma,
+                                           T v[7]) {
+  CellRaw R;
+  cell_load(S, G, s, R);
+  face_local_raw<T>(R, a, gamma, v);
+}
+
 template <typename T, int RIEMANN>
 __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, const Work<T>& W,
                                                const FacePlan& FP, int s, const int s3[3], int a,
                                                int stage, const T qL[7], const T qR[7],
-                                               double gamma_d, double eta_d) {
+                                               double bn_d, double gamma_d, double eta_d) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   FState<T> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
   FState<T> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
-  T bn = (T)S.b[a][s];
+  T bn = (T)bn_d;  // normal field of the face, S.b[a][s]
   T F[5], ap, am;
   int fb = 0;
   if (RIEMANN == kHLLD) {
@@ -424,24 +457,43 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
                         int wave, int stage, double gamma, double eta, int& nfb) {
   constexpr int r = recon_halfwidth(RECON);
   const int lane = threadIdx.x & 63;
-  const int row = wave / FP.xnseg, seg = wave % FP.xnseg;
-  const int y = FP.tlo + row % FP.tlen[1];
-  const int z = FP.tlo + row / FP.tlen[1];
-  const int x = FP.lo[0] - (r + 1) + seg * FP.xseg + lane;
-  const int xc = x < 0 ? 0 : (x > G.N[0] - 2 ? G.N[0] - 2 : x);  // loads stay in the box
-  const int s = xc + G.st[1] * y + G.st[2] * z;
-  T v[7];
-  face_local<T>(S, G, s, 0, gamma, v);
-  T qm[7], qp[7];
+  // this wavefront takes items [it, end) (item = row * xnseg + segment) and
+  // loads the cells of the next item before it resolves the current one
+  int it = wave * FP.xrows;
+  const int end = it + FP.xrows < FP.xwaves ? it + FP.xrows : FP.xwaves;
+  auto locate = [&](int item, int& x, int& y, int& z) {
+    const int row = item / FP.xnseg, seg = item % FP.xnseg;
+    y = FP.tlo + row % FP.tlen[1];
+    z = FP.tlo + row / FP.tlen[1];
+    x = FP.lo[0] - (r + 1) + seg * FP.xseg + lane;
+    const int xc = x < 0 ? 0 : (x > G.N[0] - 2 ? G.N[0] - 2 : x);  // loads stay in the box
+    return xc + G.st[1] * y + G.st[2] * z;
+  };
+  int xn, yn, zn;
+  int sn = locate(it, xn, yn, zn);
+  CellRaw nxt;
+  cell_load(S, G, sn, nxt);
+  for (; it < end; ++it) {  // wavefront-uniform trip count (cross-lane shuffles below)
+    const CellRaw cur = nxt;
+    const int x = xn, y = yn, z = zn, s = sn;
+    if (it + 1 < end) {
+      sn = locate(it + 1, xn, yn, zn);
+      cell_load(S, G, sn, nxt);
+    }
+    T v[7];
+    face_local_raw<T>(cur, 0, gamma, v);
+    T qm[7], qp[7];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], lane, qm[k], qp[k]);
-  T qL[7];
+    for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], lane, qm[k], qp[k]);
+    T qL[7];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) qL[k] = lane_shfl(qp[k], lane - 1);
-  const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
-  if (face) {
-    const int s3[3] = {x, y, z};
-    nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, 0, stage, qL, qm, gamma, eta);
+    for (int k = 0; k < 7; ++k) qL[k] = lane_shfl(qp[k], lane - 1);
+    const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
+    if (face) {
+      const int s3[3] = {x, y, z};
+      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, 0, stage, qL, qm, cur.bl[0], gamma,
+                                         eta);
+    }
   }
 }
 
@@ -466,19 +518,22 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
   const int base = s3[0] + G.st[C] * s3[C];
   ReconStream<RECON, T> rs[7];
   T qprev[7];
-  // warm-up: cells f0-1-r .. f0-2+r (outputs not yet complete)
-  for (int q = f0 - 1 - r; q < f0 - 1 + r; ++q) {
-    T v[7];
-    face_local<T>(S, G, base + q * sa, A, gamma, v);
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      T a0, a1;
-      rs[k].push(v[k], a0, a1);
+  // cells f0-1-r .. f1-1+r; the pushes before cell f0-1+r only warm up the
+  // pipeline.  The loads of cell q+1 and the normal field of the face it
+  // completes are issued before the stores of the face completed by cell q.
+  int q = f0 - 1 - r;
+  CellRaw nxt;
+  cell_load(S, G, base + q * sa, nxt);
+  double bn_next = 0.0;  // read only for the faces f0 .. f1-1
+  for (; q <= f1 - 1 + r; ++q) {
+    const CellRaw cur = nxt;
+    const double bn = bn_next;
+    if (q < f1 - 1 + r) {
+      cell_load(S, G, base + (q + 1) * sa, nxt);
+      if (q + 1 - r >= f0) bn_next = S.b[A][base + (q + 1 - r) * sa];
     }
-  }
-  for (int q = f0 - 1 + r; q <= f1 - 1 + r; ++q) {
     T v[7];
-    face_local<T>(S, G, base + q * sa, A, gamma, v);
+    face_local_raw<T>(cur, A, gamma, v);
     const int cell = q - r;  // completed by this push
     T qm[7], qp[7];
 #pragma unroll
@@ -486,7 +541,7 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
     if (cell >= f0) {
       s3[A] = cell;
       const int s = base + cell * sa;
-      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, A, stage, qprev, qm, gamma, eta);
+      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, A, stage, qprev, qm, bn, gamma, eta);
     }
 #pragma unroll
     for (int k = 0; k < 7; ++k) qprev[k] = qp[k];
@@ -508,7 +563,8 @@ __device__ __forceinline__ void faces_block(const State& S, const Geom& G, const
   } else {
     b -= FP.blocks[1];
     const int wave = b * (kBlock / 64) + (threadIdx.x >> 6);
-    if (wave < FP.xwaves) faces_x<T, RECON, RIEMANN>(S, G, W, FP, wave, stage, gamma, eta, nfb);
+    if (wave * FP.xrows < FP.xwaves)
+      faces_x<T, RECON, RIEMANN>(S, G, W, FP, wave, stage, gamma, eta, nfb);
   }
 }
 

@@ -26,7 +26,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tuning knobs in ctmhd_params.tile: bits 0-7 minimum faces per marching
 // chunk (default 32), bits 8-15 256-element strips per batched work item
-// (default 1), bits 16-23 batched schedule (0 per phase, 1 persistent).
+// (default 1), bits 16-23 batched schedule (0 per phase, 1 persistent),
+// bits 24-30 x-face row segments per wavefront (default 4).
 int tile_chunk(const ctmhd_params* p) {
   int c = p->tile & 0xff;
   return c > 0 ? c : 32;
@@ -37,6 +38,11 @@ int tile_strips(const ctmhd_params* p) {
 }
 // bits 16-23: batched schedule, 0 one launch per phase, 1 persistent queue
 int tile_sched(const ctmhd_params* p) { return (p->tile >> 16) & 0xff; }
+// bits 24-30: x-face items (row segments) per wavefront (default 4)
+int tile_xrows(const ctmhd_params* p) {
+  int x = (p->tile >> 24) & 0x7f;
+  return x > 0 ? x : 4;
+}
 
 int check_params(const ctmhd_params* p) {
   if (!p) return fail(CTMHD_EARG, "params is NULL");
@@ -50,7 +56,7 @@ int check_params(const ctmhd_params* p) {
   if (p->emf_compute < 0 || p->emf_compute > 2) return fail(CTMHD_EARG, "unknown EMF scheme");
   if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
   if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32) return fail(CTMHD_EARG, "unknown precision");
-  if (p->tile < 0 || p->tile > 0x1ffff) return fail(CTMHD_EARG, "tile knob out of range");
+  if (p->tile < 0 || (p->tile & ~0x7f01ffff) != 0) return fail(CTMHD_EARG, "tile knob out of range");
   return CTMHD_OK;
 }
 
@@ -150,7 +156,7 @@ inline void prof_end(hipStream_t st) {
   } while (0)
 
 // Face plan: ranges and launch shape of the fused face kernel.
-FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min) {
+FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min, int xrows) {
   FacePlan P;
   const int r = recon_halfwidth(recon);
   const int g = G.g;
@@ -170,7 +176,9 @@ FacePlan make_face_plan(const Geom& G, int recon, int emf, int chunk_min) {
   P.xseg = 64 - 2 * r - 1;
   P.xnseg = (P.nf[0] + P.xseg - 1) / P.xseg;
   P.xwaves = P.xnseg * P.tlen[1] * P.tlen[2];
-  P.xblocks = (P.xwaves + kBlock / 64 - 1) / (kBlock / 64);
+  P.xrows = xrows;
+  const int xwf = (P.xwaves + xrows - 1) / xrows;  // wavefronts of the x part
+  P.xblocks = (xwf + kBlock / 64 - 1) / (kBlock / 64);
   // y and z parts: enough chunks along the march for ~8192 waves in flight
   P.total_blocks = P.xblocks;
   for (int A = 1; A <= 2; ++A) {

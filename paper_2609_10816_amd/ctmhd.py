@@ -107,11 +107,12 @@ def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", 
                   0, int(bool(fofc)), int(flag_mask), PRECISION[precision], int(tile), ff)
 
 
-def make_tile(chunk=0, strips=0, persistent=False):
+def make_tile(chunk=0, strips=0, persistent=False, xrows=0):
     """The ctmhd_params.tile knob: minimum marching chunk, batched strips per
-    work item and the batched schedule (per-phase launches or one persistent
-    launch per step)."""
-    return (int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8) | ((1 if persistent else 0) << 16)
+    work item, the batched schedule (per-phase launches or one persistent
+    launch per step) and the x-face row segments per wavefront (0: defaults)."""
+    return ((int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8) | ((1 if persistent else 0) << 16)
+            | ((int(xrows) & 0x7F) << 24))
 
 
 def make_box(n, ng, dx, offset=0) -> Box:
