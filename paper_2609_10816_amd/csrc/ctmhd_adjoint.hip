@@ -137,26 +137,29 @@ __global__ void __launch_bounds__(kBlock)
 // Adjoint of X[f] through the reconstructions along axis d that produce the
 // edge values whose adjoints are UP (upper value of the cell below the edge,
 // stored at the edge) and LO (lower value of the cell above the edge): the
-// cells f - st, f, f + st are the centres that read X[f].
+// centres f - r st .. f + r st read X[f] (r the reconstruction half-width).
+// Centres whose stencil leaves the box carry no adjoint and are skipped.
 template <int RECON>
 __device__ __forceinline__ double gather_along(const double* Xv, const double* UP, const double* LO,
                                                const Geom& G, const int s3[3], int f, int d) {
+  constexpr int r = recon_halfwidth(RECON);
   const int st = G.st[d], x0 = s3[d], N = G.N[d];
   double acc = 0.0;
 #pragma unroll
-  for (int k = -1; k <= 1; ++k) {
-    const int cx = x0 + k;
-    const double up = (cx + 1 >= 0 && cx + 1 < N) ? UP[f + (k + 1) * st] : 0.0;
-    const double lo = (cx >= 0 && cx < N) ? LO[f + k * st] : 0.0;
+  for (int k = -r; k <= r; ++k) {
+    const int cx = x0 + k;  // centre
+    if (cx - r < 0 || cx + r >= N) continue;
+    const double up = cx + 1 < N ? UP[f + (k + 1) * st] : 0.0;
+    const double lo = LO[f + k * st];
     if (up == 0.0 && lo == 0.0) continue;
-    if (k == 0) acc += up + lo;
-    if constexpr (RECON == kPLM_MC || RECON == kPLM_MM) {
-      if (cx - 1 < 0 || cx + 1 >= N) continue;
-      double dm, d0, dp;
-      plm_slope_partials<RECON>(Xv[f + (k - 1) * st], Xv[f + k * st], Xv[f + (k + 1) * st], dm, d0,
-                                dp);
-      acc += 0.5 * (up - lo) * (k == -1 ? dp : (k == 0 ? d0 : dm));
+    double q[5], qb[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      q[m] = (m - 2 >= -r && m - 2 <= r) ? Xv[f + (k + m - 2) * st] : 0.0;
+      qb[m] = 0.0;
     }
+    recon_cell_adj5<RECON>(q, lo, up, qb);
+    acc += qb[2 - k];  // X[f] is offset -k from the centre
   }
   return acc;
 }
@@ -283,18 +286,13 @@ __global__ void __launch_bounds__(kBlock)
     for (int q = 0; q < 7; ++q) {
       const double* P = X.prim[vmap[q]];
       double w[5], lo, hi;
+      // upper value of cell t - sa, lower value of cell t
 #pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = 0.0;
-      // upper value of cell t - sa from (t - 2sa, t - sa, t)
-      w[1] = r ? P[t - 2 * sa] : 0.0;
-      w[2] = P[t - sa];
-      w[3] = r ? P[t] : 0.0;
+      for (int k = 0; k < 5; ++k) w[k] = (k - 2 >= -r && k - 2 <= r) ? P[t + (k - 3) * sa] : 0.0;
       recon_cell<RECON>(w, lo, hi);
       qL[q] = hi;
-      // lower value of cell t from (t - sa, t, t + sa)
-      w[1] = r ? P[t - sa] : 0.0;
-      w[2] = P[t];
-      w[3] = r ? P[t + sa] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) w[k] = (k - 2 >= -r && k - 2 <= r) ? P[t + (k - 2) * sa] : 0.0;
       recon_cell<RECON>(w, lo, hi);
       qR[q] = lo;
     }
@@ -476,9 +474,6 @@ size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
 int check_adjoint(const ctmhd_params* p) {
   if (p->precision != CTMHD_FP64)
     return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the FP64 form only");
-  if (p->recon != CTMHD_RECON_PC && p->recon != CTMHD_RECON_PLM_MC &&
-      p->recon != CTMHD_RECON_PLM_MINMOD)
-    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for PC and PLM reconstruction only");
   if (p->emf_compute != CTMHD_EMF_Q26)
     return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the Q26 EMF only");
   return CTMHD_OK;
@@ -635,9 +630,12 @@ int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double
     case CTMHD_RECON_PLM_MC:
       return adjoint_riemann<kPLM_MC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
                                       g_bface_out, workspace, ws_bytes, st);
-    default:
+    case CTMHD_RECON_PLM_MINMOD:
       return adjoint_riemann<kPLM_MM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
                                       g_bface_out, workspace, ws_bytes, st);
+    default:
+      return adjoint_riemann<kPPM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                   g_bface_out, workspace, ws_bytes, st);
   }
 }
 

@@ -63,25 +63,101 @@ CTMHD_HD void recon_cell_adj(T qm, T q0, T qp, T lob, T hib, T& qmb, T& q0b, T& 
   }
 }
 
-// Adjoint of value q at position 0 of a line of values q[-2..2] (x[0..4])
-// through every reconstruction that reads it: the centres -1, 0, +1, each
-// with the adjoint of its upper value up[k] and its lower value lo[k]
-// (k = 0, 1, 2 for centres -1, 0, +1).
-template <int M, typename T>
-CTMHD_HD T recon_gather_adj(const T x[5], const T up[3], const T lo[3]) {
-  T acc = up[1] + lo[1];
-  if constexpr (M == kPLM_MC || M == kPLM_MM) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      T dm, d0, dp;
-      plm_slope_partials<M>(x[k], x[k + 1], x[k + 2], dm, d0, dp);
-      const T sb = T(0.5) * (up[k] - lo[k]);
-      // position 0 is the right neighbour of centre -1, the centre of 0 and
-      // the left neighbour of +1
-      acc += sb * (k == 0 ? dp : (k == 1 ? d0 : dm));
+// Partial derivatives of the PPM limited slope ppm_slope(qm, q0, qp) with
+// respect to (qm, q0, qp): the centred difference where it is the smaller
+// candidate, else twice the smaller one-sided difference (Sec. 2.2).
+template <typename T>
+CTMHD_HD void ppm_slope_partials(T qm, T q0, T qp, T& dm, T& d0, T& dp) {
+  const T dl = q0 - qm, dr = qp - q0, dc = T(0.5) * (qp - qm);
+  dm = d0 = dp = T(0);
+  if (dl * dr > T(0)) {
+    // dl, dr and dc share one sign, so each candidate is linear in the values
+    if (tabs(dc) <= T(2) * tmin(tabs(dl), tabs(dr))) {
+      dm = T(-0.5);
+      dp = T(0.5);
+    } else if (tabs(dl) <= tabs(dr)) {  // s = 2 dl
+      dm = T(-2);
+      d0 = T(2);
+    } else {  // s = 2 dr
+      d0 = T(-2);
+      dp = T(2);
     }
+  }
+}
+
+// Adjoint of the PPM face values of the centre cell of q[0..4] (recon_cell):
+// interface values from the limited slopes of the three middle cells, then
+// the Colella-Woodward constraints in the branch the forward takes.
+template <typename T>
+CTMHD_HD void ppm_cell_adj(const T q[5], T lob, T hib, T qb[5]) {
+  const T sixth = T(1) / T(6);
+  const T d1 = ppm_slope(q[0], q[1], q[2]);
+  const T d2 = ppm_slope(q[1], q[2], q[3]);
+  const T d3 = ppm_slope(q[2], q[3], q[4]);
+  const T qL = ppm_iface(q[1], q[2], d1, d2);
+  const T qR = ppm_iface(q[2], q[3], d2, d3);
+  T qLb = T(0), qRb = T(0);  // adjoints of the unconstrained interface values
+  if ((qR - q[2]) * (q[2] - qL) <= T(0)) {
+    qb[2] += lob + hib;  // local extremum: both values set to the centre
   } else {
-    (void)x;
+    const T dq = qR - qL;
+    const T q6 = dq * (q[2] - T(0.5) * (qL + qR));
+    const T d6 = dq * dq * sixth;
+    if (q6 > d6) {  // lower value reset to 3 q0 - 2 qR
+      qb[2] += T(3) * lob;
+      qRb += hib - T(2) * lob;
+    } else if (-d6 > q6) {  // upper value reset to 3 q0 - 2 qL
+      qb[2] += T(3) * hib;
+      qLb += lob - T(2) * hib;
+    } else {
+      qLb += lob;
+      qRb += hib;
+    }
+  }
+  // qL = (q1 + q2)/2 - (d2 - d1)/6, qR = (q2 + q3)/2 - (d3 - d2)/6
+  qb[1] += T(0.5) * qLb;
+  qb[2] += T(0.5) * (qLb + qRb);
+  qb[3] += T(0.5) * qRb;
+  const T db[3] = {qLb * sixth, (qRb - qLb) * sixth, -qRb * sixth};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    T pm, p0, pp;
+    ppm_slope_partials(q[j], q[j + 1], q[j + 2], pm, p0, pp);
+    qb[j] += db[j] * pm;
+    qb[j + 1] += db[j] * p0;
+    qb[j + 2] += db[j] * pp;
+  }
+}
+
+// Adjoint of the lower / upper face values of the centre cell of q[0..4]
+// (recon_cell, any scheme): adds to qb[0..4].
+template <int M, typename T>
+CTMHD_HD void recon_cell_adj5(const T q[5], T lob, T hib, T qb[5]) {
+  if constexpr (M == kPPM)
+    ppm_cell_adj(q, lob, hib, qb);
+  else
+    recon_cell_adj<M>(q[1], q[2], q[3], lob, hib, qb[1], qb[2], qb[3]);
+}
+
+// Adjoint of the value at position 0 of a line of values at positions
+// -2r .. 2r (x[0 .. 4r], r the reconstruction half-width) through the
+// reconstructions of the centres -r .. r that read it; up[k] and lo[k] are
+// the adjoints of the upper and lower values of centre k - r.
+template <int M, typename T>
+CTMHD_HD T recon_gather_adj(const T* x, const T* up, const T* lo) {
+  constexpr int r = recon_halfwidth(M);
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k <= 2 * r; ++k) {
+    T q[5], qb[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      // offset m - 2 from centre k - r: position k - r + m - 2, index k + m - 2 + r
+      q[m] = (m - 2 >= -r && m - 2 <= r) ? x[k + m - 2 + r] : T(0);
+      qb[m] = T(0);
+    }
+    recon_cell_adj5<M>(q, lo[k], up[k], qb);
+    acc += qb[2 + r - k];  // position 0 is offset r - k from centre k - r
   }
   return acc;
 }

@@ -246,30 +246,32 @@ static void check_ld04() {
 }
 
 // ---- reconstruction ----
+// A line of 13 values; the centres 2 .. 10 (whose five-point windows lie in
+// the line) carry random adjoints of their lower and upper values.  The
+// scatter form (recon_cell_adj5 per centre) is checked against central
+// differences, the gather form (recon_gather_adj per position) against the
+// scatter form where every centre that reads the position carries adjoints.
 template <int M>
-static void check_recon(const char* name) {
+static void check_recon(const char* name, int* branches) {
+  constexpr int r = recon_halfwidth(M);
+  constexpr int L = 13;
   double worst = 0, gworst = 0;
   int n = 0;
-  for (int it = 0; it < 20000 && n < 3000; ++it) {
-    // a line of 7 values; the reconstructions of centres 1..5 read 0..6
-    double q[7], dq[7];
-    for (int k = 0; k < 7; ++k) {
+  for (int it = 0; it < 40000 && n < 4000; ++it) {
+    double q[L], dq[L], lob[L] = {0}, hib[L] = {0};
+    for (int k = 0; k < L; ++k) {
       q[k] = U(-1, 1);
       dq[k] = U(-1, 1);
     }
-    double lob[7] = {0}, hib[7] = {0};
-    for (int c = 1; c <= 5; ++c) {
+    for (int c = 2; c <= L - 3; ++c) {
       lob[c] = U(-1, 1);
       hib[c] = U(-1, 1);
     }
     auto J = [&](double h) {
       double j = 0;
-      for (int c = 1; c <= 5; ++c) {
+      for (int c = 2; c <= L - 3; ++c) {
         double qq[5], lo, hi;
-        for (int k = 0; k < 5; ++k) {
-          int i = c - 2 + k;
-          qq[k] = (i >= 0 && i < 7) ? q[i] + h * dq[i] : 0.0;
-        }
+        for (int k = 0; k < 5; ++k) qq[k] = q[c - 2 + k] + h * dq[c - 2 + k];
         recon_cell<M>(qq, lo, hi);
         j += lob[c] * lo + hib[c] * hi;
       }
@@ -278,21 +280,35 @@ static void check_recon(const char* name) {
     const double h = 1e-7;
     double jp = J(h), jm = J(-h), j0 = J(0);
     if (std::fabs(jp - 2 * j0 + jm) > 1e-10) continue;  // limiter kink inside [-h, h]
-    // adjoint by scatter (recon_cell_adj) and by gather (recon_gather_adj)
-    double qs[7] = {0};
-    for (int c = 1; c <= 5; ++c) recon_cell_adj<M>(q[c - 1], q[c], q[c + 1], lob[c], hib[c],
-                                                   qs[c - 1], qs[c], qs[c + 1]);
+    double qs[L] = {0};
+    for (int c = 2; c <= L - 3; ++c) {
+      double qb[5] = {0, 0, 0, 0, 0};
+      recon_cell_adj5<M>(q + c - 2, lob[c], hib[c], qb);
+      for (int k = 0; k < 5; ++k) qs[c - 2 + k] += qb[k];
+      if (branches && M == kPPM) {
+        // census of the constraint branches (extremum, lower reset, upper reset, none)
+        const double* w = q + c - 2;
+        const double d1 = ppm_slope(w[0], w[1], w[2]), d2 = ppm_slope(w[1], w[2], w[3]);
+        const double d3 = ppm_slope(w[2], w[3], w[4]);
+        const double a = ppm_iface(w[1], w[2], d1, d2), b = ppm_iface(w[2], w[3], d2, d3);
+        const double dqq = b - a, q6 = dqq * (w[2] - 0.5 * (a + b)), d6 = dqq * dqq / 6.0;
+        ++branches[(b - w[2]) * (w[2] - a) <= 0 ? 0 : (q6 > d6 ? 1 : (-d6 > q6 ? 2 : 3))];
+      }
+    }
     double ad = 0, sc = 0;
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < L; ++k) {
       ad += qs[k] * dq[k];
       sc += std::fabs(qs[k] * dq[k]);
     }
-    for (int k = 2; k <= 4; ++k) {  // positions whose three centres all exist
-      double x[5] = {q[k - 2], q[k - 1], q[k], q[k + 1], q[k + 2]};
-      double up[3] = {hib[k - 1], hib[k], hib[k + 1]};
-      double lo[3] = {lob[k - 1], lob[k], lob[k + 1]};
+    for (int p = 2 + r; p <= L - 3 - r; ++p) {  // positions whose centres all carry adjoints
+      double x[9], up[5], lo[5];
+      for (int k = 0; k <= 4 * r; ++k) x[k] = q[p - 2 * r + k];
+      for (int k = 0; k <= 2 * r; ++k) {
+        up[k] = hib[p - r + k];
+        lo[k] = lob[p - r + k];
+      }
       double gk = recon_gather_adj<M>(x, up, lo);
-      gworst = std::fmax(gworst, std::fabs(gk - qs[k]) / (std::fabs(qs[k]) + 1.0));
+      gworst = std::fmax(gworst, std::fabs(gk - qs[p]) / (std::fabs(qs[p]) + 1.0));
     }
     const double fd = (jp - jm) / (2 * h);
     worst = std::fmax(worst, relmis(ad, fd, sc));
@@ -302,15 +318,28 @@ static void check_recon(const char* name) {
   std::snprintf(lab, sizeof(lab), "%s gather = scatter", name);
   report(lab, gworst, 1e-14);
   report(name, worst, 1e-7);
+  if (n < 1000) {
+    std::printf("%s: only %d samples away from limiter kinks\n", name, n);
+    ++g_fail;
+  }
 }
 
 int main() {
   check_fast();
   check_phys();
   check_ld04();
-  check_recon<kPC>("recon PC");
-  check_recon<kPLM_MC>("recon PLM-MC");
-  check_recon<kPLM_MM>("recon PLM-minmod");
+  check_recon<kPC>("recon PC", nullptr);
+  check_recon<kPLM_MC>("recon PLM-MC", nullptr);
+  check_recon<kPLM_MM>("recon PLM-minmod", nullptr);
+  int ppmb[4] = {0};
+  check_recon<kPPM>("recon PPM", ppmb);
+  std::printf("PPM constraint branches (extremum, lower reset, upper reset, none): %d %d %d %d\n",
+              ppmb[0], ppmb[1], ppmb[2], ppmb[3]);
+  for (int k = 0; k < 4; ++k)
+    if (ppmb[k] < 500) {
+      std::printf("PPM constraint branch %d covered by fewer than 500 samples\n", k);
+      ++g_fail;
+    }
   int reg[6] = {0};
   check_face<kLLF>("LLF face outputs", 2.0, 1.5, nullptr);
   check_face<kHLLD>("HLLD face outputs (subsonic)", 1.0, 1.5, reg);

@@ -24,6 +24,9 @@ CONFIGS = [
     ("plm", "hlld", 1e-3),
     ("plm_minmod", "hlld", 1e-3),
     ("pc", "hlld", 1e-3),
+    ("ppm", "llf", 0.0),
+    ("ppm", "hlld", 0.0),
+    ("ppm", "hlld", 1e-3),
 ]
 
 
@@ -83,18 +86,25 @@ def test_adjoint_dot_product_vs_oracle_dual(recon, riemann, eta):
     assert worst <= 1e-12, worst
 
 
-def test_adjoint_gradient_vs_central_differences_16():
+@pytest.mark.parametrize("recon", ["plm", "ppm"])
+def test_adjoint_gradient_vs_central_differences_16(recon):
     """Loss L(S) = <w, step(S)> on the 16^3 smooth box (amplitude 0.05,
-    beta = 1; FP64, PLM-MC + HLLD + Q26 + LD04, eta = 1e-3, no flux
+    beta = 1; FP64, PLM-MC or PPM + HLLD + Q26 + LD04, eta = 1e-3, no flux
     correction, frozen dt).  Sampled entries of dL/dS from the adjoint against
     fourth-order central differences of the GPU forward step, one entry at a
     time (a dense random direction would cross limiter kinks somewhere in the
-    box; one entry moves only the limiters around one cell)."""
+    box; one entry moves only the limiters around one cell).
+
+    L is only piecewise smooth: a limiter or PPM constraint can switch branch
+    within the difference stencil of an entry, and there the difference
+    quotient is not the derivative.  Such an entry is recognised from the
+    differences alone (steps h and h/4 disagree) and left out; at least 16 of
+    the 24 entries must be smooth, and every smooth one must match."""
     n = 16
     cons, bf, info = inputs.smooth_modes_box(n, amp=0.05, beta=1.0, seed=5)
     dx = info["dx"]
-    P = ctmhd.make_params(recon="plm", riemann="hlld", eta=1e-3, fofc=False)
-    Q = oracle.make_params(recon="plm", riemann="hlld", eta=1e-3, fofc=False)
+    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=1e-3, fofc=False)
+    Q = oracle.make_params(recon=recon, riemann="hlld", eta=1e-3, fofc=False)
     dt = oracle.cfl_dt(Q, cons, bf, dx)
     rng = np.random.default_rng(11)
     wc = rng.standard_normal(cons.shape)
@@ -106,8 +116,12 @@ def test_adjoint_gradient_vs_central_differences_16():
         c1, b1, _, _ = ctmhd.run(P, c, b, dx, 1, dt_fixed=[dt])
         return float(np.sum(wc * c1) + np.sum(wb * b1))
 
-    worst = 0.0
-    for rep in range(16):
+    def fd4(dc, db, h):
+        f = {s_: loss(cons + s_ * h * dc, bf + s_ * h * db) for s_ in (-2, -1, 1, 2)}
+        return (-f[2] + 8.0 * f[1] - 8.0 * f[-1] + f[-2]) / (12.0 * h)
+
+    worst, smooth = 0.0, 0
+    for rep in range(24):
         m = int(rng.integers(0, 8))
         k, j, i = (int(v) for v in rng.integers(0, n, 3))
         dc = np.zeros(cons.shape)
@@ -120,16 +134,23 @@ def test_adjoint_gradient_vs_central_differences_16():
             db[m - 5, k, j, i] = 1.0
             h = 1e-5 * float(np.abs(bf).mean())
             an = ab[m - 5, k, j, i]
-        f = {s_: loss(cons + s_ * h * dc, bf + s_ * h * db) for s_ in (-2, -1, 1, 2)}
-        fd = (-f[2] + 8.0 * f[1] - 8.0 * f[-1] + f[-2]) / (12.0 * h)
-        err = abs(fd - an) / (abs(fd) + 1e-3 * gscale)
+        fd, fd_fine = fd4(dc, db, h), fd4(dc, db, 0.25 * h)
+        scale = abs(fd) + 1e-3 * gscale
+        if abs(fd - fd_fine) > 5e-7 * scale:
+            print(f"[adjoint] 16^3 {recon} entry field {m} cell {(k, j, i)}: differences with "
+                  f"h and h/4 disagree ({fd:.12e}, {fd_fine:.12e}): branch switch, left out",
+                  flush=True)
+            continue
+        smooth += 1
+        err = abs(fd - an) / scale
         worst = max(worst, err)
-        print(f"[adjoint] 16^3 entry field {m} cell {(k, j, i)}: adjoint {an:.12e}, "
+        print(f"[adjoint] 16^3 {recon} entry field {m} cell {(k, j, i)}: adjoint {an:.12e}, "
               f"central difference {fd:.12e}, relative {err:.2e}", flush=True)
+    assert smooth >= 16, smooth
     assert worst <= 1e-6, worst
 
 
-@pytest.mark.parametrize("kw", [dict(recon="ppm"), dict(precision="fp32"), dict(emf="b25a")])
+@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(emf="b25a"), dict(emf="fs18")])
 def test_adjoint_refuses_unsupported(kw):
     import torch
     P = ctmhd.make_params(**kw)
