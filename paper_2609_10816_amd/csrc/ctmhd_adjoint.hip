@@ -31,6 +31,10 @@
 
 namespace {
 
+struct PrimPtrs {
+  double* p[8];
+};
+
 struct AdjArrays {
   double* v[8];        // adjoint of D: 5 cell fields, 3 face fields; 0 outside the interior
   double* prim[8];     // rho, u0, u1, u2, p, bc0, bc1, bc2 of the state
@@ -134,36 +138,6 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
-// Adjoint of X[f] through the reconstructions along axis d that produce the
-// edge values whose adjoints are UP (upper value of the cell below the edge,
-// stored at the edge) and LO (lower value of the cell above the edge): the
-// centres f - r st .. f + r st read X[f] (r the reconstruction half-width).
-// Centres whose stencil leaves the box carry no adjoint and are skipped.
-template <int RECON>
-__device__ __forceinline__ double gather_along(const double* Xv, const double* UP, const double* LO,
-                                               const Geom& G, const int s3[3], int f, int d) {
-  constexpr int r = recon_halfwidth(RECON);
-  const int st = G.st[d], x0 = s3[d], N = G.N[d];
-  double acc = 0.0;
-#pragma unroll
-  for (int k = -r; k <= r; ++k) {
-    const int cx = x0 + k;  // centre
-    if (cx - r < 0 || cx + r >= N) continue;
-    const double up = cx + 1 < N ? UP[f + (k + 1) * st] : 0.0;
-    const double lo = LO[f + k * st];
-    if (up == 0.0 && lo == 0.0) continue;
-    double q[5], qb[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      q[m] = (m - 2 >= -r && m - 2 <= r) ? Xv[f + (k + m - 2) * st] : 0.0;
-      qb[m] = 0.0;
-    }
-    recon_cell_adj5<RECON>(q, lo, up, qb);
-    acc += qb[2 - k];  // X[f] is offset -k from the centre
-  }
-  return acc;
-}
-
 // Adjoint of a face value v[f] read as one of the two arguments of an edge
 // speed max(v[e - st], v[e]) at the edges e = f + st and e = f (axis d).
 __device__ __forceinline__ double gather_max(const double* V, const double* AB, const Geom& G,
@@ -183,12 +157,11 @@ __device__ __forceinline__ double gather_max(const double* V, const double* AB, 
 
 // ---------------------------------------------------------------------------
 // Faces, part 1 (direction blockIdx.y): flux adjoint from v (transposed
-// divergence), the u* / alpha / face-field adjoints gathered from the edges
-// that read them, and the Joule flux in reverse.  The inputs of the reverse Riemann solve are left in
-// fa[a][0..7] (5 local flux components, alpha+, alpha-, u*); the gathered
-// face-field adjoint goes to bn.
+// divergence), the alpha adjoints gathered from the edges that read them, and
+// the Joule flux in reverse.  With the u* adjoint that face_lines leaves in
+// fa[a][7], the inputs of the reverse Riemann solve are then in fa[a][0..7]
+// (5 local flux components, alpha+, alpha-, u*).
 // ---------------------------------------------------------------------------
-template <int RECON>
 __global__ void __launch_bounds__(kBlock)
     k_adj_fgather(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
   if (*stop) return;
@@ -220,10 +193,6 @@ __global__ void __launch_bounds__(kBlock)
                     gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
     X.fa[a][6][t] = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
                     gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
-    X.fa[a][7][t] = gather_along<RECON>(W.us[a], X.ea[c][0], X.ea[c][1], G, s3, t, b) +
-                    gather_along<RECON>(W.us[a], X.ea[b][2], X.ea[b][3], G, s3, t, c);
-    X.bn[a][t] = gather_along<RECON>(S.b[a], X.ea[c][4], X.ea[c][5], G, s3, t, b) +
-                 gather_along<RECON>(S.b[a], X.ea[b][6], X.ea[b][7], G, s3, t, c);
     if (eta > 0.0 && upd && Fb[4] != 0.0) {
       // Joule flux (joule): J = eb (bcl + bcr)/2 - ec (bbl + bbr)/2
       const double Jb = Fb[4];
@@ -285,16 +254,12 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const double* P = X.prim[vmap[q]];
-      double w[5], lo, hi;
-      // upper value of cell t - sa, lower value of cell t
+      // upper value of cell t - sa and lower value of cell t from the
+      // six-point sequence t - 3 sa .. t + 2 sa (shared slopes for PPM)
+      double w[6];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = (k - 2 >= -r && k - 2 <= r) ? P[t + (k - 3) * sa] : 0.0;
-      recon_cell<RECON>(w, lo, hi);
-      qL[q] = hi;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = (k - 2 >= -r && k - 2 <= r) ? P[t + (k - 2) * sa] : 0.0;
-      recon_cell<RECON>(w, lo, hi);
-      qR[q] = lo;
+      for (int m = 0; m < 6; ++m) w[m] = stencil_uses<RECON>(m) ? P[t + (m - 3) * sa] : 0.0;
+      recon_iface<RECON>(w, qL[q], qR[q]);
     }
     const FState<double> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
     const FState<double> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
@@ -318,28 +283,210 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // ---------------------------------------------------------------------------
-// Cells: face-state adjoints through the reverse of the reconstructions, then
+// Line gathers: out[f] (=, or += with acc) the adjoint of X[f] through the
+// reconstructions along one axis whose upper / lower values have the adjoints
+// UP (stored at the upper face of each centre) and LO (at its lower face),
+// the same sum as gather_along, for every position of the box.  Each centre's
+// reconstruction is reversed once: along x by the 64 lanes of a wavefront
+// (stencil values and the five contributions by cross-lane shuffles), along y
+// and z by a thread marching through a segment of a line with the values and
+// the open partial sums in registers.  Centres whose stencil leaves the box
+// carry no adjoint.
+// ---------------------------------------------------------------------------
+struct LineJob {
+  const double* X;
+  const double* UP;
+  const double* LO;
+  double* out;
+  int acc;
+};
+constexpr int kMaxLineJobs = 8;
+struct LineJobs {
+  LineJob j[kMaxLineJobs];
+  int chunk;  // positions per marching thread (y, z)
+};
+
+template <int RECON>
+__global__ void __launch_bounds__(kBlock) k_line_x(Geom G, LineJobs J, const int* stop) {
+  if (*stop) return;
+  constexpr int r = recon_halfwidth(RECON);
+  constexpr int seg = 64 - 4 * r;  // positions resolved per wavefront
+  const LineJob& L = J.j[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int N = G.N[0];
+  const int nseg = (N + seg - 1) / seg;
+  if (wave >= nseg * G.N[1] * G.N[2]) return;  // whole wavefronts
+  const int row = wave / nseg, sg = wave % nseg;
+  const int base = row * N;  // (y, z) row of x-contiguous values
+  const int x = sg * seg - 2 * r + lane;  // position of this lane, and the centre it reverses
+  const bool in = x >= 0 && x < N;
+  const double xv = L.X[base + (in ? x : (x < 0 ? 0 : N - 1))];
+  const bool valid = x - r >= 0 && x + r < N;
+  const double lo = valid ? L.LO[base + x] : 0.0;
+  const double up = valid && x + 1 < N ? L.UP[base + x + 1] : 0.0;
+  double q[5], qb[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    q[m] = (m - 2 >= -r && m - 2 <= r) ? __shfl(xv, lane + m - 2, 64) : 0.0;
+    qb[m] = 0.0;
+  }
+  if (lo != 0.0 || up != 0.0) recon_cell_adj5<RECON>(q, lo, up, qb);
+  // position x receives qb[m] of the centre at lane - (m - 2); lanes
+  // [2r, 63-2r] have every such centre (and its stencil) in the wavefront
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+    if (m - 2 >= -r && m - 2 <= r) acc += __shfl(qb[m], lane - (m - 2), 64);
+  if (in && lane >= 2 * r && lane < 64 - 2 * r) {
+    double* o = L.out + base + x;
+    *o = L.acc ? *o + acc : acc;
+  }
+}
+
+template <int RECON, int D>
+__global__ void __launch_bounds__(kBlock) k_line_march(Geom G, LineJobs J, const int* stop) {
+  if (*stop) return;
+  constexpr int r = recon_halfwidth(RECON);
+  constexpr int W = 2 * r + 1;
+  constexpr int C = D == 1 ? 2 : 1;  // transverse axes: x and C
+  const LineJob& L = J.j[blockIdx.z];
+  const int lane = blockIdx.x * kBlock + threadIdx.x;
+  if (lane >= G.N[0] * G.N[C]) return;
+  const int base = lane % G.N[0] + (lane / G.N[0]) * G.st[C];
+  const int st = G.st[D], N = G.N[D];
+  const int p0 = blockIdx.y * J.chunk;
+  const int p1 = p0 + J.chunk < N ? p0 + J.chunk : N;
+  // val[j], acc[j]: position c - r + j for the current centre c
+  double val[W], acc[W];
+#pragma unroll
+  for (int j = 0; j < W - 1; ++j) {
+    const int p = p0 - 2 * r + j;
+    val[j] = p >= 0 && p < N ? L.X[base + p * st] : 0.0;
+    acc[j] = 0.0;
+  }
+  acc[W - 1] = 0.0;
+  for (int c = p0 - r; c <= p1 - 1 + r; ++c) {
+    {
+      const int p = c + r;
+      val[W - 1] = p >= 0 && p < N ? L.X[base + p * st] : 0.0;
+    }
+    const bool valid = c - r >= 0 && c + r < N;
+    const double lo = valid ? L.LO[base + c * st] : 0.0;
+    const double up = valid && c + 1 < N ? L.UP[base + (c + 1) * st] : 0.0;
+    if (lo != 0.0 || up != 0.0) {
+      double q[5], qb[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        q[m] = (m - 2 >= -r && m - 2 <= r) ? val[m - 2 + r] : 0.0;
+        qb[m] = 0.0;
+      }
+      recon_cell_adj5<RECON>(q, lo, up, qb);
+#pragma unroll
+      for (int m = 0; m < 5; ++m)
+        if (m - 2 >= -r && m - 2 <= r) acc[m - 2 + r] += qb[m];
+    }
+    const int p = c - r;  // complete: no later centre reads it
+    if (p >= p0 && p < p1) {
+      double* o = L.out + base + p * st;
+      *o = L.acc ? *o + acc[0] : acc[0];
+    }
+#pragma unroll
+    for (int j = 0; j < W - 1; ++j) {
+      val[j] = val[j + 1];
+      acc[j] = acc[j + 1];
+    }
+    acc[W - 1] = 0.0;
+  }
+}
+
+// One line gather launch per axis for up to kMaxLineJobs arrays.
+template <int RECON>
+int launch_lines(hipStream_t st, const Geom& G, int D, const LineJobs& J, int njobs,
+                 const int* stop) {
+  if (D == 0) {
+    constexpr int seg = 64 - 4 * recon_halfwidth(RECON);
+    const long long waves = (long long)((G.N[0] + seg - 1) / seg) * G.N[1] * G.N[2];
+    const int blocks = (int)((waves + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL(k_line_x<RECON>, dim3(blocks, njobs), dim3(kBlock), 0, st, G, J, stop);
+  } else {
+    const int C = D == 1 ? 2 : 1;
+    const int blocks = (G.N[0] * G.N[C] + kBlock - 1) / kBlock;
+    const dim3 grid(blocks, (G.N[D] + J.chunk - 1) / J.chunk, njobs);
+    if (D == 1)
+      hipLaunchKernelGGL((k_line_march<RECON, 1>), grid, dim3(kBlock), 0, st, G, J, stop);
+    else
+      hipLaunchKernelGGL((k_line_march<RECON, 2>), grid, dim3(kBlock), 0, st, G, J, stop);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: line gather");
+  return CTMHD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Faces, part 0: the u* and face-field adjoints of face direction a gathered
+// from the edges that reconstruct them along the two transverse axes: edges
+// of direction c read them along b, edges of direction b along c.  Written to
+// fa[a][7] and bn[a]; on each axis the faces whose first gather it is write,
+// the others add.
+// ---------------------------------------------------------------------------
+template <int RECON>
+int face_lines(hipStream_t st, const Geom& G, const State& S, const Work<double>& W,
+               const AdjArrays& X, const int* stop) {
+  for (int D = 0; D < 3; ++D) {
+    LineJobs J{};
+    J.chunk = 16;
+    int n = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      if (D == b) {  // the first gather of face direction a when b < c
+        const int acc = b > c;
+        J.j[n++] = LineJob{W.us[a], X.ea[c][0], X.ea[c][1], X.fa[a][7], acc};
+        J.j[n++] = LineJob{S.b[a], X.ea[c][4], X.ea[c][5], X.bn[a], acc};
+      } else if (D == c) {
+        const int acc = c > b;
+        J.j[n++] = LineJob{W.us[a], X.ea[b][2], X.ea[b][3], X.fa[a][7], acc};
+        J.j[n++] = LineJob{S.b[a], X.ea[b][6], X.ea[b][7], X.bn[a], acc};
+      }
+    }
+    const int rc = launch_lines<RECON>(st, G, D, J, n, stop);
+    if (rc) return rc;
+  }
+  return CTMHD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cells: face-state adjoints through the reverse of the reconstructions (line
+// gathers into the primitive adjoints pb, three axes in turn), then
 // primitive -> conserved.
 // ---------------------------------------------------------------------------
 template <int RECON>
+int cell_lines(hipStream_t st, const Geom& G, const AdjArrays& X, double* const pb[8],
+               const int* stop) {
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+    LineJobs J{};
+    J.chunk = 16;
+    for (int q = 0; q < 7; ++q) {
+      // the left state of face e is the upper value of cell e - st, the right
+      // state the lower value of cell e; axis 0 writes its seven primitives
+      // first, bc0 is first written by axis 1
+      J.j[q] = LineJob{X.prim[vmap[q]], X.fa[a][q], X.fa[a][7 + q], pb[vmap[q]],
+                       a == 0 ? 0 : (a == 1 ? (vmap[q] != 5) : 1)};
+    }
+    const int rc = launch_lines<RECON>(st, G, a, J, 7, stop);
+    if (rc) return rc;
+  }
+  return CTMHD_OK;
+}
+
 __global__ void __launch_bounds__(kBlock)
-    k_adj_cell(State S, Geom G, AdjArrays X, double gamma, const int* stop) {
+    k_adj_cfinish(Geom G, AdjArrays X, PrimPtrs PB, double gamma, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
   int s3[3];
   decode(G, t, s3);
-  double pb[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
-    const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
-#pragma unroll
-    for (int q = 0; q < 7; ++q)
-      // the left state of face e is the upper value of cell e - st, the right
-      // state the lower value of cell e
-      pb[vmap[q]] += gather_along<RECON>(X.prim[vmap[q]], X.fa[a][q], X.fa[a][7 + q], G, s3, t, a);
-  }
   const bool valid = s3[0] < G.N[0] - 1 && s3[1] < G.N[1] - 1 && s3[2] < G.N[2] - 1;
   if (!valid) {
 #pragma unroll
@@ -348,6 +495,9 @@ __global__ void __launch_bounds__(kBlock)
     for (int d = 0; d < 3; ++d) X.cb[d][t] = 0.0;
     return;
   }
+  double pb[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) pb[v] = PB.p[v][t];
   // p = (gamma - 1) (e - rho |u|^2 / 2 - |bc|^2 / 2), u = m / rho
   const double rho = X.prim[0][t], p_b = pb[4], gm1 = gamma - 1.0;
   const double u[3] = {X.prim[1][t], X.prim[2][t], X.prim[3][t]};
@@ -487,13 +637,18 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   LAUNCH(k_adj_zero3, nb, G, X);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
   LAUNCH(k_adj_edge<RECON>, nb, S, G, W, X, p->eta, W.stop);
+  if (const int rc = face_lines<RECON>(st, G, S, W, X, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
-  hipLaunchKernelGGL((k_adj_fgather<RECON>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
+  hipLaunchKernelGGL(k_adj_fgather, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
                      W.stop);
   hipLaunchKernelGGL((k_adj_friemann<RECON, RIEMANN>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, X,
                      p->gamma, W.stop);
   if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint faces");
-  LAUNCH(k_adj_cell<RECON>, nb, S, G, X, p->gamma, W.stop);
+  // the primitive adjoints go to ea[0][0..7], free once the face gathers are done
+  PrimPtrs PB;
+  for (int v = 0; v < 8; ++v) PB.p[v] = X.ea[0][v];
+  if (const int rc = cell_lines<RECON>(st, G, X, PB.p, W.stop)) return rc;
+  LAUNCH(k_adj_cfinish, nb, G, X, PB, p->gamma, W.stop);
   LAUNCH(k_adj_bsum, nb, G, X, W.stop);
   return CTMHD_OK;
 }

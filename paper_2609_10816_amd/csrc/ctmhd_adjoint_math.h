@@ -139,29 +139,6 @@ CTMHD_HD void recon_cell_adj5(const T q[5], T lob, T hib, T qb[5]) {
     recon_cell_adj<M>(q[1], q[2], q[3], lob, hib, qb[1], qb[2], qb[3]);
 }
 
-// Adjoint of the value at position 0 of a line of values at positions
-// -2r .. 2r (x[0 .. 4r], r the reconstruction half-width) through the
-// reconstructions of the centres -r .. r that read it; up[k] and lo[k] are
-// the adjoints of the upper and lower values of centre k - r.
-template <int M, typename T>
-CTMHD_HD T recon_gather_adj(const T* x, const T* up, const T* lo) {
-  constexpr int r = recon_halfwidth(M);
-  T acc = T(0);
-#pragma unroll
-  for (int k = 0; k <= 2 * r; ++k) {
-    T q[5], qb[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      // offset m - 2 from centre k - r: position k - r + m - 2, index k + m - 2 + r
-      q[m] = (m - 2 >= -r && m - 2 <= r) ? x[k + m - 2 + r] : T(0);
-      qb[m] = T(0);
-    }
-    recon_cell_adj5<M>(q, lo[k], up[k], qb);
-    acc += qb[2 + r - k];  // position 0 is offset r - k from centre k - r
-  }
-  return acc;
-}
-
 // ---------------------------------------------------------------------------
 // Fast magnetosonic speed (eq. waves:fast-speed).
 // ---------------------------------------------------------------------------

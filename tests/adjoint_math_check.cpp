@@ -247,15 +247,13 @@ static void check_ld04() {
 
 // ---- reconstruction ----
 // A line of 13 values; the centres 2 .. 10 (whose five-point windows lie in
-// the line) carry random adjoints of their lower and upper values.  The
-// scatter form (recon_cell_adj5 per centre) is checked against central
-// differences, the gather form (recon_gather_adj per position) against the
-// scatter form where every centre that reads the position carries adjoints.
+// the line) carry random adjoints of their lower and upper values; the
+// adjoint (recon_cell_adj5 per centre, summed) is checked against central
+// differences.
 template <int M>
 static void check_recon(const char* name, int* branches) {
-  constexpr int r = recon_halfwidth(M);
   constexpr int L = 13;
-  double worst = 0, gworst = 0;
+  double worst = 0;
   int n = 0;
   for (int it = 0; it < 40000 && n < 4000; ++it) {
     double q[L], dq[L], lob[L] = {0}, hib[L] = {0};
@@ -300,23 +298,10 @@ static void check_recon(const char* name, int* branches) {
       ad += qs[k] * dq[k];
       sc += std::fabs(qs[k] * dq[k]);
     }
-    for (int p = 2 + r; p <= L - 3 - r; ++p) {  // positions whose centres all carry adjoints
-      double x[9], up[5], lo[5];
-      for (int k = 0; k <= 4 * r; ++k) x[k] = q[p - 2 * r + k];
-      for (int k = 0; k <= 2 * r; ++k) {
-        up[k] = hib[p - r + k];
-        lo[k] = lob[p - r + k];
-      }
-      double gk = recon_gather_adj<M>(x, up, lo);
-      gworst = std::fmax(gworst, std::fabs(gk - qs[p]) / (std::fabs(qs[p]) + 1.0));
-    }
     const double fd = (jp - jm) / (2 * h);
     worst = std::fmax(worst, relmis(ad, fd, sc));
     ++n;
   }
-  char lab[64];
-  std::snprintf(lab, sizeof(lab), "%s gather = scatter", name);
-  report(lab, gworst, 1e-14);
   report(name, worst, 1e-7);
   if (n < 1000) {
     std::printf("%s: only %d samples away from limiter kinks\n", name, n);
