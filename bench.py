@@ -25,8 +25,8 @@ Beside the headline line's FP64 value the same JSON line carries the other
 forms: fp32_form (the same workload in the FP32 form), batched_form (2000
 AMR-like boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against
 one ctmhd_step call per box) and adjoint_form (64^3 gradient of the kinetic
-energy after 20 steps through the hand-written adjoint, backward / forward
-time).
+energy after 20 steps through the hand-written adjoint, PLM and PPM: backward /
+forward time of the rollout, and one adjoint step against one forward step).
 """
 from __future__ import annotations
 
@@ -227,14 +227,52 @@ def run_batched_form(K, W, log_tune=True):
     return out
 
 
-def run_adjoint_form(nsteps=20, every=5, reps=2):
+def _adjoint_step_times(P, cons, bf, dx, calls=20):
+    """Mean time of one forward step (ctmhd_step with a frozen dt) and of one
+    adjoint step (ctmhd_step_adjoint) on the same box, over `calls` calls
+    each after a warm-up call.  The dt is the CFL dt of the first step."""
+    import torch
+
+    from paper_2609_10816_amd import ctmhd
+
+    ng = ctmhd.required_ghosts(P)
+    S = ctmhd.BoxState.from_numpy(cons, bf, ng, dx)
+    G = ctmhd.BoxState.from_numpy(cons, bf, ng, dx)  # any cotangent
+    O = ctmhd.BoxState(S.n, ng, dx)
+    dev = S.cons[0].device
+    ws_f = torch.empty(ctmhd.workspace_bytes(P, S.box), dtype=torch.uint8, device=dev)
+    ws_a = torch.empty(ctmhd.adjoint_workspace_bytes(P, S.box), dtype=torch.uint8, device=dev)
+    dtt = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctmhd.ctmhd_step(P, S.box, S.cons, S.bface, 1, None, dtt, None, ws_f)
+
+    def fwd():
+        ctmhd.ctmhd_step(P, S.box, S.cons, S.bface, 1, dtt, None, None, ws_f)
+
+    def adj():
+        ctmhd.ctmhd_step_adjoint(P, S.box, S.cons, S.bface, dtt, G.cons, G.bface, O.cons,
+                                 O.bface, ws_a)
+
+    out = []
+    for f in (fwd, adj):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            f()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) / calls * 1e3)
+    return out
+
+
+def run_adjoint_form(nsteps=20, every=5, reps=3):
     """The derivative workload: 64^3 smooth periodic box (3 sine modes of
-    amplitude 0.05 per field, beta = 1), PLM-MC + HLLD + Q26 + LD04, FP64, no
-    flux correction; loss = total kinetic energy after `nsteps` steps; the
-    gradient with respect to the initial velocity and face field through the
-    hand-written adjoint with a checkpoint every `every` steps.  Times the
-    forward rollout alone and the backward pass (recomputation + adjoint
-    steps); the last of `reps` repetitions is reported."""
+    amplitude 0.05 per field, beta = 1), PLM-MC or PPM + HLLD + Q26 + LD04,
+    FP64, no flux correction; loss = total kinetic energy after `nsteps`
+    steps; the gradient with respect to the initial velocity and face field
+    through the hand-written adjoint with a checkpoint every `every` steps.
+    Times the forward rollout alone and the backward pass (recomputation +
+    adjoint steps), the fastest of `reps` repetitions each, and one adjoint
+    step against one forward step of the same box."""
     import numpy as np
     import torch
 
@@ -251,35 +289,44 @@ def run_adjoint_form(nsteps=20, every=5, reps=2):
     p = torch.tensor((5.0 / 3.0 - 1.0) * (cons[4] - 0.5 * (cons[1:4] ** 2).sum(0) / cons[0] -
                                           0.5 * (bc ** 2).sum(0)), device=dev)
     b0 = torch.tensor(bf, device=dev)
-    P = ctmhd.make_params(recon="plm", riemann="hlld", emf="q26", eta=0.0, fofc=False)
-    res = {}
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.no_grad():
-            ad.rollout(ad.conserved_from_primitives(rho, u0, p, b0), b0, P, dx, nsteps, every=every)
-        torch.cuda.synchronize()
-        tf = time.perf_counter() - t0
-        u = u0.clone().requires_grad_(True)
-        b = b0.clone().requires_grad_(True)
-        c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, nsteps, every=every)
-        ke = ad.kinetic_energy(c, dx)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ke.backward()
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t1
-        res = {"forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "ratio": tb / tf,
-               "grad_norm_u": float(u.grad.norm()), "grad_norm_b": float(b.grad.norm())}
-    log(f"adjoint form: forward {res['forward_ms']:.1f} ms, backward {res['backward_ms']:.1f} ms "
-        f"(ratio {res['ratio']:.2f})")
-    return {"workload": "smooth-64^3-amp0.05-beta1-plm-hlld-q26-ld04", "dtype": "f64",
-            "steps": nsteps, "checkpoint_every": every,
-            "loss": "total kinetic energy after the steps",
-            "gradient": "d loss / d (initial velocity, initial face field)",
-            "forward_ms": res["forward_ms"], "backward_ms": res["backward_ms"],
-            "ratio_backward_to_forward": res["ratio"],
-            "grad_norm_u": res["grad_norm_u"], "grad_norm_b": res["grad_norm_b"]}
+    out = {"workload": "smooth-64^3-amp0.05-beta1-hlld-q26-ld04", "dtype": "f64",
+           "steps": nsteps, "checkpoint_every": every,
+           "loss": "total kinetic energy after the steps",
+           "gradient": "d loss / d (initial velocity, initial face field)",
+           "timing": f"fastest of {reps} repetitions"}
+    for recon in ("plm", "ppm"):
+        P = ctmhd.make_params(recon=recon, riemann="hlld", emf="q26", eta=0.0, fofc=False)
+        tf_best = tb_best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.no_grad():
+                ad.rollout(ad.conserved_from_primitives(rho, u0, p, b0), b0, P, dx, nsteps,
+                           every=every)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            u = u0.clone().requires_grad_(True)
+            b = b0.clone().requires_grad_(True)
+            c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, nsteps,
+                              every=every)
+            ke = ad.kinetic_energy(c, dx)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ke.backward()
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t1
+            tf_best = tf if tf_best is None else min(tf_best, tf)
+            tb_best = tb if tb_best is None else min(tb_best, tb)
+        f_ms, a_ms = _adjoint_step_times(P, cons, bf, dx)
+        out[recon] = {"forward_ms": tf_best * 1e3, "backward_ms": tb_best * 1e3,
+                      "ratio_backward_to_forward": tb_best / tf_best,
+                      "step_forward_ms": f_ms, "step_adjoint_ms": a_ms,
+                      "ratio_adjoint_step_to_forward_step": a_ms / f_ms,
+                      "grad_norm_u": float(u.grad.norm()), "grad_norm_b": float(b.grad.norm())}
+        log(f"adjoint form {recon}: rollout forward {tf_best * 1e3:.1f} ms, backward "
+            f"{tb_best * 1e3:.1f} ms (ratio {tb_best / tf_best:.2f}); one step {f_ms:.3f} ms, "
+            f"its adjoint {a_ms:.3f} ms (ratio {a_ms / f_ms:.2f})")
+    return out
 
 
 def cpu_baseline(cfg, emf, state, min_seconds=10.0, max_steps=20):
