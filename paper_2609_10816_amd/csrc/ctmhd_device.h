@@ -422,30 +422,46 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
   return fb;
 }
 
-template <typename T>
-__device__ __forceinline__ T lane_shfl(T v, int src) {
-  return __shfl(v, src, 64);
+// Value of the neighbouring lane (l - 1 for lane_prev, l + 1 for lane_next)
+// by a DPP whole-wavefront shift, a VALU move; lane 0 (63) receives 0.
+__device__ __forceinline__ int dpp_prev(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ int dpp_next(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ __forceinline__ double lane_prev(double v) {
+  return __hiloint2double(dpp_prev(__double2hiint(v)), dpp_prev(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  return __hiloint2double(dpp_next(__double2hiint(v)), dpp_next(__double2loint(v)));
+}
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(dpp_prev(__float_as_int(v)));
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(dpp_next(__float_as_int(v)));
 }
 
 // x faces: one wavefront holds 64 consecutive cells of a row; lane l forms
 // the primitives, the limited slope and the upper interface value of its own
-// cell, neighbours come from cross-lane shuffles, and the face at lane l takes
-// the upper value of lane l-1.  Faces at lanes [r+1, 63-r] are resolved
+// cell, neighbours come from whole-wavefront DPP shifts by one lane, and the
+// face at lane l takes the upper value of lane l-1.  Faces at lanes [r+1, 63-r] are resolved
 // (overlapping segments).
 template <int RECON, typename T>
-__device__ __forceinline__ void recon_lanes(T q, int lane, T& qm, T& qp) {
+__device__ __forceinline__ void recon_lanes(T q, T& qm, T& qp) {
   if constexpr (RECON == kPC) {
     qm = q;
     qp = q;
   } else if constexpr (RECON == kPLM_MC || RECON == kPLM_MM) {
-    T s = T(0.5) * plm_slope<RECON>(lane_shfl(q, lane - 1), q, lane_shfl(q, lane + 1));
+    T s = T(0.5) * plm_slope<RECON>(lane_prev(q), q, lane_next(q));
     qm = q - s;
     qp = q + s;
   } else {
-    T qr = lane_shfl(q, lane + 1);
-    T dm = ppm_slope(lane_shfl(q, lane - 1), q, qr);
-    T ihi = ppm_iface(q, qr, dm, lane_shfl(dm, lane + 1));
-    T ilo = lane_shfl(ihi, lane - 1);
+    T qr = lane_next(q);
+    T dm = ppm_slope(lane_prev(q), q, qr);
+    T ihi = ppm_iface(q, qr, dm, lane_next(dm));
+    T ilo = lane_prev(ihi);
     ppm_constrain(q, ilo, ihi);
     qm = ilo;
     qp = ihi;
@@ -484,10 +500,10 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
     face_local_raw<T>(cur, 0, gamma, v);
     T qm[7], qp[7];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], lane, qm[k], qp[k]);
+    for (int k = 0; k < 7; ++k) recon_lanes<RECON>(v[k], qm[k], qp[k]);
     T qL[7];
 #pragma unroll
-    for (int k = 0; k < 7; ++k) qL[k] = lane_shfl(qp[k], lane - 1);
+    for (int k = 0; k < 7; ++k) qL[k] = lane_prev(qp[k]);
     const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
     if (face) {
       const int s3[3] = {x, y, z};
