@@ -350,6 +350,25 @@ def cpu_baseline(cfg, emf, state, min_seconds=10.0, max_steps=20):
                       f"({n3 * steps / 1e6:.2f} M cell-updates), {el:.1f} s"}
 
 
+def cpu_baseline_one_core(cfg, emf, n=64):
+    """The oracle on one thread: one step of the n^3 box of the same recipe."""
+    import oracle
+    from paper_2609_10816_amd import inputs
+    cons, bf, info = getattr(inputs, cfg["recipe"])(n)
+    Q = oracle.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3)
+    nthr = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(Q, cons, bf, info["dx"], nsteps=1)
+        el = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nthr)
+    return {"value": n ** 3 / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 step of a {n}^3 box of the same recipe ({n ** 3 / 1e6:.2f} M "
+                      f"cell-updates), {el:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +446,10 @@ def main():
         out["adjoint_form"] = run_adjoint_form()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.emf, state)
+        out["cpu_baseline_one_core"] = cpu_baseline_one_core(cfg, args.emf)
+        log(f"oracle: {out['cpu_baseline']['value']:.3f} Mcell-updates/s on "
+            f"{out['cpu_baseline']['cores']} threads, "
+            f"{out['cpu_baseline_one_core']['value']:.3f} on one")
     print(json.dumps(out), flush=True)
 
 

@@ -1008,6 +1008,7 @@ int oracle_count_step(const Params* P, const int n[3], const double dx[3], const
 
 // Threads the parallel loops use.
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 // ---- unit-level entry points used by the pinning tests -------------------
 void oracle_recon1d(int method, const double q[5], double* qm, double* qp) {

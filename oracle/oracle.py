@@ -74,12 +74,20 @@ def lib():
         L.oracle_fluxes.argtypes = [P, _ip, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only; the
+    results do not depend on it)."""
+    lib().oracle_set_threads(int(n))
 
 
 def _ptr(a, t=_dp):
