@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------
 // Line gathers: out[f] (=, or += with acc) the adjoint of X[f] through the
 // reconstructions along one axis whose upper / lower values have the adjoints
-// UP (stored at the upper face of each centre) and LO (at its lower face),
-// the same sum as gather_along, for every position of the box.  Each centre's
+// UP (stored at the upper face of each centre) and LO (at its lower face):
+// the sum over the 2r+1 centres whose stencil holds f, for every position of
+// the box.  Each centre's
 // reconstruction is reversed once: along x by the 64 lanes of a wavefront
 // (stencil values and the five contributions by cross-lane shuffles), along y
 // and z by a thread marching through a segment of a line with the values and
