@@ -76,3 +76,38 @@ def test_unsupported_averaging():
     p = ctmhd.make_params()
     p.emf_average = 1
     assert _call_step(p, ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3)) == -2
+
+
+def test_tile_knob_validation():
+    b = ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3)
+    ok = ctmhd.make_params(tile=ctmhd.make_tile(chunk=16, strips=2, xrows=8))
+    assert _call_step(ok, b) == -1  # passes the knob check, stops at the missing workspace
+    assert b"workspace" in ctmhd.lib().ctmhd_last_error()
+    for bad in (1 << 17, 1 << 20, -1):
+        p = ctmhd.make_params(tile=bad)
+        assert _call_step(p, b) == -1
+        assert b"tile" in ctmhd.lib().ctmhd_last_error()
+
+
+def test_adjoint_configurations_and_workspace_query():
+    b = ctmhd.make_box((8, 8, 8), 4, (0.1,) * 3)
+    for kw in (dict(recon="pc"), dict(recon="plm"), dict(recon="plm_minmod"), dict(recon="ppm"),
+               dict(recon="ppm", riemann="llf"), dict(recon="plm", eta=1e-3, cfl=0.3)):
+        p = ctmhd.make_params(fofc=False, **kw)
+        assert ctmhd.adjoint_workspace_bytes(p, b) > ctmhd.workspace_bytes(p, b), kw
+    for kw in (dict(precision="fp32"), dict(emf="b25a"), dict(emf="fs18")):
+        assert ctmhd.adjoint_workspace_bytes(ctmhd.make_params(**kw), b) == 0, kw
+        assert b"adjoint" in ctmhd.lib().ctmhd_last_error()
+
+
+def test_adjoint_rejects_null_pointers_before_any_device_call():
+    L = ctmhd.lib()
+    p = ctmhd.make_params(recon="plm", fofc=False)
+    b = ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3)
+    d = 256  # never dereferenced: validation fails first
+    c5 = ctmhd._PTR5(*([d] * 5))
+    c3 = ctmhd._PTR3(*([d] * 3))
+    rc = L.ctmhd_step_adjoint(ctypes.byref(p), ctypes.byref(b), c5, c3, None, c5, c3, c5, c3,
+                              None, 0, None)
+    assert rc == -1
+    assert b"NULL" in L.ctmhd_last_error()
