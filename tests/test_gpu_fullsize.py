@@ -1,6 +1,6 @@
-"""Parity at full size: the 256^3 Mach-2, beta-1, eta = 1e-3 turbulent box
-(PPM + HLLD + Q26/B25a + LD04, FP64), one step in the launch configuration the
-benchmark times.
+"""Parity at full size, one step in the launch configuration the benchmark
+times: the 256^3 Mach-2, beta-1, eta = 1e-3 turbulent box (PPM + HLLD +
+Q26/B25a + LD04, FP64) and the 128^3 Mach-5 box of the headline figure.
 
 The oracle cannot step 16.7 M cells quickly, but one step only couples a cell
 to its neighbours within a bounded distance (reconstruction half-width 2, the
@@ -33,10 +33,22 @@ def _crop(a, k, j, i):
 def test_full_size_256_sampled(emf):
     n = 256
     cons, bf, info = inputs.turbulent_mach2_beta1(n)
-    dx = info["dx"]
-    P = ctmhd.make_params(recon="ppm", emf=emf, eta=1e-3)
+    _sampled_parity(cons, bf, info["dx"], n, dict(recon="ppm", emf=emf, eta=1e-3), f"256^3 {emf}")
+
+
+def test_full_size_128_headline_sampled():
+    """The benchmark's own workload: 128^3 Mach-5 turbulent box, PPM + HLLD +
+    Q26 + LD04, FP64, flux correction on, CFL 0.3."""
+    n = 128
+    cons, bf, info = inputs.turbulent_mach5(n)
+    _sampled_parity(cons, bf, info["dx"], n, dict(recon="ppm", emf="q26", eta=0.0),
+                    "128^3 Mach-5 q26")
+
+
+def _sampled_parity(cons, bf, dx, n, Q, label):
+    P = ctmhd.make_params(**Q)
     cg, bg, dtg, dg = ctmhd.run(P, cons, bf, dx, 1)
-    Q = dict(recon="ppm", emf=emf, eta=1e-3)
+    emf = Q["emf"]
     dt_oracle = oracle.cfl_dt(Q, cons, bf, dx)
     assert dtg[0] == pytest.approx(dt_oracle, rel=1e-13)
     # whole-box invariants of the GPU result
@@ -64,5 +76,5 @@ def test_full_size_256_sampled(emf):
             d = abs(bg[a, k, j, i] - bo[a, HW, HW, HW]) / bscale
             worst = max(worst, d)
             assert d <= 1e-12, (emf, (k, j, i), "b", a, d)
-    print(f"[fullsize] 256^3 {emf}: dt {dtg[0]:.6e} (oracle {dt_oracle:.6e}), 16 sampled cells, "
+    print(f"[fullsize] {label}: dt {dtg[0]:.6e} (oracle {dt_oracle:.6e}), 16 sampled cells, "
           f"worst scaled difference {worst:.2e}, flagged {int(dg[0, :2].sum())}", flush=True)
