@@ -7,7 +7,11 @@ through the hand-written adjoint of the step (ctmhd_step_adjoint).
 
 The step is differentiated with its dt values frozen (taken from the forward
 rollout, or given) and without flux correction, so the library is called with
-fofc = 0 in both directions.  The forward keeps a copy of the state every
+fofc = 0 in both directions.  With params in the FP32 form the forward steps
+(and their recomputation) run in that form, and each adjoint step is the FP64
+adjoint evaluated at the FP32-form states: the gradient of the FP64 step
+along the FP32-form trajectory, whose states differ from the FP64 ones at the
+FP32 form's error level.  The forward keeps a copy of the state every
 `every` steps; the backward pass restores each checkpoint, recomputes the
 states of that segment and applies the adjoint step by step, newest first.
 Memory: nsteps / every + every states; work: one forward, one forward
@@ -27,6 +31,10 @@ class _Box:
 
     def __init__(self, params: ctmhd.Params, n, dx, device):
         self.params = params
+        # the adjoint is built for the FP64 form; the FP32 form's forward is
+        # differentiated through it
+        self.adj_params = ctmhd.Params.from_buffer_copy(params)
+        self.adj_params.precision = ctmhd.PRECISION["fp64"]
         self.ng = ctmhd.required_ghosts(params)
 
         def packed():
@@ -41,7 +49,7 @@ class _Box:
         self.g_out, self.gout_buf = packed()
         self.step_ws = torch.empty(ctmhd.workspace_bytes(params, self.state.box), dtype=torch.uint8,
                                    device=device)
-        nb = ctmhd.adjoint_workspace_bytes(params, self.state.box)
+        nb = ctmhd.adjoint_workspace_bytes(self.adj_params, self.state.box)
         if nb == 0:
             raise ctmhd.CtmhdError("this configuration has no adjoint: "
                                    + ctmhd.lib().ctmhd_last_error().decode())
@@ -71,8 +79,8 @@ class _Box:
         (5|3, n2, n1, n0) tensors); the state is left unchanged."""
         self.gin_buf[(slice(0, 5),) + self.sl[1:]] = gc
         self.gin_buf[(slice(5, 8),) + self.sl[1:]] = gb
-        ctmhd.ctmhd_step_adjoint(self.params, self.state.box, self.state.cons, self.state.bface, dt,
-                                 self.g_in.cons, self.g_in.bface, self.g_out.cons,
+        ctmhd.ctmhd_step_adjoint(self.adj_params, self.state.box, self.state.cons, self.state.bface,
+                                 dt, self.g_in.cons, self.g_in.bface, self.g_out.cons,
                                  self.g_out.bface, self.adj_ws)
         v = self.gout_buf[self.sl]
         return v[:5].clone(), v[5:].clone()
@@ -123,8 +131,8 @@ class _Rollout(torch.autograd.Function):
 
 def rollout(cons, bface, params: ctmhd.Params, dx, nsteps, every=5, dt_fixed=None):
     """Differentiable `nsteps`-step rollout (see the module docstring).  The
-    library parameters must have fofc = 0; dt_fixed: None (CFL dt from the
-    forward rollout, then frozen) or nsteps values."""
+    library parameters must have fofc = 0 (FP64 or FP32 form); dt_fixed: None
+    (CFL dt from the forward rollout, then frozen) or nsteps values."""
     if params.fofc:
         raise ValueError("the differentiable rollout takes steps without flux correction (fofc=0)")
     if every < 1:
