@@ -10,6 +10,8 @@
 // degenerate star states, HLL fallback).  Adjoint arguments accumulate (+=).
 #pragma once
 
+#include <type_traits>
+
 #include "ctmhd_math.h"
 
 namespace ctmhd {
@@ -280,24 +282,30 @@ template <typename T>
 CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamma, const T Fb[5],
                             T SLbar, T SRbar, FState<T>& Lb, FState<T>& Rb, T& bnb) {
   const T gm1inv = T(1) / (gamma - T(1));
-  T UL[5], FL[5], UR[5], FR[5], pTL, pTR;
-  phys_flux(L, bn, gm1inv, UL, FL, pTL);
-  phys_flux(R, bn, gm1inv, UR, FR, pTR);
+  // The outer conserved states and fluxes (phys_flux) are formed where the
+  // reverse reads them rather than kept live across the fan; the fan needs
+  // only their total pressures and energies.  Their adjoints go through
+  // phys_flux_adj as soon as they are complete (it is linear in them).
+  T pTL, pTR, eL, eR;
+  {
+    T U[5], F[5];
+    phys_flux(L, bn, gm1inv, U, F, pTL);
+    eL = U[4];
+    phys_flux(R, bn, gm1inv, U, F, pTR);
+    eR = U[4];
+  }
   const T cfL = fast_speed(L.rho, L.p, bn, L.bt1, L.bt2, gamma);
   const T cfR = fast_speed(R.rho, R.p, bn, R.bt1, R.bt2, gamma);
   const T cmax = tmax(cfL, cfR);
   const T SL = tmin(L.un, R.un) - cmax;
   const T SR = tmax(L.un, R.un) + cmax;
-  T ULb[5], FLb[5], URb[5], FRb[5], pTLb = T(0), pTRb = T(0);
-#pragma unroll
-  for (int m = 0; m < 5; ++m) ULb[m] = FLb[m] = URb[m] = FRb[m] = T(0);
+  T pTLb = T(0), pTRb = T(0), eLb = T(0), eRb = T(0);
+  const T zero5[5] = {T(0), T(0), T(0), T(0), T(0)};
 
   if (SL > T(0)) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) FLb[m] += Fb[m];
+    phys_flux_adj(L, bn, gm1inv, zero5, Fb, T(0), Lb, bnb);
   } else if (SR < T(0)) {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) FRb[m] += Fb[m];
+    phys_flux_adj(R, bn, gm1inv, zero5, Fb, T(0), Rb, bnb);
   } else {
     // ---- forward of the fan (same operations as hlld_flux) ----
     const T bn2 = bn * bn;
@@ -340,43 +348,39 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     const T vbR = R.un * bn + R.ut1 * R.bt1 + R.ut2 * R.bt2;
     const T vbsL = SM * bn + vsL * bysL + wsL * bzsL;
     const T vbsR = SM * bn + vsR * bysR + wsR * bzsR;
-    const T NeL = dL * UL[4] - pTL * L.un + pTs * SM + bn * (vbL - vbsL);
-    const T NeR = dR * UR[4] - pTR * R.un + pTs * SM + bn * (vbR - vbsR);
+    const T NeL = dL * eL - pTL * L.un + pTs * SM + bn * (vbL - vbsL);
+    const T NeR = dR * eR - pTR * R.un + pTs * SM + bn * (vbR - vbsR);
     const T esL = NeL * idsL, esR = NeR * idsR;
     const bool bad = !(rsL > T(0)) || !(rsR > T(0)) || !(pTs > T(0)) || !(SL < SM) ||
                      !(SM < SR) || !tfinite(SM) || !tfinite(vsL + wsL + bysL + bzsL + esL) ||
                      !tfinite(vsR + wsR + bysR + bzsR + esR);
     if (bad) {
       if (SL >= T(0)) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) FLb[m] += Fb[m];
+        phys_flux_adj(L, bn, gm1inv, zero5, Fb, T(0), Lb, bnb);
       } else if (SR <= T(0)) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) FRb[m] += Fb[m];
+        phys_flux_adj(R, bn, gm1inv, zero5, Fb, T(0), Rb, bnb);
       } else {
         // F = (SR FL - SL FR + SL SR (UR - UL)) / (SR - SL)
+        T UL[5], FL[5], UR[5], FR[5], pd;
+        phys_flux(L, bn, gm1inv, UL, FL, pd);
+        phys_flux(R, bn, gm1inv, UR, FR, pd);
         const T iw = T(1) / (SR - SL);
+        T ULb[5], FLb[5], URb[5], FRb[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
           const T N = SR * FL[m] - SL * FR[m] + SL * SR * (UR[m] - UL[m]);
-          FLb[m] += Fb[m] * SR * iw;
-          FRb[m] -= Fb[m] * SL * iw;
-          URb[m] += Fb[m] * SL * SR * iw;
-          ULb[m] -= Fb[m] * SL * SR * iw;
+          FLb[m] = Fb[m] * SR * iw;
+          FRb[m] = -Fb[m] * SL * iw;
+          URb[m] = Fb[m] * SL * SR * iw;
+          ULb[m] = -Fb[m] * SL * SR * iw;
           SRbar += Fb[m] * (FL[m] + SL * (UR[m] - UL[m])) * iw - Fb[m] * N * iw * iw;
           SLbar += Fb[m] * (-FR[m] + SR * (UR[m] - UL[m])) * iw + Fb[m] * N * iw * iw;
         }
+        phys_flux_adj(L, bn, gm1inv, ULb, FLb, T(0), Lb, bnb);
+        phys_flux_adj(R, bn, gm1inv, URb, FRb, T(0), Rb, bnb);
       }
     } else {
-      const T UsL[5] = {rsL, rsL * SM, rsL * vsL, rsL * wsL, esL};
-      const T UsR[5] = {rsR, rsR * SM, rsR * vsR, rsR * wsR, esR};
       T SsL = SM, SsR = SM;
-      T UssL[5], UssR[5];
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        UssL[m] = UsL[m];
-        UssR[m] = UsR[m];
-      }
       const bool dstar = !(bn2 <= T(1e-12) * pTs);
       T sg = T(0), sqL = T(0), sqR = T(0), abn = T(0), isum = T(0);
       T vss = T(0), wss = T(0), byss = T(0), bzss = T(0), vbss = T(0);
@@ -398,55 +402,61 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
         byss = Nby * isum;
         bzss = Nbz * isum;
         vbss = SM * bn + vss * byss + wss * bzss;
-        UssL[2] = rsL * vss;
-        UssL[3] = rsL * wss;
-        UssL[4] = esL - sqL * (vbsL - vbss) * sg;
-        UssR[2] = rsR * vss;
-        UssR[3] = rsR * wss;
-        UssR[4] = esR + sqR * (vbsR - vbss) * sg;
       }
       // ---- reverse ----
       T UsLb[5], UsRb[5], UssLb[5], UssRb[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) UsLb[m] = UsRb[m] = UssLb[m] = UssRb[m] = T(0);
       T SsLb = T(0), SsRb = T(0);
-      if (SsL >= T(0)) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {  // F = FL + SL (UsL - UL)
-          FLb[m] += Fb[m];
-          SLbar += Fb[m] * (UsL[m] - UL[m]);
-          UsLb[m] += Fb[m] * SL;
-          ULb[m] -= Fb[m] * SL;
+      // The flux is taken from one side K: F = FK + SK (UsK - UK), plus
+      // SsK (UssK - UsK) in the inner regions.  The outer, star and
+      // double-star conserved states of K are formed here, where the reverse
+      // reads them, instead of being kept live across the fan.
+      auto side = [&](auto left_tag, bool inner) {
+        constexpr bool LEFT = decltype(left_tag)::value;
+        const FState<T>& K = LEFT ? L : R;
+        const T SK = LEFT ? SL : SR, SsK = LEFT ? SsL : SsR;
+        const T rs = LEFT ? rsL : rsR, vs = LEFT ? vsL : vsR, ws = LEFT ? wsL : wsR;
+        const T es = LEFT ? esL : esR;
+        T UK[5], FK[5], pd;
+        phys_flux(K, bn, gm1inv, UK, FK, pd);
+        const T Us[5] = {rs, rs * SM, rs * vs, rs * ws, es};
+        T Uss[5] = {Us[0], Us[1], Us[2], Us[3], Us[4]};
+        if (dstar) {
+          Uss[2] = rs * vss;
+          Uss[3] = rs * wss;
+          Uss[4] = LEFT ? esL - sqL * (vbsL - vbss) * sg : esR + sqR * (vbsR - vbss) * sg;
         }
-      } else if (SM >= T(0)) {
+        T UKb[5], SKbar = T(0), SsKb = T(0);
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {  // F = FL + SL (UsL - UL) + SsL (UssL - UsL)
-          FLb[m] += Fb[m];
-          SLbar += Fb[m] * (UsL[m] - UL[m]);
-          UsLb[m] += Fb[m] * (SL - SsL);
-          ULb[m] -= Fb[m] * SL;
-          SsLb += Fb[m] * (UssL[m] - UsL[m]);
-          UssLb[m] += Fb[m] * SsL;
+        for (int m = 0; m < 5; ++m) {
+          SKbar += Fb[m] * (Us[m] - UK[m]);
+          UKb[m] = -Fb[m] * SK;
+          if (inner) {
+            (LEFT ? UsLb : UsRb)[m] += Fb[m] * (SK - SsK);
+            SsKb += Fb[m] * (Uss[m] - Us[m]);
+            (LEFT ? UssLb : UssRb)[m] += Fb[m] * SsK;
+          } else {
+            (LEFT ? UsLb : UsRb)[m] += Fb[m] * SK;
+          }
         }
-      } else if (SsR >= T(0)) {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {  // F = FR + SR (UsR - UR) + SsR (UssR - UsR)
-          FRb[m] += Fb[m];
-          SRbar += Fb[m] * (UsR[m] - UR[m]);
-          UsRb[m] += Fb[m] * (SR - SsR);
-          URb[m] -= Fb[m] * SR;
-          SsRb += Fb[m] * (UssR[m] - UsR[m]);
-          UssRb[m] += Fb[m] * SsR;
+        if constexpr (LEFT) {
+          SLbar += SKbar;
+          SsLb += SsKb;
+        } else {
+          SRbar += SKbar;
+          SsRb += SsKb;
         }
-      } else {
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {  // F = FR + SR (UsR - UR)
-          FRb[m] += Fb[m];
-          SRbar += Fb[m] * (UsR[m] - UR[m]);
-          UsRb[m] += Fb[m] * SR;
-          URb[m] -= Fb[m] * SR;
-        }
-      }
+        phys_flux_adj(K, bn, gm1inv, UKb, Fb, T(0), LEFT ? Lb : Rb, bnb);
+      };
+      if (SsL >= T(0))
+        side(std::integral_constant<bool, true>(), false);
+      else if (SM >= T(0))
+        side(std::integral_constant<bool, true>(), true);
+      else if (SsR >= T(0))
+        side(std::integral_constant<bool, false>(), true);
+      else
+        side(std::integral_constant<bool, false>(), false);
       T SMb = T(0), rsLb = T(0), rsRb = T(0), esLb = T(0), esRb = T(0);
       T vsLb = T(0), wsLb = T(0), bysLb = T(0), bzsLb = T(0);
       T vsRb = T(0), wsRb = T(0), bysRb = T(0), bzsRb = T(0);
@@ -541,8 +551,8 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       T dLb = T(0), dRb = T(0), pTsb = T(0), idsLb = T(0), idsRb = T(0), vbLb = T(0), vbRb = T(0);
       {
         const T g = esLb * idsL;
-        dLb += g * UL[4];
-        ULb[4] += g * dL;
+        dLb += g * eL;
+        eLb += g * dL;
         pTLb -= g * L.un;
         Lb.un -= g * pTL;
         pTsb += g * SM;
@@ -554,8 +564,8 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       }
       {
         const T g = esRb * idsR;
-        dRb += g * UR[4];
-        URb[4] += g * dR;
+        dRb += g * eR;
+        eRb += g * dR;
         pTRb -= g * R.un;
         Rb.un -= g * pTR;
         pTsb += g * SM;
@@ -697,8 +707,10 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     fast_speed_adj(L.rho, L.p, bn, L.bt1, L.bt2, gamma, cmaxb, Lb.rho, Lb.p, bnb, Lb.bt1, Lb.bt2);
   else
     fast_speed_adj(R.rho, R.p, bn, R.bt1, R.bt2, gamma, cmaxb, Rb.rho, Rb.p, bnb, Rb.bt1, Rb.bt2);
-  phys_flux_adj(L, bn, gm1inv, ULb, FLb, pTLb, Lb, bnb);
-  phys_flux_adj(R, bn, gm1inv, URb, FRb, pTRb, Rb, bnb);
+  // the energies and total pressures the fan read
+  const T eLv[5] = {T(0), T(0), T(0), T(0), eLb}, eRv[5] = {T(0), T(0), T(0), T(0), eRb};
+  phys_flux_adj(L, bn, gm1inv, eLv, zero5, pTLb, Lb, bnb);
+  phys_flux_adj(R, bn, gm1inv, eRv, zero5, pTRb, Rb, bnb);
 }
 
 // ---------------------------------------------------------------------------
