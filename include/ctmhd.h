@@ -169,6 +169,39 @@ int ctmhd_step_batched(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, 
                        const double* dt_fixed, double* dt_out, int64_t* diag, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* One level of boxes (Sec. 2.6: the cell-centred update couples boxes only
+ * through their ghost zones).  The boxes tile the periodic index domain
+ * [0, domain[0]) x [0, domain[1]) x [0, domain[2]) exactly once: box b's
+ * first interior cell has level index origin[3b .. 3b+2] (0 <= origin <
+ * domain), its cells run over n[d] indices from there (wrapping at the domain
+ * end), all boxes share dx, and no two boxes overlap, also through the wrap.
+ * The ghost layers of every box are filled from the interiors of the boxes
+ * that own those cells, at the start of a call and after every update, so
+ * that a level advances exactly as one periodic box of the domain size would
+ * (bitwise: every face and edge on a box boundary is computed by both boxes
+ * from the same values).  Face b_a at the lower face of a box's first cell
+ * belongs to that box; its upper boundary face belongs to the next box.
+ * With fofc on, the invalid-cell flags of the neighbouring boxes are
+ * exchanged too, and a first-order fix-up, when any cell of the level is
+ * flagged, runs on every box (as on one box).  Plan: built on the host
+ * (boxes, origin, domain: HOST arrays) into a buffer of
+ * ctmhd_level_plan_bytes() bytes (0 for bad arguments or a level that does
+ * not tile its domain) and copied by the caller to device memory; it also
+ * holds the ghost exchange table (one rectangular block per pair of box and
+ * owning box image).  Workspace: ctmhd_workspace_bytes() of the same boxes.
+ * ctmhd_step_level: as ctmhd_step_batched with dt_mode CTMHD_DT_GLOBAL (a
+ * level has one dt); the packed layout, dt_fixed, dt_out, diag and the
+ * errors are those of the batched call, and a level that does not tile its
+ * domain returns CTMHD_EARG. */
+size_t ctmhd_level_plan_bytes(const ctmhd_params* p, const ctmhd_box* boxes, const int32_t* origin,
+                              int nbox, const int32_t domain[3]);
+int ctmhd_level_plan(const ctmhd_params* p, const ctmhd_box* boxes, const int32_t* origin, int nbox,
+                     const int32_t domain[3], void* host_plan, size_t bytes);
+int ctmhd_step_level(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const int32_t* origin,
+                     const int32_t domain[3], const void* plan, double* const cons[5],
+                     double* const bface[3], int nsteps, const double* dt_fixed, double* dt_out,
+                     int64_t* diag, void* workspace, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for ctmhd_step_adjoint on this machine (0 for bad arguments or
  * an unsupported configuration). */
 size_t ctmhd_adjoint_workspace_bytes(const ctmhd_params* p, const ctmhd_box* box);

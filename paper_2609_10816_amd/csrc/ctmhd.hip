@@ -60,6 +60,7 @@ int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T
   U.gamma = p->gamma;
   U.sres = sres;
   U.force = p->force_flags ? p->force_flags + (size_t)stage * ninter : nullptr;
+  U.flag_storage = 0;
   LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 0, U, diag, W.stop);
   if (p->fofc) {
     if ((rc = launch_fo<T>(st, p, base, G, W, stage, ninter))) return rc;

@@ -712,6 +712,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   U.gamma = p->gamma;
   U.sres = 0.0;
   U.force = nullptr;
+  U.flag_storage = 0;
 
   // forward: S0 with ghosts, the caller's dt, stage 1 into H = S1
   LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);

@@ -76,7 +76,7 @@ struct Work {
   T* am[3];
   T* us[3];
   T* E[2][3];       // per stage, edge EMFs
-  uint8_t* flag;    // interior cells
+  uint8_t* flag;    // interior cells, x0 fastest; a level of boxes: every storage position
   // CFL maxima (bits of non-negative doubles), kMaxSlots each: [0] fused into
   // the stage-2 update, [1] recomputed by a stage-2 fix-up
   unsigned long long* smax;
@@ -760,6 +760,7 @@ struct UpdateCfg {
   double gamma;
   double sres;       // resistive signal speed term of the CFL maximum
   const uint8_t* force;  // forced flags of this stage or null
+  int flag_storage;  // 1: flags indexed by storage position (a level of boxes)
 };
 
 // fixup = 0: main update (flags, and for stage 1 the CFL maximum into slot 0)
@@ -839,7 +840,7 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
         if ((U.crit & CTMHD_FLAG_P) && !(p > 0.0)) bad = 1;
         if ((U.crit & CTMHD_FLAG_NONFINITE) && (nonfin || !__builtin_isfinite(p))) bad = 1;
         if (U.force && U.force[t]) bad = 1;
-        W.flag[t] = (uint8_t)bad;
+        W.flag[U.flag_storage ? s : t] = (uint8_t)bad;
       }
       if (stage == 1) sig = cfl_signal(rho, u, p, bc, G, U.gamma, U.sres);
     }
@@ -915,27 +916,46 @@ __device__ __forceinline__ T fo_corner_cell(const State& Sn, const Geom& G, int 
   return -(T)u[a] * bbX + (T)u[b] * baY;  // FS18 with PC: cell velocity, edge field
 }
 
-// One thread per interior cell position s: its three lower faces and the
-// three edges at its lower corner.  Stage 1 writes both stored flux sets so
-// that their RK average is the first-order value.  Periodic images of the
-// upper boundary faces / edges are written as well (the update reads them).
+// Flag of the cell at storage coordinates p3: periodic box (interior flags,
+// wrapped) or a level of boxes (flags at every storage position, the ghost
+// layers filled from the neighbouring boxes).
+template <typename T>
+__device__ __forceinline__ uint8_t flag_of(const Geom& G, const Work<T>& W, bool lvl,
+                                           const int p3[3]) {
+  if (lvl) return W.flag[p3[0] + G.st[1] * p3[1] + G.st[2] * p3[2]];
+  return W.flag[interior_id(G, p3[0], p3[1], p3[2])];
+}
+
+// One thread per cell position s: its three lower faces and the three edges
+// at its lower corner.  Stage 1 writes both stored flux sets so that their RK
+// average is the first-order value.
+//   periodic box (lvl false): interior positions; the periodic images of the
+//     upper boundary faces / edges are written as well (the update reads them);
+//   a level of boxes (lvl true): positions 0..n along each axis, so that the
+//     upper boundary faces / edges are computed from this box's ghost cells
+//     and flags (bitwise the values the neighbour that owns them computes).
 template <typename T, int EMF>
 __device__ __forceinline__ void fo_at(const State& Sn, const Geom& G, const Work<T>& W, int stage,
-                                      double gamma, double eta_d, int t) {
-  int nf = G.n[0] * G.n[1] * G.n[2];
-  if (t >= nf) return;
-  const int s3[3] = {t % G.n[0] + G.g, (t / G.n[0]) % G.n[1] + G.g, t / (G.n[0] * G.n[1]) + G.g};
+                                      double gamma, double eta_d, int t, bool lvl) {
+  const int e = lvl ? 1 : 0;
+  const int m0 = G.n[0] + e, m1 = G.n[1] + e;
+  if (t >= m0 * m1 * (G.n[2] + e)) return;
+  const int s3[3] = {t % m0 + G.g, (t / m0) % m1 + G.g, t / (m0 * m1) + G.g};
   const int s = s3[0] + G.st[1] * s3[1] + G.st[2] * s3[2];
-  const bool f0 = W.flag[t] != 0;
+  bool up[3];  // on the upper boundary layer along each axis (level only)
+#pragma unroll
+  for (int d = 0; d < 3; ++d) up[d] = s3[d] == G.g + G.n[d];
+  const bool f0 = flag_of(G, W, lvl, s3) != 0;
   for (int a = 0; a < 3; ++a) {
+    if (up[(a + 1) % 3] || up[(a + 2) % 3]) continue;  // not a face of this box
     int l3[3] = {s3[0], s3[1], s3[2]};
     l3[a] -= 1;
-    if (!f0 && !W.flag[interior_id(G, l3[0], l3[1], l3[2])]) continue;
+    if (!f0 && !flag_of(G, W, lvl, l3)) continue;
     T F[5], us;
     fo_face<T>(Sn, G, s, a, gamma, F, us);
     if (eta_d > 0.0) F[4] += joule<T>(Sn, G, s, a, (T)eta_d);
     for (int rep = 0; rep < 2; ++rep) {
-      if (rep && s3[a] != G.g) break;
+      if (rep && (lvl || s3[a] != G.g)) break;
       const int sw = s + (rep ? G.n[a] * G.st[a] : 0);
       for (int m = 0; m < 5; ++m) {
         W.F[stage][a][m][sw] = F[m];
@@ -945,12 +965,13 @@ __device__ __forceinline__ void fo_at(const State& Sn, const Geom& G, const Work
   }
   for (int c = 0; c < 3; ++c) {
     const int a = (c + 1) % 3, b = (c + 2) % 3;
+    if (up[c]) continue;  // not an edge of this box
     int fl = 0;
     for (int q = 0; q < 4; ++q) {
       int p3[3] = {s3[0], s3[1], s3[2]};
       p3[a] -= (q & 1);
       p3[b] -= (q >> 1);
-      fl |= W.flag[interior_id(G, p3[0], p3[1], p3[2])];
+      fl |= flag_of(G, W, lvl, p3);
     }
     if (!fl) continue;
     const int sa = G.st[a], sb = G.st[b];
@@ -980,6 +1001,7 @@ __device__ __forceinline__ void fo_at(const State& Sn, const Geom& G, const Work
     if (eta_d > 0.0) eps += eta_j<T>(Sn, G, s, c, (T)eta_d);
     for (int qa = 0; qa < 2; ++qa)
       for (int qb = 0; qb < 2; ++qb) {
+        if ((qa || qb) && lvl) continue;
         if ((qa && s3[a] != G.g) || (qb && s3[b] != G.g)) continue;
         const int sw = s + (qa ? G.n[a] * sa : 0) + (qb ? G.n[b] * sb : 0);
         W.E[stage][c][sw] = eps;
@@ -993,7 +1015,7 @@ __global__ void __launch_bounds__(kBlock)
     k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
   if (*stop) return;
   if (W.nflag[stage] == 0) return;
-  fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, gidx());
+  fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, gidx(), false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,11 +1024,29 @@ __global__ void __launch_bounds__(kBlock)
 // first inside a phase), so an item only ever waits for items that precede
 // it in the queue (the previous phase of its own box): with workgroups that
 // claim an item only after finishing the last one, the queue always drains.
-// Each box is a periodic box of its own (ghosts wrapped per box); no data
-// crosses boxes.
+// Each box is a periodic box of its own (ghosts wrapped per box), or the boxes
+// tile one periodic domain (a level of an AMR hierarchy): then the ghost
+// layers of every box are filled from the interiors of the boxes that own
+// those cells (exchange phases after every update).
 // ---------------------------------------------------------------------------
-enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P };
-constexpr int kMaxPhases = 16;
+enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG };
+constexpr int kMaxPhases = 24;
+
+// Exchange phase argument (PlanHeader::xarg): which state to fill, whether
+// the invalid-cell flags travel too, and whether it runs only after a fix-up.
+enum : int { XG_HALF = 0, XG_NEXT = 1, XG_CUR = 2, XG_TARGET = 3, XG_FLAGS = 4, XG_IF_FIXUP = 8 };
+
+// One block of a box's ghost region whose cells are owned by one box (possibly
+// itself, through the periodic wrap): dst and src are packed element indices
+// of the block's first element, in the destination box's ghost region and the
+// owner's interior.
+struct XBlock {
+  long long dst, src;
+  int dsy, dsz, ssy, ssz;  // strides along axes 1 and 2 of both boxes
+  int ex, ey;              // extents along axes 0 and 1 (axis 2: from the volume)
+  int vol_lo;              // first ghost index of the block in its box's list
+  int vol;                 // elements of the block
+};
 
 struct BoxDesc {
   Geom G;
@@ -1025,7 +1065,12 @@ struct PlanHeader {
   int range[3][2];           // phase ranges [lo, hi) of the start, step and copy launches
   int range_items[3];        // items of each launch
   long long order_off, prefix_off, desc_off;  // byte offsets of the arrays below
-  // int order[nbox]; int prefix[nphase][nbox + 1]; BoxDesc desc[nbox]
+  int xarg[kMaxPhases];      // XG_* of exchange phases
+  int level;                 // 1: the boxes tile one periodic domain
+  int nxblk;                 // exchange blocks
+  long long xbox_off, xblk_off;
+  // int order[nbox]; int prefix[nphase][nbox + 1]; BoxDesc desc[nbox];
+  // level only: int xbox[nbox + 1] (first block of each box); XBlock xblk[nxblk]
 };
 constexpr int kPlanMagic = 0x43544d48;
 
@@ -1049,6 +1094,7 @@ struct BatchArgs {
   unsigned long long tab;  // device address of BoxTab<T>[nbox]
   double gamma, eta;
   int fofc, crit;
+  int level;          // the boxes tile one periodic domain
 };
 
 // Everything one box needs, with its pointers already shifted to the box:
@@ -1129,12 +1175,42 @@ __device__ __forceinline__ void signal_count(int* cnt) {
   if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Ghost exchange of a level: element r of box b's ghost region takes the
+// value of the cell (faces: the lower face of the cell) that owns it, for all
+// 8 fields of S and, with `flags`, the invalid-cell flag.  Reads touch only
+// interiors and writes only ghost positions, so one launch serves all boxes.
+template <typename T>
+__device__ __forceinline__ void xchg_at(const BatchArgs<T>& A, const State& S, bool flags, int b,
+                                        int r) {
+  const PlanHeader* P = (const PlanHeader*)A.plan;
+  const int* xbox = (const int*)(A.plan + P->xbox_off);
+  const XBlock* xb = (const XBlock*)(A.plan + P->xblk_off);
+  int k0 = xbox[b], k1 = xbox[b + 1];
+  if (k0 >= k1) return;
+  const XBlock& lastb = xb[k1 - 1];
+  if (r >= lastb.vol_lo + lastb.vol) return;
+  while (k1 - k0 > 1) {  // the block holding r: largest k with vol_lo <= r
+    const int mid = (k0 + k1) >> 1;
+    if (xb[mid].vol_lo <= r) k0 = mid; else k1 = mid;
+  }
+  const XBlock& B = xb[k0];
+  const int l = r - B.vol_lo;
+  const int x = l % B.ex, y = (l / B.ex) % B.ey, z = l / (B.ex * B.ey);
+  const long long d = B.dst + x + (long long)B.dsy * y + (long long)B.dsz * z;
+  const long long s = B.src + x + (long long)B.ssy * y + (long long)B.ssz * z;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) S.c[m][d] = S.c[m][s];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) S.b[a][d] = S.b[a][s];
+  if (flags) A.W.flag[d] = A.W.flag[s];
+}
+
 // One work item of a batched step: phase kind `kind` (run-time; KIND is its
 // compile-time class: PH_U covers PH_U and PH_X, so that the main and the
 // fix-up update share one call site as in k_update) of box b, tile `tile`.
 template <typename T, int RECON, int RIEMANN, int EMF, int KIND>
 __device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kind, int stage,
-                                           int tile, int strips, int cl) {
+                                           int tile, int strips, int cl, int xa) {
   const BoxTab<T>& tb = *(const BoxTab<T>*)((const CTMHD_CONST BoxTab<T>*)A.tab + b);
   const Geom& G = tb.G;
   const State& cur = cl == 0 ? tb.su : tb.sb;
@@ -1172,6 +1248,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kin
       U.gamma = A.gamma;
       U.sres = tb.sres;
       U.force = nullptr;
+      U.flag_storage = A.level;
       const int fix = kind == PH_X ? 1 : 0;
       if (!fix || W.nflag[stage])
         update_item<T>(cur, Hs, stage == 0 ? Hs : oth, G, W, stage, fix, U, A.diag, tile, strips,
@@ -1179,9 +1256,18 @@ __device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kin
     } else if constexpr (KIND == PH_O) {
       if (W.nflag[stage])
         for (int s = 0; s < strips; ++s)
-          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x);
+          fo_at<T, EMF>(cur, G, W, stage, A.gamma, A.eta, (tile * strips + s) * kBlock + threadIdx.x,
+                        A.level != 0);
     } else if constexpr (KIND == PH_WRAP) {
       for (int s = 0; s < strips; ++s) wrap_at(cur, G, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_XCHG) {
+      if ((xa & XG_IF_FIXUP) && !W.nflag[stage]) return;
+      const int tg = xa & XG_TARGET;
+      // packed (unshifted) arrays: the owner of a ghost block is another box
+      const State& dst = tg == XG_HALF ? A.H : tg == XG_CUR ? (cl == 0 ? A.user : A.B)
+                                                              : (cl == 0 ? A.B : A.user);
+      for (int s = 0; s < strips; ++s)
+        xchg_at(A, dst, (xa & XG_FLAGS) != 0, b, (tile * strips + s) * kBlock + threadIdx.x);
     } else if constexpr (KIND == PH_DT) {
       double sig = 0.0;
       for (int s = 0; s < strips; ++s) {
@@ -1208,7 +1294,7 @@ __global__ void __launch_bounds__(kBlock) k_btab(BatchArgs<T> A, int nbox) {
   Work<T> W = shift_work(A.W, d.off);
   W.flag = A.W.flag + d.flag_off;
   W.dt = A.dt + (A.dt_per_box ? b : 0);
-  W.nflag = A.nflag + 4 * b;
+  W.nflag = A.nflag + (A.level ? 0 : 4 * b);  // a level flags and fixes up as one domain
   W.smax = A.slots + 2 * b;
   W.stop = A.stop;
   tb->w = W;
@@ -1271,15 +1357,16 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
     }
     const int kind = P->kind[p], stage = P->stage[p];
     switch (kind) {
-      case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_U:
-      case PH_X: batch_item<T, RECON, RIEMANN, EMF, PH_U>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_O: batch_item<T, RECON, RIEMANN, EMF, PH_O>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_WRAP: batch_item<T, RECON, RIEMANN, EMF, PH_WRAP>(A, b, kind, stage, tile, strips, cl); break;
-      case PH_DT: batch_item<T, RECON, RIEMANN, EMF, PH_DT>(A, b, kind, stage, tile, strips, cl); break;
-      default: batch_item<T, RECON, RIEMANN, EMF, PH_COPY>(A, b, kind, stage, tile, strips, cl); break;
+      case PH_X: batch_item<T, RECON, RIEMANN, EMF, PH_U>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_O: batch_item<T, RECON, RIEMANN, EMF, PH_O>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_WRAP: batch_item<T, RECON, RIEMANN, EMF, PH_WRAP>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_DT: batch_item<T, RECON, RIEMANN, EMF, PH_DT>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_XCHG: batch_item<T, RECON, RIEMANN, EMF, PH_XCHG>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      default: batch_item<T, RECON, RIEMANN, EMF, PH_COPY>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
     }
     signal_count(A.done + (long long)p * nbox + b);
   }
@@ -1299,13 +1386,13 @@ __global__ void __launch_bounds__(kBlock) k_bphase(BatchArgs<T> A, int p) {
   const int k0 = item_box(pre, nbox, r);
   const int b = ((const int*)(A.plan + P->order_off))[k0];
   batch_item<T, RECON, RIEMANN, EMF, KIND>(A, b, P->kind[p], P->stage[p], r - pre[k0], P->strips,
-                                           *A.loc);
+                                           *A.loc, P->xarg[p]);
 }
 
 // dt of a batched step from the per-box CFL maxima (the fix-up maximum where
 // a box's second stage was fixed up); resets the per-step counters.
 __global__ void __launch_bounds__(kBlock)
-    k_bdt_final(int nbox, int nphase, int dt_per_box, unsigned long long* slots, int* nflag,
+    k_bdt_final(int nbox, int nphase, int dt_per_box, int level, unsigned long long* slots, int* nflag,
                 int* done, int* cursor, double cfl, const double* dt_fixed, double* dt,
                 double* dt_out, int* stop, const int* err, long long* diag) {
   __shared__ unsigned long long red[kBlock];
@@ -1313,7 +1400,7 @@ __global__ void __launch_bounds__(kBlock)
   unsigned long long mx = 0;
   const bool stopped = *stop != 0;
   for (int b = t; b < nbox; b += kBlock) {
-    unsigned long long v = nflag[4 * b + 2] ? slots[2 * b + 1] : slots[2 * b];
+    unsigned long long v = nflag[4 * (level ? 0 : b) + 2] ? slots[2 * b + 1] : slots[2 * b];
     mx = v > mx ? v : mx;
     if (dt_per_box) {
       double x = stopped ? 0.0 : (dt_fixed ? dt_fixed[b] : cfl / __longlong_as_double((long long)v));

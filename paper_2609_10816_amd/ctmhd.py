@@ -71,6 +71,14 @@ def lib():
         L.ctmhd_batch_plan.argtypes = [_P, _B, ctypes.c_int, _vp, ctypes.c_size_t]
         L.ctmhd_batch_plan.restype = ctypes.c_int
         L.ctmhd_step_batched.restype = ctypes.c_int
+        _I3 = ctypes.POINTER(ctypes.c_int32)
+        L.ctmhd_level_plan_bytes.argtypes = [_P, _B, _I3, ctypes.c_int, _I3]
+        L.ctmhd_level_plan_bytes.restype = ctypes.c_size_t
+        L.ctmhd_level_plan.argtypes = [_P, _B, _I3, ctypes.c_int, _I3, _vp, ctypes.c_size_t]
+        L.ctmhd_level_plan.restype = ctypes.c_int
+        L.ctmhd_step_level.argtypes = [_P, ctypes.c_int, _B, _I3, _I3, _vp, _PTR5, _PTR3,
+                                       ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.ctmhd_step_level.restype = ctypes.c_int
         L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
                                          _vp, ctypes.c_size_t, _vp]
         L.ctmhd_step_adjoint.restype = ctypes.c_int
@@ -88,6 +96,7 @@ def lib():
 
 EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
             "ctmhd_batch_plan_bytes", "ctmhd_batch_plan", "ctmhd_step_batched",
+            "ctmhd_level_plan_bytes", "ctmhd_level_plan", "ctmhd_step_level",
             "ctmhd_step_adjoint", "ctmhd_adjoint_workspace_bytes", "ctmhd_profile_events",
             "ctmhd_profile_recorded", "ctmhd_last_error")
 
@@ -176,6 +185,39 @@ def ctmhd_step_batched(params: Params, boxes, plan, cons, bface, nsteps, dt_mode
                                   _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
                                   int(nsteps), int(dt_mode), _p(dt_fixed), _p(dt_out), _p(diag),
                                   _p(ws), ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+def _i32(v, n):
+    arr = (ctypes.c_int32 * n)(*[int(x) for x in np.asarray(v).reshape(-1)])
+    return arr
+
+
+def level_plan(params: Params, boxes, origin, domain):
+    """Host plan bytes of a level (boxes tiling the periodic domain; origin:
+    (nbox, 3) level index of each box's first cell, axis 0 first)."""
+    arr = (Box * len(boxes))(*boxes)
+    org = _i32(origin, 3 * len(boxes))
+    dom = _i32(domain, 3)
+    n = int(lib().ctmhd_level_plan_bytes(ctypes.byref(params), arr, org, len(boxes), dom))
+    if n == 0:
+        raise CtmhdError("level plan size query failed (bad parameters, or the boxes do not "
+                         "tile the domain)")
+    buf = np.zeros(n, np.uint8)
+    _check(lib().ctmhd_level_plan(ctypes.byref(params), arr, org, len(boxes), dom,
+                                  buf.ctypes.data_as(ctypes.c_void_p), n))
+    return buf
+
+
+def ctmhd_step_level(params: Params, boxes, origin, domain, plan, cons, bface, nsteps,
+                     dt_fixed=None, dt_out=None, diag=None, workspace=None, stream=None):
+    arr = (Box * len(boxes))(*boxes)
+    ws = workspace
+    rc = lib().ctmhd_step_level(ctypes.byref(params), len(boxes), arr, _i32(origin, 3 * len(boxes)),
+                                _i32(domain, 3), _p(plan), _PTR5(*[_p(t) for t in cons]),
+                                _PTR3(*[_p(t) for t in bface]), int(nsteps), _p(dt_fixed),
+                                _p(dt_out), _p(diag), _p(ws), ws.numel() if ws is not None else 0,
+                                _stream(stream))
     return _check(rc)
 
 
@@ -442,6 +484,93 @@ def run_batched(params: Params, states, nsteps=1, dt_mode=DT_GLOBAL, dt_fixed=No
     return st.to_numpy(), dts.cpu().numpy().reshape(nsteps, ndt), diag.cpu().numpy().reshape(nsteps, 4)
 
 
+# ---------------------------------------------------------------------------
+# A level: boxes that tile one periodic domain, ghosts exchanged between them.
+# ---------------------------------------------------------------------------
+class LevelStepper:
+    """Workspace and device plan of a level over the packed boxes of `state`."""
+
+    def __init__(self, params: Params, state: BatchedState, origin, domain):
+        import torch
+        self.params = params
+        self.state = state
+        self.origin = np.asarray(origin, np.int32).reshape(len(state.boxes), 3)
+        self.domain = tuple(int(v) for v in domain)
+        dev = state.cons[0].device
+        self.plan = torch.from_numpy(level_plan(params, state.boxes, self.origin, self.domain)).to(dev)
+        nbytes = workspace_bytes(params, state.boxes)
+        if nbytes == 0:
+            raise CtmhdError("workspace size query failed")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        if self.workspace.data_ptr() % 256 or self.plan.data_ptr() % 16:
+            raise CtmhdError("workspace / plan allocation is not aligned")
+
+    def step(self, nsteps=1, dt_fixed=None, dt_out=None, diag=None, stream=None):
+        ctmhd_step_level(self.params, self.state.boxes, self.origin, self.domain, self.plan,
+                         self.state.cons, self.state.bface, nsteps, dt_fixed, dt_out, diag,
+                         self.workspace, stream)
+
+
+def split_level(cons, bface, dx, cuts, shift=(0, 0, 0)):
+    """Cut a periodic domain (numpy cons (5, n2, n1, n0), bface (3, ...)) into
+    boxes: cuts[d] are the increasing box boundaries along axis d (0 ... n_d),
+    and every box starts `shift` cells further along (wrapping), so that boxes
+    may straddle the periodic boundary.  Returns [(cons, bface, dx)], origin."""
+    n = (cons.shape[3], cons.shape[2], cons.shape[1])
+    states, origin = [], []
+    for k in range(len(cuts[2]) - 1):
+        for j in range(len(cuts[1]) - 1):
+            for i in range(len(cuts[0]) - 1):
+                lo = [cuts[0][i], cuts[1][j], cuts[2][k]]
+                hi = [cuts[0][i + 1], cuts[1][j + 1], cuts[2][k + 1]]
+                o = [(lo[d] + shift[d]) % n[d] for d in range(3)]
+                idx = [np.arange(o[d], o[d] + hi[d] - lo[d]) % n[d] for d in range(3)]
+                sel = np.ix_(idx[2], idx[1], idx[0])
+                c = np.stack([cons[m][sel] for m in range(5)])
+                b = np.stack([bface[a][sel] for a in range(3)])
+                states.append((c, b, tuple(dx)))
+                origin.append(o)
+    return states, np.asarray(origin, np.int32)
+
+
+def join_level(parts, origin, domain):
+    """Inverse of split_level: list of (cons, bface) boxes -> domain arrays."""
+    n0, n1, n2 = domain
+    cons = np.zeros((5, n2, n1, n0))
+    bface = np.zeros((3, n2, n1, n0))
+    for (c, b), o in zip(parts, origin):
+        m = (c.shape[3], c.shape[2], c.shape[1])
+        idx = [np.arange(o[d], o[d] + m[d]) % domain[d] for d in range(3)]
+        sel = np.ix_(idx[2], idx[1], idx[0])
+        for q in range(5):
+            cons[q][sel] = c[q]
+        for a in range(3):
+            bface[a][sel] = b[a]
+    return cons, bface
+
+
+def run_level(params: Params, cons, bface, dx, cuts, nsteps=1, dt_fixed=None, shift=(0, 0, 0),
+              ng=None, device="cuda"):
+    """Convenience: cut the domain into a level of boxes, advance it with
+    ctmhd_step_level and join the result.  Returns (cons, bface, dts, diag)."""
+    import torch
+    if ng is None:
+        ng = required_ghosts(params)
+    states, origin = split_level(cons, bface, dx, cuts, shift)
+    domain = (cons.shape[3], cons.shape[2], cons.shape[1])
+    st = BatchedState.from_numpy(states, ng, device)
+    S = LevelStepper(params, st, origin, domain)
+    dts = torch.zeros(nsteps, dtype=torch.float64, device=device)
+    diag = torch.zeros(4 * nsteps, dtype=torch.int64, device=device)
+    dtf = None
+    if dt_fixed is not None:
+        dtf = torch.as_tensor(np.asarray(dt_fixed, np.float64).reshape(-1).copy(), device=device)
+    S.step(nsteps, dtf, dts, diag)
+    torch.cuda.synchronize()
+    c, b = join_level(st.to_numpy(), origin, domain)
+    return c, b, dts.cpu().numpy(), diag.cpu().numpy().reshape(nsteps, 4)
+
+
 def parse_plan(plan):
     """Decode a host plan (for checks on the CPU): header fields, box order,
     per-phase item prefixes."""
@@ -449,7 +578,7 @@ def parse_plan(plan):
     buf = bytes(plan)
     nbox, nphase, strips, magic = struct.unpack_from("4i", buf, 0)
     (key,) = struct.unpack_from("Q", buf, 16)
-    kmax = 16
+    kmax = 24
     o = 24
     kind = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
     stage = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
@@ -457,10 +586,20 @@ def parse_plan(plan):
     rng = struct.unpack_from("6i", buf, o); o += 24
     range_items = struct.unpack_from("3i", buf, o); o += 12
     o = (o + 7) & ~7
-    order_off, prefix_off, desc_off = struct.unpack_from("3q", buf, o)
+    order_off, prefix_off, desc_off = struct.unpack_from("3q", buf, o); o += 24
+    xarg = list(struct.unpack_from(f"{kmax}i", buf, o)); o += 4 * kmax
+    level, nxblk = struct.unpack_from("2i", buf, o); o += 8
+    xbox_off, xblk_off = struct.unpack_from("2q", buf, o)
     order = np.frombuffer(buf, np.int32, nbox, order_off)
+    xbox = xblk = None
+    if level:
+        xbox = np.frombuffer(buf, np.int32, nbox + 1, xbox_off)
+        xblk = np.frombuffer(buf, np.dtype([("dst", "<i8"), ("src", "<i8"), ("dsy", "<i4"),
+                                            ("dsz", "<i4"), ("ssy", "<i4"), ("ssz", "<i4"),
+                                            ("ex", "<i4"), ("ey", "<i4"), ("vol_lo", "<i4"),
+                                            ("vol", "<i4")]), nxblk, xblk_off)
     prefix = np.frombuffer(buf, np.int32, nphase * (nbox + 1), prefix_off).reshape(nphase, nbox + 1)
     return dict(nbox=nbox, nphase=nphase, strips=strips, magic=magic, key=key, kind=kind[:nphase],
                 stage=stage[:nphase], item_off=item_off[:nphase],
                 range=[rng[0:2], rng[2:4], rng[4:6]], range_items=list(range_items),
-                order=order, prefix=prefix)
+                order=order, prefix=prefix, xarg=xarg[:nphase], level=level, xbox=xbox, xblk=xblk)

@@ -373,3 +373,25 @@ def smooth_modes_box(n, amp=0.05, beta=1.0, seed=5, nmodes=3, L=(1.0, 1.0, 1.0),
     bf = curl_edges(A, dx)
     bf[0] += bmag
     return from_primitives(rho, u, p, bf, gamma), bf, {"dx": dx, "b0": bmag}
+
+
+def field_loop(n=(96, 64, 32), radius=0.5, db=1e-3, gamma=GAMMA):
+    """Field-loop advection (Sec. 4.6): the domain [-1.5, 1.5] x [-1, 1] x
+    [-0.5, 0.5], rho = 1, p = 1, a uniform velocity (3, 2, 1)/sqrt(13) and a
+    weak loop of field db inside the cylinder r = sqrt(x0^2 + x1^2) < radius,
+    from the edge potential A_2 = db max(radius - r, 0) (b = db (-x1, x0)/r
+    inside), so that the discrete divergence is zero to round-off.
+    Returns (cons, bface, info)."""
+    L = (3.0, 2.0, 1.0)
+    dx = tuple(L[d] / n[d] for d in range(3))
+    A = np.zeros((3, n[2], n[1], n[0]))
+    x0, x1, _ = edge_coords(n, 2, L)
+    r = np.sqrt((x0 - 1.5) ** 2 + (x1 - 1.0) ** 2)
+    A[2] = db * np.maximum(radius - r, 0.0)
+    bf = curl_edges(A, dx)
+    shp = (n[2], n[1], n[0])
+    u = np.zeros((3,) + shp)
+    for d, v in enumerate((3.0, 2.0, 1.0)):
+        u[d] = v / math.sqrt(13.0)
+    cons = from_primitives(np.ones(shp), u, np.ones(shp), bf, gamma)
+    return cons, bf, {"dx": dx, "L": L, "gamma": gamma}
