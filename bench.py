@@ -227,6 +227,41 @@ def run_batched_form(K, W, log_tune=True):
     return out
 
 
+def run_level_form(cfg, emf, state, K, W, box=32):
+    """The headline box cut into a level of box^3 boxes (ctmhd_step_level:
+    ghosts exchanged between the boxes after every update), FP64, the same
+    scheme and steps as the single-box line."""
+    import torch
+
+    from paper_2609_10816_amd import ctmhd
+
+    cons, bf, info = state
+    n = cfg["n"]
+    cuts = (tuple(range(0, n + 1, box)),) * 3
+    P = ctmhd.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3)
+    states, origin = ctmhd.split_level(cons, bf, info["dx"], cuts)
+    st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
+    S = ctmhd.LevelStepper(P, st, origin, (n, n, n))
+    dev = st.cons[0].device
+    dts = torch.zeros(max(K, W, 1), dtype=torch.float64, device=dev)
+    diag = torch.zeros(4 * max(K, W, 1), dtype=torch.int64, device=dev)
+    if W:
+        S.step(W, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.step(K, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    v = n ** 3 * K / el / 1e6
+    log(f"level of {len(states)} boxes of {box}^3: {v:.1f} Mcell-updates/s "
+        f"({el / K * 1e3:.3f} ms/step)")
+    del S, st
+    torch.cuda.empty_cache()
+    return {"value": v, "unit": "Mcell-updates/s", "ms_per_step": el / K * 1e3,
+            "workload": f"{cfg['name']} as a level of {len(states)} boxes of {box}^3",
+            "precision": "fp64", "steps": K}
+
+
 def _adjoint_step_times(P, cons, bf, dx, calls=20):
     """Mean time of one forward step (ctmhd_step with a frozen dt) and of one
     adjoint step (ctmhd_step_adjoint) on the same box, over `calls` calls
@@ -390,6 +425,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--no-level", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -444,6 +480,9 @@ def main():
         r32, _ = run_gpu(cfg, "fp32", args.emf, K, W)
         v32 = n3 * K / r32["elapsed"] / 1e6
         out["fp32_form"] = {"value": v32, "unit": "Mcell-updates/s", "speedup": v32 / value}
+    if args.precision == "fp64" and not args.no_level:
+        out["level_form"] = run_level_form(cfg, args.emf, state, K, W)
+        out["level_form"]["vs_single_box"] = out["level_form"]["value"] / value
     if not args.no_batched:
         bf = run_batched_form(args.batched_steps, W)
         bf["speedup_fp32_vs_fp64_single_box_step"] = bf["fp32"]["value"] / value
