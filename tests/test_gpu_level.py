@@ -138,3 +138,74 @@ def test_level_refuses_a_plan_of_other_boxes():
     torch.cuda.synchronize()
     assert int(diag[3]) & 4                   # plan refused by the kernels
     assert all(torch.equal(a, b) for a, b in zip(before, st.cons))
+
+
+def test_single_box_level_is_the_periodic_box():
+    """A level of one box: the exchange is the periodic wrap."""
+    cons, bf, dx = _turb()
+    P = ctmhd.make_params(recon="ppm", emf="q26", eta=1e-3)
+    cuts = ((0, 24), (0, 16), (0, 12))
+    cl, bl, dtl, _ = ctmhd.run_level(P, cons, bf, dx, cuts, nsteps=3, shift=(7, 3, 11))
+    cs, bs, dts, _ = ctmhd.run(P, cons, bf, dx, nsteps=3)
+    assert np.allclose(dtl, np.asarray(dts).reshape(-1), rtol=1e-13, atol=0)
+    _same(list(cl) + list(bl), list(cs) + list(bs), "one-box level")
+
+
+def test_level_hipgraph_replay():
+    """A 2-step level call captured in a HIP graph (the call enqueues kernels
+    only) and replayed three times from the same state, with eager work in
+    between: every replay equals the eager result."""
+    import torch
+    cons, bf, dx = _turb()
+    P = ctmhd.make_params(recon="ppm", emf="q26", fofc=True)
+    states, origin = ctmhd.split_level(cons, bf, dx, CUTS, SHIFT)
+    st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
+    S = ctmhd.LevelStepper(P, st, origin, (24, 16, 12))
+    init = [t.clone() for t in st.cons + st.bface]
+    dts = torch.zeros(2, dtype=torch.float64, device="cuda")
+    diag = torch.zeros(8, dtype=torch.int64, device="cuda")
+
+    def reset():
+        for t, s in zip(st.cons + st.bface, init):
+            t.copy_(s)
+
+    reset()
+    S.step(2, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in st.cons + st.bface]
+    ref_dt = dts.clone()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        reset()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            S.step(2, dt_out=dts, diag=diag)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        reset()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(t, r) for t, r in zip(st.cons + st.bface, ref)), rep
+        assert torch.equal(dts, ref_dt), rep
+        del junk
+
+
+def test_level_of_many_uneven_boxes_vs_oracle():
+    """A 40 x 36 x 28 domain cut into 5 x 4 x 4 uneven boxes (2 to 15 cells
+    per axis), straddling the periodic boundary; FP64 PLM-MC + HLLD + B25a
+    with resistivity, 2 steps against the oracle on the whole domain."""
+    cons, bf, info = inputs.turbulent_box((40, 36, 28), mach=3.0, b0=(0.3, 0.0, 0.4),
+                                          db_rms=0.1, seed_v=7, seed_a=8)
+    dx = info["dx"]
+    cuts = ((0, 2, 12, 27, 33, 40), (0, 15, 17, 29, 36), (0, 9, 11, 20, 28))
+    P = ctmhd.make_params(recon="plm", emf="b25a", eta=2e-3)
+    Q = oracle.make_params(recon="plm", emf="b25a", eta=2e-3)
+    cl, bl, dtl, _ = ctmhd.run_level(P, cons, bf, dx, cuts, nsteps=2, shift=(21, 30, 5))
+    co, bo, dto, _ = oracle.step(Q, cons, bf, dx, nsteps=2)
+    assert np.allclose(dtl, dto, rtol=1e-13, atol=0)
+    compare_fields(cl, bl, co, bo, 1e-12, "80-box level vs oracle")
+    assert divb_rel(bl, dx) < 1e-13
