@@ -53,10 +53,10 @@ def _cmp_box(cg, bg, co, bo, tol, label):
     return worst
 
 
-@pytest.mark.parametrize("emf", ["q26", "b25a"])
-def test_batched_equals_single_box_path(emf):
+@pytest.mark.parametrize("emf,precision", [("q26", "fp64"), ("b25a", "fp64"), ("q26", "fp32")])
+def test_batched_equals_single_box_path(emf, precision):
     states = _small_boxes()
-    P, _ = _params(recon="ppm", emf=emf, eta=1e-3)
+    P, _ = _params(recon="ppm", emf=emf, eta=1e-3, precision=precision)
     outs, dts, dg = ctmhd.run_batched(P, states, nsteps=3)
     for b, (c, bf, dx) in enumerate(states):
         cg, bg, _, _ = ctmhd.run(P, c, bf, dx, 3, dt_fixed=dts[:, 0])
@@ -154,6 +154,31 @@ def test_batched_fp32_vs_oracle():
         assert divb_rel(outs[b][1], dx) < 1e-13
     print(f"[batched] fp32, 10 steps: worst normalised relative L1 of the smooth boxes {worst:.2e}",
           flush=True)
+
+
+def test_batched_fp32_100_steps_vs_oracle():
+    """The FP32 form in a batch over 100 steps (global CFL dt): AMR-like boxes
+    of 8 and 16 cells per axis (the batched workload's recipe) against the
+    FP64 oracle run on each box with the same dt sequence (normalisation of
+    the float64 parity bar).  These boxes hold one to two wavelengths of
+    supersonic, low-to-high beta flow, and the FP32 error grows to a few 1e-5
+    in 100 steps (the 128^3 and 48^3 turbulent boxes stay near 1e-6 and below
+    1e-6; the oracle's own response to a 1e-7 perturbation of the initial
+    state stays below 5e-7 on the first box): bound 1e-4, every value printed."""
+    states = inputs.amr_like_boxes(nbox=6, seed=11, sizes=(8, 16))
+    P, Q = _params(recon="ppm", emf="q26", precision="fp32")
+    outs, dts, dg = ctmhd.run_batched(P, states, nsteps=100)
+    worst = 0.0
+    for b, (c, bf, dx) in enumerate(states):
+        co, bo, _, _ = oracle.step(Q, c, bf, dx, nsteps=100, dt_fixed=dts[:, 0])
+        errs = field_errors(outs[b][0], outs[b][1], co, bo)
+        print(f"[batched] fp32 100 steps box {b} {c.shape[1:]}: " +
+              " ".join(f"{n}={v[0]:.1e}/{v[1]:.1e}" for n, v in zip(FIELDS, errs)), flush=True)
+        e = max(v[1] for v in errs)
+        worst = max(worst, e)
+        assert e <= 1e-4, (b, e)
+        assert divb_rel(outs[b][1], dx) < 1e-13
+    print(f"[batched] fp32, 100 steps: worst normalised relative L1 {worst:.2e}", flush=True)
 
 
 def test_batched_tile_knob_same_result():
