@@ -162,3 +162,39 @@ def test_bad_levels_are_refused(what):
         domain = [4, 12, 9]
     with pytest.raises(ctmhd.CtmhdError):
         ctmhd.level_plan(P, boxes, origin, domain)
+
+
+def _step_level_rc(P, boxes, origin, domain, plan=b"\0" * 16):
+    """ctmhd_step_level with placeholder device pointers that are never
+    dereferenced: every case below fails validation on the host first."""
+    import ctypes
+    L = ctmhd.lib()
+    arr = (ctmhd.Box * len(boxes))(*boxes)
+    d = 256
+    c5 = ctmhd._PTR5(*([d] * 5))
+    c3 = ctmhd._PTR3(*([d] * 3))
+    return L.ctmhd_step_level(ctypes.byref(P), len(boxes), arr, ctmhd._i32(origin, 3 * len(boxes)),
+                              ctmhd._i32(domain, 3), plan, c5, c3, 1, None, None, None, None, 0,
+                              None)
+
+
+@pytest.mark.parametrize("what", ["gap", "overlap", "null_plan", "persistent", "force_flags"])
+def test_step_level_validates_on_the_host(what):
+    cuts, shift, _ = CASES["aligned_ppm"]
+    P = ctmhd.make_params(recon="plm")
+    boxes, origin, _ = _level(DOMAIN, cuts, shift, 3)
+    domain, plan = list(DOMAIN), b"\0" * 16
+    if what == "gap":
+        domain[2] += 2
+    elif what == "overlap":
+        origin = origin.copy()
+        origin[3] = origin[4]
+    elif what == "null_plan":
+        plan = None
+    elif what == "persistent":
+        P.tile = ctmhd.make_tile(persistent=True)
+    else:
+        P.force_flags = 256
+    rc = _step_level_rc(P, boxes, origin, domain, plan)
+    assert rc == (-2 if what == "persistent" else -1), (what, rc)
+    assert ctmhd.lib().ctmhd_last_error() != b""
