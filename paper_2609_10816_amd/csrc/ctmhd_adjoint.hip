@@ -13,14 +13,17 @@
 // atomics):
 //   edges  the EMF adjoint from v (transposed curl), then LD04 and the Q26
 //          corners in reverse: adjoints of the edge-reconstructed u*, face
-//          fields and edge speeds, stored per edge
+//          fields and edge speeds, stored per edge (B25a: the adjoints of the
+//          corner values of both two-step reconstructions of the cell EMF)
 //   faces  the flux adjoint from v (transposed divergence); the adjoints of
 //          u*, alpha+-, and of the face field gathered from the edges that
 //          read them (through the reverse of their reconstructions); the
 //          Riemann solver in reverse: adjoints of the two face-local states
 //          and of the normal field; Joule flux and eta j in reverse
 //   cells  face-local state adjoints gathered through the reverse of the
-//          cell reconstructions, then primitive -> conserved (Sec. 2.2,
+//          cell reconstructions (B25a: also the cell-EMF adjoint, gathered
+//          through the reverse of both two-step reconstructions, onto u and
+//          the cell field), then primitive -> conserved (Sec. 2.2,
 //          eq. state:primitive)
 //   fields cell-centred field adjoints onto the two faces of each cell
 //   fold   every ghost copy's adjoint added to its interior cell or face
@@ -45,6 +48,11 @@ struct AdjArrays {
   double* bj[3];       // face-field adjoint of the Ohmic terms (atomic accumulation)
   double* ca[5];       // conserved-field adjoint per cell
   double* cb[3];       // cell-centred field adjoint per cell
+  // B25a only: per edge direction, the adjoints of the corner values of the
+  // two-step reconstructions of the cell EMF, (LB, RB, LT, RT) in the order
+  // [x_a x_b] then [x_b x_a]; and five scratch arrays of its gathers
+  double* ec[3][8];
+  double* tmp[5];
 };
 
 __device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
@@ -89,9 +97,9 @@ __device__ __forceinline__ void etaj_adj(double* const bj[3], const Geom& G, int
 }
 
 // ---------------------------------------------------------------------------
-// Edges: EMF adjoint and the reverse of LD04 + Q26 (edge_emf).
+// Edges: EMF adjoint and the reverse of LD04 + Q26 or B25a corners (edge_emf).
 // ---------------------------------------------------------------------------
-template <int RECON>
+template <int RECON, int EMF>
 __global__ void __launch_bounds__(kBlock)
     k_adj_edge(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
   if (*stop) return;
@@ -108,6 +116,10 @@ __global__ void __launch_bounds__(kBlock)
     if (!inside || s3[c] >= G.g + G.n[c]) {
 #pragma unroll
       for (int q = 0; q < 13; ++q) X.ea[c][q][t] = 0.0;
+      if constexpr (EMF == kB25A) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) X.ec[c][q][t] = 0.0;
+      }
       continue;
     }
     const int a = (c + 1) % 3, b = (c + 2) % 3;
@@ -115,18 +127,39 @@ __global__ void __launch_bounds__(kBlock)
     // the EMF enters the new face fields b_a at t, t - sb and b_b at t, t - sa
     const double Eb = dt * ((X.v[5 + a][t] - X.v[5 + a][t - sb]) * G.idx[b] -
                             (X.v[5 + b][t] - X.v[5 + b][t - sa]) * G.idx[a]);
-    double u[4], bv[4], al[4];
+    double bv[4], al[4];
     iface_along_d<RECON>(S.b[a], t, sb, bv[0], bv[1]);  // baB, baT
     iface_along_d<RECON>(S.b[b], t, sa, bv[2], bv[3]);  // bbL, bbR
-    iface_along<RECON>(W.us[a], t, sb, u[0], u[1]);     // uaB, uaT
-    iface_along<RECON>(W.us[b], t, sa, u[2], u[3]);     // ubL, ubR
     al[0] = tmax(W.ap[a][t - sb], W.ap[a][t]);
     al[1] = tmax(W.am[a][t - sb], W.am[a][t]);
     al[2] = tmax(W.ap[b][t - sa], W.ap[b][t]);
     al[3] = tmax(W.am[b][t - sa], W.am[b][t]);
     double ub[4] = {0.0, 0.0, 0.0, 0.0}, bb[4] = {0.0, 0.0, 0.0, 0.0};
     double alb[4] = {0.0, 0.0, 0.0, 0.0};
-    q26_ld04_adj(u, bv, al, Eb, ub, bb, alb);
+    if constexpr (EMF == kB25A) {
+      // corners: the mean of the two two-step reconstructions of the cell EMF
+      // (edge_emf); e[q] = (ab[q] + ba[perm q]) / 2
+      double ab[4], ba[4];
+      two_step<RECON>(W.ecell[c], t, sa, sb, ab);
+      two_step<RECON>(W.ecell[c], t, sb, sa, ba);
+      const double e[4] = {0.5 * (ab[0] + ba[0]), 0.5 * (ab[1] + ba[2]), 0.5 * (ab[2] + ba[1]),
+                           0.5 * (ab[3] + ba[3])};
+      double eb[4] = {0.0, 0.0, 0.0, 0.0};
+      ld04_adj(e, bv, al, Eb, eb, bb, alb);
+      X.ec[c][0][t] = 0.5 * eb[0];
+      X.ec[c][1][t] = 0.5 * eb[1];
+      X.ec[c][2][t] = 0.5 * eb[2];
+      X.ec[c][3][t] = 0.5 * eb[3];
+      X.ec[c][4][t] = 0.5 * eb[0];
+      X.ec[c][5][t] = 0.5 * eb[2];
+      X.ec[c][6][t] = 0.5 * eb[1];
+      X.ec[c][7][t] = 0.5 * eb[3];
+    } else {
+      double u[4];
+      iface_along<RECON>(W.us[a], t, sb, u[0], u[1]);  // uaB, uaT
+      iface_along<RECON>(W.us[b], t, sa, u[2], u[3]);  // ubL, ubR
+      q26_ld04_adj(u, bv, al, Eb, ub, bb, alb);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       X.ea[c][q][t] = ub[q];
@@ -481,6 +514,81 @@ int cell_lines(hipStream_t st, const Geom& G, const AdjArrays& X, double* const 
   return CTMHD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// B25a cell EMF (eq. emf:b25a-emf-centre), reconstructed to the edge corners
+// in two steps in both orders (first along d1 to the x_d1 faces, then along
+// d2 to the edge).  In reverse, per edge direction and order: the first-step
+// face values (recomputed here), their adjoints gathered along d2 from the
+// stored corner adjoints, then the cell-EMF adjoint gathered along d1; all
+// through the line gathers above.  Finally the cell-EMF adjoint onto u and
+// the cell-centred field.
+// ---------------------------------------------------------------------------
+// First step along d1 at every position: the values on both sides of the
+// x_d1 interface at t (upper value of the cell t - st_d1, lower value of t),
+// 0 where the stencil leaves the box.
+template <int RECON>
+__global__ void __launch_bounds__(kBlock)
+    k_adj_iface(Geom G, const double* A, int d1, double* lo, double* hi, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  constexpr int r = recon_halfwidth(RECON);
+  double l = 0.0, h = 0.0;
+  if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1]) iface_along<RECON>(A, t, G.st[d1], l, h);
+  lo[t] = l;
+  hi[t] = h;
+}
+
+// e_c = -u_a bc_b + u_b bc_a in reverse: adds to the primitive adjoints.
+__global__ void __launch_bounds__(kBlock)
+    k_adj_ecell(Geom G, AdjArrays X, PrimPtrs PB, const double* EB, int c, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  const double g = EB[t];
+  if (g == 0.0) return;
+  const int a = (c + 1) % 3, b = (c + 2) % 3;
+  PB.p[1 + a][t] += -g * X.prim[5 + b][t];
+  PB.p[5 + b][t] += -g * X.prim[1 + a][t];
+  PB.p[1 + b][t] += g * X.prim[5 + a][t];
+  PB.p[5 + a][t] += g * X.prim[1 + b][t];
+}
+
+template <int RECON>
+int b25a_cell_emf_adj(hipStream_t st, const Geom& G, const Work<double>& W, const AdjArrays& X,
+                      const PrimPtrs& PB, const int* stop) {
+  const int nb = nblocks(G.elems);
+  double* const T0 = X.tmp[0];
+  double* const T1 = X.tmp[1];
+  double* const T2 = X.tmp[2];
+  double* const T3 = X.tmp[3];
+  double* const EB = X.tmp[4];
+  for (int c = 0; c < 3; ++c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    for (int order = 0; order < 2; ++order) {
+      const int d1 = order == 0 ? a : b, d2 = order == 0 ? b : a;
+      double* const* E = X.ec[c] + 4 * order;  // LB, RB, LT, RT of this order
+      LAUNCH(k_adj_iface<RECON>, nb, G, W.ecell[c], d1, T0, T1, stop);
+      // second step: the lower-d1 face values give the LB / LT corners, the
+      // upper ones RB / RT
+      LineJobs J{};
+      J.chunk = 16;
+      J.j[0] = LineJob{T0, E[0], E[2], T2, 0};
+      J.j[1] = LineJob{T1, E[1], E[3], T3, 0};
+      if (const int rc = launch_lines<RECON>(st, G, d2, J, 2, stop)) return rc;
+      // first step
+      LineJobs K{};
+      K.chunk = 16;
+      K.j[0] = LineJob{W.ecell[c], T2, T3, EB, order};
+      if (const int rc = launch_lines<RECON>(st, G, d1, K, 1, stop)) return rc;
+    }
+    LAUNCH(k_adj_ecell, nb, G, X, PB, EB, c, stop);
+  }
+  return CTMHD_OK;
+}
+
 __global__ void __launch_bounds__(kBlock)
     k_adj_cfinish(Geom G, AdjArrays X, PrimPtrs PB, double gamma, const int* stop) {
   if (*stop) return;
@@ -615,29 +723,33 @@ __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
 // ---------------------------------------------------------------------------
 // V, G1, prim, ea, fa, bn, bj, ca, cb, saved face arrays of S0
 constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3 + 9;
+// B25a: corner adjoints and gather scratch
+constexpr int kAdjArraysB25a = 24 + 5;
 
 size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
   size_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
-  return box_ws_bytes(b, 8, p->emf_compute) + (size_t)kAdjArrays * align256(e * 8);
+  const int n = kAdjArrays + (p->emf_compute == CTMHD_EMF_B25A ? kAdjArraysB25a : 0);
+  return box_ws_bytes(b, 8, p->emf_compute) + (size_t)n * align256(e * 8);
 }
 
 int check_adjoint(const ctmhd_params* p) {
   if (p->precision != CTMHD_FP64)
     return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the FP64 form only");
-  if (p->emf_compute != CTMHD_EMF_Q26)
-    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the Q26 EMF only");
+  if (p->emf_compute != CTMHD_EMF_Q26 && p->emf_compute != CTMHD_EMF_B25A)
+    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the Q26 and B25a EMFs only");
   return CTMHD_OK;
 }
 
 // D'(S)^T v into X.ca / X.bn (ghosted), given the forward face arrays of S in W.
-template <int RECON, int RIEMANN>
+template <int RECON, int RIEMANN, int EMF>
 int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<double>& W,
           const AdjArrays& X) {
   const int nb = nblocks(G.elems);
   LAUNCH(k_adj_zero3, nb, G, X);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
-  LAUNCH(k_adj_edge<RECON>, nb, S, G, W, X, p->eta, W.stop);
+  if constexpr (EMF == kB25A) LAUNCH((k_prim<double, kB25A>), nb, S, G, W, p->gamma, W.stop);
+  LAUNCH((k_adj_edge<RECON, EMF>), nb, S, G, W, X, p->eta, W.stop);
   if (const int rc = face_lines<RECON>(st, G, S, W, X, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
   hipLaunchKernelGGL(k_adj_fgather, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
@@ -649,12 +761,14 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   PrimPtrs PB;
   for (int v = 0; v < 8; ++v) PB.p[v] = X.ea[0][v];
   if (const int rc = cell_lines<RECON>(st, G, X, PB.p, W.stop)) return rc;
+  if constexpr (EMF == kB25A)
+    if (const int rc = b25a_cell_emf_adj<RECON>(st, G, W, X, PB, W.stop)) return rc;
   LAUNCH(k_adj_cfinish, nb, G, X, PB, p->gamma, W.stop);
   LAUNCH(k_adj_bsum, nb, G, X, W.stop);
   return CTMHD_OK;
 }
 
-template <int RECON, int RIEMANN>
+template <int RECON, int RIEMANN, int EMF>
 int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* const cons_n[5],
                 const double* const bface_n[3], const double* dt, const double* const g_cons[5],
                 const double* const g_bface[3], double* const g_cons_out[5],
@@ -685,6 +799,9 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   for (int a = 0; a < 3; ++a) X.bj[a] = cv.take<double>(e);
   for (int m = 0; m < 5; ++m) X.ca[m] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 8; ++q) X.ec[c][q] = EMF == kB25A ? cv.take<double>(e) : nullptr;
+  for (int q = 0; q < 5; ++q) X.tmp[q] = EMF == kB25A ? cv.take<double>(e) : nullptr;
   Work<double> W0 = W;  // W with the face arrays of S0 (saved after its face pass)
   for (int a = 0; a < 3; ++a) {
     W0.ap[a] = cv.take<double>(e);
@@ -722,6 +839,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
          (long long*)nullptr);
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   LAUNCH(k_adj_save9, nb, G, W, W0);
+  if constexpr (EMF == kB25A) LAUNCH((k_prim<double, kB25A>), nb, A, G, W, p->gamma, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
@@ -729,12 +847,12 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   LAUNCH(k_adj_load, nb, G, V, Gin, 0.5, W.stop);
   for (int m = 0; m < 5; ++m) X.v[m] = V.c[m];
   for (int a = 0; a < 3; ++a) X.v[5 + a] = V.b[a];
-  if ((rc = vjp_d<RECON, RIEMANN>(st, p, H, G, W, X))) return rc;
+  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, H, G, W, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, G1, Gin, 0.5, Gin, 0.0, X, W.stop);
   // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
   for (int m = 0; m < 5; ++m) X.v[m] = G1.c[m];
   for (int a = 0; a < 3; ++a) X.v[5 + a] = G1.b[a];
-  if ((rc = vjp_d<RECON, RIEMANN>(st, p, A, G, W0, X))) return rc;
+  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, A, G, W0, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, G1, 1.0, X, W.stop);
   return CTMHD_OK;
 }
@@ -745,11 +863,12 @@ int adjoint_riemann(const ctmhd_params* p, const ctmhd_box* box, const double* c
                     const double* const g_cons[5], const double* const g_bface[3],
                     double* const g_cons_out[5], double* const g_bface_out[3], void* ws,
                     size_t ws_bytes, hipStream_t st) {
-  if (p->riemann == CTMHD_RIEMANN_HLLD)
-    return adjoint_box<RECON, kHLLD>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                     g_bface_out, ws, ws_bytes, st);
-  return adjoint_box<RECON, kLLF>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                  g_bface_out, ws, ws_bytes, st);
+#define CTMHD_ADJ(RI, EM) \
+  adjoint_box<RECON, RI, EM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out, g_bface_out, ws, ws_bytes, st)
+  if (p->emf_compute == CTMHD_EMF_B25A)
+    return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kB25A) : CTMHD_ADJ(kLLF, kB25A);
+  return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kQ26) : CTMHD_ADJ(kLLF, kQ26);
+#undef CTMHD_ADJ
 }
 
 }  // namespace

@@ -786,4 +786,35 @@ CTMHD_HD void q26_ld04_adj(const T u[4], const T b[4], const T al[4], T Eb, T ub
   bb[1] += e2b * ubL + e3b * ubR;
 }
 
+// ---------------------------------------------------------------------------
+// LD04 averaging alone (eq. emf:ld04), for corner EMFs that do not depend on
+// the edge-reconstructed fields (B25a).  In: the four corner EMFs (LB, RB,
+// LT, RT), the edge fields (baB, baT, bbL, bbR), the edge speeds (apa, ama,
+// apb, amb) and the adjoint Eb of the averaged EMF.  Out (+=): adjoints in
+// the same order.
+// ---------------------------------------------------------------------------
+template <typename T>
+CTMHD_HD void ld04_adj(const T e[4], const T b[4], const T al[4], T Eb, T eb[4], T bb[4],
+                       T alb[4]) {
+  const T baB = b[0], baT = b[1], bbL = b[2], bbR = b[3];
+  const T apa = al[0], ama = al[1], apb = al[2], amb = al[3];
+  const T sa = apa + ama, sb = apb + amb;
+  const T iab = T(1) / (sa * sb);
+  const T P = apa * apb * e[0] + ama * apb * e[1] + apa * amb * e[2] + ama * amb * e[3];
+  const T dba = baT - baB, dbb = bbR - bbL;
+  eb[0] += Eb * apa * apb * iab;
+  eb[1] += Eb * ama * apb * iab;
+  eb[2] += Eb * apa * amb * iab;
+  eb[3] += Eb * ama * amb * iab;
+  alb[0] += Eb * ((apb * e[0] + amb * e[2]) * iab - P * iab / sa + ama * ama / (sa * sa) * dbb);
+  alb[1] += Eb * ((apb * e[1] + amb * e[3]) * iab - P * iab / sa + apa * apa / (sa * sa) * dbb);
+  alb[2] += Eb * ((apa * e[0] + ama * e[1]) * iab - P * iab / sb - amb * amb / (sb * sb) * dba);
+  alb[3] += Eb * ((apa * e[2] + ama * e[3]) * iab - P * iab / sb - apb * apb / (sb * sb) * dba);
+  const T cb = apb * amb / sb, ca = apa * ama / sa;
+  bb[0] += Eb * cb;
+  bb[1] += -Eb * cb;
+  bb[2] += -Eb * ca;
+  bb[3] += Eb * ca;
+}
+
 }  // namespace ctmhd

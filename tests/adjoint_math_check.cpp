@@ -245,6 +245,43 @@ static void check_ld04() {
   report("q26_ld04_adj", worst, 1e-7);
 }
 
+// ---- LD04 alone (corner EMFs as inputs, as for B25a) ----
+static void check_ld04_alone() {
+  double worst = 0;
+  for (int it = 0; it < 2000; ++it) {
+    double e[4], b[4], al[4], de[4], db[4], dal[4];
+    for (int k = 0; k < 4; ++k) {
+      e[k] = U(-2, 2);
+      b[k] = U(-2, 2);
+      al[k] = U(0.2, 3);
+      de[k] = U(-1, 1);
+      db[k] = U(-1, 1);
+      dal[k] = U(-1, 1);
+    }
+    const double Eb = U(-1, 1);
+    auto E = [&](double h) {
+      double ee[4], bb[4], aa[4];
+      for (int k = 0; k < 4; ++k) {
+        ee[k] = e[k] + h * de[k];
+        bb[k] = b[k] + h * db[k];
+        aa[k] = al[k] + h * dal[k];
+      }
+      return Eb * ld04(ee[0], ee[1], ee[2], ee[3], aa[0], aa[1], aa[2], aa[3], bb[0], bb[1], bb[2],
+                       bb[3]);
+    };
+    double eb[4] = {0, 0, 0, 0}, bb[4] = {0, 0, 0, 0}, alb[4] = {0, 0, 0, 0};
+    ld04_adj(e, b, al, Eb, eb, bb, alb);
+    double ad = 0, sc = 0;
+    for (int k = 0; k < 4; ++k) {
+      ad += eb[k] * de[k] + bb[k] * db[k] + alb[k] * dal[k];
+      sc += std::fabs(eb[k] * de[k]) + std::fabs(bb[k] * db[k]) + std::fabs(alb[k] * dal[k]);
+    }
+    const double h = 1e-6;
+    worst = std::fmax(worst, relmis(ad, (E(h) - E(-h)) / (2 * h), sc));
+  }
+  report("ld04_adj", worst, 1e-7);
+}
+
 // ---- reconstruction ----
 // A line of 13 values; the centres 2 .. 10 (whose five-point windows lie in
 // the line) carry random adjoints of their lower and upper values; the
@@ -313,6 +350,7 @@ int main() {
   check_fast();
   check_phys();
   check_ld04();
+  check_ld04_alone();
   check_recon<kPC>("recon PC", nullptr);
   check_recon<kPLM_MC>("recon PLM-MC", nullptr);
   check_recon<kPLM_MM>("recon PLM-minmod", nullptr);

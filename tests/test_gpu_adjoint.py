@@ -18,15 +18,19 @@ from paper_2609_10816_amd import ctmhd, inputs
 pytestmark = pytest.mark.gpu
 
 CONFIGS = [
-    ("pc", "llf", 0.0),
-    ("plm", "llf", 0.0),
-    ("plm", "hlld", 0.0),
-    ("plm", "hlld", 1e-3),
-    ("plm_minmod", "hlld", 1e-3),
-    ("pc", "hlld", 1e-3),
-    ("ppm", "llf", 0.0),
-    ("ppm", "hlld", 0.0),
-    ("ppm", "hlld", 1e-3),
+    ("pc", "llf", 0.0, "q26"),
+    ("plm", "llf", 0.0, "q26"),
+    ("plm", "hlld", 0.0, "q26"),
+    ("plm", "hlld", 1e-3, "q26"),
+    ("plm_minmod", "hlld", 1e-3, "q26"),
+    ("pc", "hlld", 1e-3, "q26"),
+    ("ppm", "llf", 0.0, "q26"),
+    ("ppm", "hlld", 0.0, "q26"),
+    ("ppm", "hlld", 1e-3, "q26"),
+    ("pc", "llf", 0.0, "b25a"),
+    ("plm", "hlld", 0.0, "b25a"),
+    ("plm_minmod", "llf", 1e-3, "b25a"),
+    ("ppm", "hlld", 1e-3, "b25a"),
 ]
 
 
@@ -58,11 +62,11 @@ def _dot(a, b):
     return float(np.sum(a * b)), float(np.sum(np.abs(a * b)))
 
 
-@pytest.mark.parametrize("recon,riemann,eta", CONFIGS)
-def test_adjoint_dot_product_vs_oracle_dual(recon, riemann, eta):
+@pytest.mark.parametrize("recon,riemann,eta,emf", CONFIGS)
+def test_adjoint_dot_product_vs_oracle_dual(recon, riemann, eta, emf):
     cons, bf, dx = _state()
-    Q = oracle.make_params(recon=recon, riemann=riemann, eta=eta, fofc=False)
-    P = ctmhd.make_params(recon=recon, riemann=riemann, eta=eta, fofc=False)
+    Q = oracle.make_params(recon=recon, riemann=riemann, eta=eta, emf=emf, fofc=False)
+    P = ctmhd.make_params(recon=recon, riemann=riemann, eta=eta, emf=emf, fofc=False)
     dt = 0.5 * oracle.cfl_dt(Q, cons, bf, dx)
     rng = np.random.default_rng(7)
     worst = 0.0
@@ -81,16 +85,17 @@ def test_adjoint_dot_product_vs_oracle_dual(recon, riemann, eta):
         scale = max(s1 + s2, t1 + t2)
         err = abs(lhs - rhs) / scale
         worst = max(worst, err)
-        print(f"[adjoint] {recon} {riemann} eta={eta} rep {rep}: <g, J t> = {lhs:.12e}, "
+        print(f"[adjoint] {recon} {riemann} {emf} eta={eta} rep {rep}: <g, J t> = {lhs:.12e}, "
               f"<J^T g, t> = {rhs:.12e}, relative {err:.2e}", flush=True)
     assert worst <= 1e-12, worst
 
 
-@pytest.mark.parametrize("recon", ["plm", "ppm"])
-def test_adjoint_gradient_vs_central_differences_16(recon):
+@pytest.mark.parametrize("recon,emf", [("plm", "q26"), ("ppm", "q26"), ("plm", "b25a"),
+                                      ("ppm", "b25a")])
+def test_adjoint_gradient_vs_central_differences_16(recon, emf):
     """Loss L(S) = <w, step(S)> on the 16^3 smooth box (amplitude 0.05,
-    beta = 1; FP64, PLM-MC or PPM + HLLD + Q26 + LD04, eta = 1e-3, no flux
-    correction, frozen dt).  Sampled entries of dL/dS from the adjoint against
+    beta = 1; FP64, PLM-MC or PPM + HLLD + Q26 or B25a + LD04, eta = 1e-3, no
+    flux correction, frozen dt).  Sampled entries of dL/dS from the adjoint against
     fourth-order central differences of the GPU forward step, one entry at a
     time (a dense random direction would cross limiter kinks somewhere in the
     box; one entry moves only the limiters around one cell).
@@ -103,8 +108,8 @@ def test_adjoint_gradient_vs_central_differences_16(recon):
     n = 16
     cons, bf, info = inputs.smooth_modes_box(n, amp=0.05, beta=1.0, seed=5)
     dx = info["dx"]
-    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=1e-3, fofc=False)
-    Q = oracle.make_params(recon=recon, riemann="hlld", eta=1e-3, fofc=False)
+    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=1e-3, emf=emf, fofc=False)
+    Q = oracle.make_params(recon=recon, riemann="hlld", eta=1e-3, emf=emf, fofc=False)
     dt = oracle.cfl_dt(Q, cons, bf, dx)
     rng = np.random.default_rng(11)
     wc = rng.standard_normal(cons.shape)
@@ -137,20 +142,20 @@ def test_adjoint_gradient_vs_central_differences_16(recon):
         fd, fd_fine = fd4(dc, db, h), fd4(dc, db, 0.25 * h)
         scale = abs(fd) + 1e-3 * gscale
         if abs(fd - fd_fine) > 5e-7 * scale:
-            print(f"[adjoint] 16^3 {recon} entry field {m} cell {(k, j, i)}: differences with "
+            print(f"[adjoint] 16^3 {recon} {emf} entry field {m} cell {(k, j, i)}: differences with "
                   f"h and h/4 disagree ({fd:.12e}, {fd_fine:.12e}): branch switch, left out",
                   flush=True)
             continue
         smooth += 1
         err = abs(fd - an) / scale
         worst = max(worst, err)
-        print(f"[adjoint] 16^3 {recon} entry field {m} cell {(k, j, i)}: adjoint {an:.12e}, "
+        print(f"[adjoint] 16^3 {recon} {emf} entry field {m} cell {(k, j, i)}: adjoint {an:.12e}, "
               f"central difference {fd:.12e}, relative {err:.2e}", flush=True)
     assert smooth >= 16, smooth
     assert worst <= 1e-6, worst
 
 
-@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(emf="b25a"), dict(emf="fs18")])
+@pytest.mark.parametrize("kw", [dict(precision="fp32"), dict(emf="fs18")])
 def test_adjoint_refuses_unsupported(kw):
     import torch
     P = ctmhd.make_params(**kw)
@@ -176,8 +181,9 @@ def _rollout_inputs(n=16, seed=5):
     return rho, u, p, b, info["dx"]
 
 
-@pytest.mark.parametrize("recon,eta", [("plm", 0.0), ("plm", 1e-3), ("ppm", 0.0)])
-def test_rollout_checkpoint_interval_does_not_change_the_gradient(recon, eta):
+@pytest.mark.parametrize("recon,eta,emf", [("plm", 0.0, "q26"), ("plm", 1e-3, "q26"),
+                                          ("ppm", 0.0, "q26"), ("ppm", 0.0, "b25a")])
+def test_rollout_checkpoint_interval_does_not_change_the_gradient(recon, eta, emf):
     """Gradient of the kinetic energy after 6 steps wrt the initial velocity and
     face field: checkpoints every 1, 2, 4 and 6 steps give bitwise the same
     gradient without resistivity, and the same to round-off with it (the
@@ -185,7 +191,7 @@ def test_rollout_checkpoint_interval_does_not_change_the_gradient(recon, eta):
     import torch
     from paper_2609_10816_amd import autograd as ad
     rho, u0, p, b0, dx = _rollout_inputs()
-    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=eta, fofc=False)
+    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=eta, emf=emf, fofc=False)
     grads = []
     for every in (1, 2, 4, 6):
         u = u0.clone().requires_grad_(True)
