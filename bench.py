@@ -302,7 +302,8 @@ def _adjoint_step_times(P, cons, bf, dx, calls=20):
 def run_adjoint_form(nsteps=20, every=5, reps=3):
     """The derivative workload: 64^3 smooth periodic box (3 sine modes of
     amplitude 0.05 per field, beta = 1), PLM-MC or PPM + HLLD + Q26 + LD04,
-    FP64 (and PLM-MC in the FP32 form), no flux correction; loss = total kinetic energy after `nsteps`
+    FP64 (also PLM-MC with the B25a EMF, and PLM-MC in the FP32 form), no
+    flux correction; loss = total kinetic energy after `nsteps`
     steps; the gradient with respect to the initial velocity and face field
     through the hand-written adjoint with a checkpoint every `every` steps.
     Times the forward rollout alone and the backward pass (recomputation +
@@ -329,8 +330,9 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
            "loss": "total kinetic energy after the steps",
            "gradient": "d loss / d (initial velocity, initial face field)",
            "timing": f"fastest of {reps} repetitions"}
-    for recon, prec in (("plm", "fp64"), ("ppm", "fp64"), ("plm", "fp32")):
-        P = ctmhd.make_params(recon=recon, riemann="hlld", emf="q26", eta=0.0, fofc=False,
+    for recon, prec, emf in (("plm", "fp64", "q26"), ("ppm", "fp64", "q26"),
+                             ("plm", "fp64", "b25a"), ("plm", "fp32", "q26")):
+        P = ctmhd.make_params(recon=recon, riemann="hlld", emf=emf, eta=0.0, fofc=False,
                               precision=prec)
         tf_best = tb_best = None
         for _ in range(reps):
@@ -354,6 +356,8 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
             tf_best = tf if tf_best is None else min(tf_best, tf)
             tb_best = tb if tb_best is None else min(tb_best, tb)
         key = recon if prec == "fp64" else f"{recon}_fp32_form"
+        if emf != "q26":
+            key += f"_{emf}"
         out[key] = {"forward_ms": tf_best * 1e3, "backward_ms": tb_best * 1e3,
                     "ratio_backward_to_forward": tb_best / tf_best,
                     "grad_norm_u": float(u.grad.norm()), "grad_norm_b": float(b.grad.norm())}
