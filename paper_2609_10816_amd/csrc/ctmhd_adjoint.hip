@@ -50,9 +50,12 @@ struct AdjArrays {
   double* cb[3];       // cell-centred field adjoint per cell
   // B25a only: per edge direction, the adjoints of the corner values of the
   // two-step reconstructions of the cell EMF, (LB, RB, LT, RT) in the order
-  // [x_a x_b] then [x_b x_a]; and five scratch arrays of its gathers
+  // [x_a x_b] then [x_b x_a]; per edge direction and order the first-step
+  // face values (lower, upper side) and their adjoints; the cell-EMF adjoint
   double* ec[3][8];
-  double* tmp[5];
+  double* fv[3][2][2];
+  double* fb[3][2][2];
+  double* eb[3];
 };
 
 __device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
@@ -523,69 +526,89 @@ int cell_lines(hipStream_t st, const Geom& G, const AdjArrays& X, double* const 
 // through the line gathers above.  Finally the cell-EMF adjoint onto u and
 // the cell-centred field.
 // ---------------------------------------------------------------------------
-// First step along d1 at every position: the values on both sides of the
-// x_d1 interface at t (upper value of the cell t - st_d1, lower value of t),
-// 0 where the stencil leaves the box.
+// First step along d1 at every position, for every edge direction c and
+// order (d1 = a then b): the values on both sides of the x_d1 interface at t
+// (upper value of the cell t - st_d1, lower value of t), 0 where the stencil
+// leaves the box.
 template <int RECON>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_iface(Geom G, const double* A, int d1, double* lo, double* hi, const int* stop) {
+    k_adj_iface(Geom G, Work<double> W, AdjArrays X, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
   int s3[3];
   decode(G, t, s3);
   constexpr int r = recon_halfwidth(RECON);
-  double l = 0.0, h = 0.0;
-  if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1]) iface_along<RECON>(A, t, G.st[d1], l, h);
-  lo[t] = l;
-  hi[t] = h;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+      double l = 0.0, h = 0.0;
+      if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
+        iface_along<RECON>(W.ecell[c], t, G.st[d1], l, h);
+      X.fv[c][o][0][t] = l;
+      X.fv[c][o][1][t] = h;
+    }
 }
 
-// e_c = -u_a bc_b + u_b bc_a in reverse: adds to the primitive adjoints.
+// e_c = -u_a b_b + u_b b_a in reverse, all three directions: adds to the
+// primitive adjoints.
 __global__ void __launch_bounds__(kBlock)
-    k_adj_ecell(Geom G, AdjArrays X, PrimPtrs PB, const double* EB, int c, const int* stop) {
+    k_adj_ecell(Geom G, AdjArrays X, PrimPtrs PB, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
-  const double g = EB[t];
-  if (g == 0.0) return;
-  const int a = (c + 1) % 3, b = (c + 2) % 3;
-  PB.p[1 + a][t] += -g * X.prim[5 + b][t];
-  PB.p[5 + b][t] += -g * X.prim[1 + a][t];
-  PB.p[1 + b][t] += g * X.prim[5 + a][t];
-  PB.p[5 + a][t] += g * X.prim[1 + b][t];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double g = X.eb[c][t];
+    if (g == 0.0) continue;
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    PB.p[1 + a][t] += -g * X.prim[5 + b][t];
+    PB.p[5 + b][t] += -g * X.prim[1 + a][t];
+    PB.p[1 + b][t] += g * X.prim[5 + a][t];
+    PB.p[5 + a][t] += g * X.prim[1 + b][t];
+  }
 }
 
+// Per axis D, one launch of the second-step gathers (the orders whose second
+// axis is D) and one of the first-step gathers (the orders whose first axis
+// is D); the first of the two first-step gathers of a direction writes the
+// cell-EMF adjoint, the other adds.
 template <int RECON>
 int b25a_cell_emf_adj(hipStream_t st, const Geom& G, const Work<double>& W, const AdjArrays& X,
                       const PrimPtrs& PB, const int* stop) {
   const int nb = nblocks(G.elems);
-  double* const T0 = X.tmp[0];
-  double* const T1 = X.tmp[1];
-  double* const T2 = X.tmp[2];
-  double* const T3 = X.tmp[3];
-  double* const EB = X.tmp[4];
-  for (int c = 0; c < 3; ++c) {
-    const int a = (c + 1) % 3, b = (c + 2) % 3;
-    for (int order = 0; order < 2; ++order) {
-      const int d1 = order == 0 ? a : b, d2 = order == 0 ? b : a;
-      double* const* E = X.ec[c] + 4 * order;  // LB, RB, LT, RT of this order
-      LAUNCH(k_adj_iface<RECON>, nb, G, W.ecell[c], d1, T0, T1, stop);
-      // second step: the lower-d1 face values give the LB / LT corners, the
-      // upper ones RB / RT
-      LineJobs J{};
-      J.chunk = 16;
-      J.j[0] = LineJob{T0, E[0], E[2], T2, 0};
-      J.j[1] = LineJob{T1, E[1], E[3], T3, 0};
-      if (const int rc = launch_lines<RECON>(st, G, d2, J, 2, stop)) return rc;
-      // first step
-      LineJobs K{};
-      K.chunk = 16;
-      K.j[0] = LineJob{W.ecell[c], T2, T3, EB, order};
-      if (const int rc = launch_lines<RECON>(st, G, d1, K, 1, stop)) return rc;
-    }
-    LAUNCH(k_adj_ecell, nb, G, X, PB, EB, c, stop);
+  LAUNCH(k_adj_iface<RECON>, nb, G, W, X, stop);
+  for (int D = 0; D < 3; ++D) {
+    LineJobs J{};
+    J.chunk = 16;
+    int n = 0;
+    for (int c = 0; c < 3; ++c)
+      for (int o = 0; o < 2; ++o) {
+        const int d2 = o == 0 ? (c + 2) % 3 : (c + 1) % 3;
+        if (d2 != D) continue;
+        double* const* E = X.ec[c] + 4 * o;  // LB, RB, LT, RT of this order
+        // the lower-d1 face values give the LB / LT corners, the upper RB / RT
+        J.j[n++] = LineJob{X.fv[c][o][0], E[0], E[2], X.fb[c][o][0], 0};
+        J.j[n++] = LineJob{X.fv[c][o][1], E[1], E[3], X.fb[c][o][1], 0};
+      }
+    if (const int rc = launch_lines<RECON>(st, G, D, J, n, stop)) return rc;
   }
+  for (int D = 0; D < 3; ++D) {
+    LineJobs J{};
+    J.chunk = 16;
+    int n = 0;
+    for (int c = 0; c < 3; ++c)
+      for (int o = 0; o < 2; ++o) {
+        const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+        const int other = o == 0 ? (c + 2) % 3 : (c + 1) % 3;
+        if (d1 != D) continue;
+        J.j[n++] = LineJob{W.ecell[c], X.fb[c][o][0], X.fb[c][o][1], X.eb[c], d1 > other};
+      }
+    if (const int rc = launch_lines<RECON>(st, G, D, J, n, stop)) return rc;
+  }
+  LAUNCH(k_adj_ecell, nb, G, X, PB, stop);
   return CTMHD_OK;
 }
 
@@ -723,8 +746,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
 // ---------------------------------------------------------------------------
 // V, G1, prim, ea, fa, bn, bj, ca, cb, saved face arrays of S0
 constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3 + 9;
-// B25a: corner adjoints and gather scratch
-constexpr int kAdjArraysB25a = 24 + 5;
+// B25a: corner adjoints, first-step values and their adjoints, cell-EMF adjoint
+constexpr int kAdjArraysB25a = 24 + 12 + 12 + 3;
 
 size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
   size_t e = 1;
@@ -801,7 +824,13 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
   for (int c = 0; c < 3; ++c)
     for (int q = 0; q < 8; ++q) X.ec[c][q] = EMF == kB25A ? cv.take<double>(e) : nullptr;
-  for (int q = 0; q < 5; ++q) X.tmp[q] = EMF == kB25A ? cv.take<double>(e) : nullptr;
+  for (int c = 0; c < 3; ++c)
+    for (int o = 0; o < 2; ++o)
+      for (int k = 0; k < 2; ++k) {
+        X.fv[c][o][k] = EMF == kB25A ? cv.take<double>(e) : nullptr;
+        X.fb[c][o][k] = EMF == kB25A ? cv.take<double>(e) : nullptr;
+      }
+  for (int c = 0; c < 3; ++c) X.eb[c] = EMF == kB25A ? cv.take<double>(e) : nullptr;
   Work<double> W0 = W;  // W with the face arrays of S0 (saved after its face pass)
   for (int a = 0; a < 3; ++a) {
     W0.ap[a] = cv.take<double>(e);
