@@ -464,11 +464,12 @@ int launch_lines(hipStream_t st, const Geom& G, int D, const LineJobs& J, int nj
 // from the edges that reconstruct them along the two transverse axes: edges
 // of direction c read them along b, edges of direction b along c.  Written to
 // fa[a][7] and bn[a]; on each axis the faces whose first gather it is write,
-// the others add.
+// the others add.  Without u* at the edges (B25a) only the face fields are
+// gathered, and k_adj_zero3 has cleared fa[a][7].
 // ---------------------------------------------------------------------------
 template <int RECON>
 int face_lines(hipStream_t st, const Geom& G, const State& S, const Work<double>& W,
-               const AdjArrays& X, const int* stop) {
+               const AdjArrays& X, bool ustar, const int* stop) {
   for (int D = 0; D < 3; ++D) {
     LineJobs J{};
     J.chunk = 16;
@@ -477,11 +478,11 @@ int face_lines(hipStream_t st, const Geom& G, const State& S, const Work<double>
       const int b = (a + 1) % 3, c = (a + 2) % 3;
       if (D == b) {  // the first gather of face direction a when b < c
         const int acc = b > c;
-        J.j[n++] = LineJob{W.us[a], X.ea[c][0], X.ea[c][1], X.fa[a][7], acc};
+        if (ustar) J.j[n++] = LineJob{W.us[a], X.ea[c][0], X.ea[c][1], X.fa[a][7], acc};
         J.j[n++] = LineJob{S.b[a], X.ea[c][4], X.ea[c][5], X.bn[a], acc};
       } else if (D == c) {
         const int acc = c > b;
-        J.j[n++] = LineJob{W.us[a], X.ea[b][2], X.ea[b][3], X.fa[a][7], acc};
+        if (ustar) J.j[n++] = LineJob{W.us[a], X.ea[b][2], X.ea[b][3], X.fa[a][7], acc};
         J.j[n++] = LineJob{S.b[a], X.ea[b][6], X.ea[b][7], X.bn[a], acc};
       }
     }
@@ -734,11 +735,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_save9(Geom G, Work<double> W, Wo
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X) {
+// Clears the Ohmic accumulators, and the u* adjoints when no edge reads u*
+// (B25a), where the face gathers leave them unwritten.
+__global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X, int zero_us) {
   const int t = gidx();
   if (t >= G.elems) return;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) X.bj[a][t] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    X.bj[a][t] = 0.0;
+    if (zero_us) X.fa[a][7][t] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -769,11 +775,11 @@ template <int RECON, int RIEMANN, int EMF>
 int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<double>& W,
           const AdjArrays& X) {
   const int nb = nblocks(G.elems);
-  LAUNCH(k_adj_zero3, nb, G, X);
+  LAUNCH(k_adj_zero3, nb, G, X, EMF == kB25A ? 1 : 0);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
   if constexpr (EMF == kB25A) LAUNCH((k_prim<double, kB25A>), nb, S, G, W, p->gamma, W.stop);
   LAUNCH((k_adj_edge<RECON, EMF>), nb, S, G, W, X, p->eta, W.stop);
-  if (const int rc = face_lines<RECON>(st, G, S, W, X, W.stop)) return rc;
+  if (const int rc = face_lines<RECON>(st, G, S, W, X, EMF == kQ26, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
   hipLaunchKernelGGL(k_adj_fgather, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
                      W.stop);
