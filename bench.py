@@ -302,7 +302,7 @@ def _adjoint_step_times(P, cons, bf, dx, calls=20):
 def run_adjoint_form(nsteps=20, every=5, reps=3):
     """The derivative workload: 64^3 smooth periodic box (3 sine modes of
     amplitude 0.05 per field, beta = 1), PLM-MC or PPM + HLLD + Q26 + LD04,
-    FP64 (also PLM-MC with the B25a EMF, and PLM-MC in the FP32 form), no
+    FP64 (also PLM-MC with the B25a and FS18 EMFs, and PLM-MC in the FP32 form), no
     flux correction; loss = total kinetic energy after `nsteps`
     steps; the gradient with respect to the initial velocity and face field
     through the hand-written adjoint with a checkpoint every `every` steps.
@@ -331,7 +331,8 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
            "gradient": "d loss / d (initial velocity, initial face field)",
            "timing": f"fastest of {reps} repetitions"}
     for recon, prec, emf in (("plm", "fp64", "q26"), ("ppm", "fp64", "q26"),
-                             ("plm", "fp64", "b25a"), ("plm", "fp32", "q26")):
+                             ("plm", "fp64", "b25a"), ("plm", "fp64", "fs18"),
+                             ("plm", "fp32", "q26")):
         P = ctmhd.make_params(recon=recon, riemann="hlld", emf=emf, eta=0.0, fofc=False,
                               precision=prec)
         tf_best = tb_best = None

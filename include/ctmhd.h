@@ -220,8 +220,8 @@ size_t ctmhd_adjoint_workspace_bytes(const ctmhd_params* p, const ctmhd_box* box
  * The derivative is taken on the branches the forward step takes at S^n
  * (limiter cases, Riemann-fan regions, min / max selections).  Built for the
  * FP64 form with PC, PLM (MC or minmod) or PPM reconstruction, HLLD or LLF,
- * Q26 or B25a corner EMFs and LD04, eta >= 0; other configurations (FP32 form,
- * FS18) return CTMHD_EUNSUPPORTED.  A
+ * Q26, B25a or FS18 corner EMFs and LD04, eta >= 0; the FP32 form returns
+ * CTMHD_EUNSUPPORTED.  A
  * non-finite dt writes NaN.  Deterministic except for the Ohmic terms (eta >
  * 0), whose face-field adjoints are accumulated with atomics. */
 int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,

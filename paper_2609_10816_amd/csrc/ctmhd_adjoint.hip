@@ -48,15 +48,26 @@ struct AdjArrays {
   double* bj[3];       // face-field adjoint of the Ohmic terms (atomic accumulation)
   double* ca[5];       // conserved-field adjoint per cell
   double* cb[3];       // cell-centred field adjoint per cell
-  // B25a only: per edge direction, the adjoints of the corner values of the
-  // two-step reconstructions of the cell EMF, (LB, RB, LT, RT) in the order
-  // [x_a x_b] then [x_b x_a]; per edge direction and order the first-step
-  // face values (lower, upper side) and their adjoints; the cell-EMF adjoint
-  double* ec[3][8];
-  double* fv[3][2][2];
-  double* fb[3][2][2];
+  // B25a and FS18 only.  Per edge direction c, the cell fields reconstructed
+  // to the corners in two steps: B25a the cell EMF e_c (field 0), FS18 the
+  // cell velocities u_a (field 0) and u_b (field 1).  ec[c][8 f + 4 o + q]:
+  // adjoint of corner q (LB, RB, LT, RT) of field f in order o ([x_a x_b],
+  // then [x_b x_a]); fv / fb[c][f][o][side]: the first-step face values
+  // (lower, upper side) and their adjoints; eb[k]: the adjoint of the cell
+  // field (B25a: e_k; FS18: u_k)
+  double* ec[3][16];
+  double* fv[3][2][2][2];
+  double* fb[3][2][2][2];
   double* eb[3];
 };
+
+// Cell fields of the two-step corner reconstructions of edge direction c.
+__host__ __device__ constexpr int corner_fields(int emf) { return emf == kFS18 ? 2 : emf == kB25A ? 1 : 0; }
+__host__ __device__ constexpr int corner_comp(int c, int f) { return f == 0 ? (c + 1) % 3 : (c + 2) % 3; }
+template <int EMF>
+__host__ __device__ const double* corner_src(const Work<double>& W, int c, int f) {
+  return EMF == kB25A ? W.ecell[c] : W.prim[1 + corner_comp(c, f)];
+}
 
 __device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
   s3[0] = t % G.N[0];
@@ -119,10 +130,8 @@ __global__ void __launch_bounds__(kBlock)
     if (!inside || s3[c] >= G.g + G.n[c]) {
 #pragma unroll
       for (int q = 0; q < 13; ++q) X.ea[c][q][t] = 0.0;
-      if constexpr (EMF == kB25A) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) X.ec[c][q][t] = 0.0;
-      }
+      for (int q = 0; q < 8 * corner_fields(EMF); ++q) X.ec[c][q][t] = 0.0;
       continue;
     }
     const int a = (c + 1) % 3, b = (c + 2) % 3;
@@ -157,6 +166,34 @@ __global__ void __launch_bounds__(kBlock)
       X.ec[c][5][t] = 0.5 * eb[2];
       X.ec[c][6][t] = 0.5 * eb[1];
       X.ec[c][7][t] = 0.5 * eb[3];
+    } else if constexpr (EMF == kFS18) {
+      // corners: -u1 b_b + u2 b_a with u1, u2 the means of the two two-step
+      // reconstructions of u_a and u_b (edge_emf)
+      double ua_ab[4], ua_ba[4], ub_ab[4], ub_ba[4];
+      two_step<RECON>(W.prim[1 + a], t, sa, sb, ua_ab);
+      two_step<RECON>(W.prim[1 + a], t, sb, sa, ua_ba);
+      two_step<RECON>(W.prim[1 + b], t, sa, sb, ub_ab);
+      two_step<RECON>(W.prim[1 + b], t, sb, sa, ub_ba);
+      constexpr int perm[4] = {0, 2, 1, 3};  // corner q -> [x_b x_a] index
+      double u1[4], u2[4], e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u1[q] = 0.5 * (ua_ab[q] + ua_ba[perm[q]]);
+        u2[q] = 0.5 * (ub_ab[q] + ub_ba[perm[q]]);
+        e[q] = -u1[q] * bv[2 + (q & 1)] + u2[q] * bv[q >> 1];
+      }
+      double eb[4] = {0.0, 0.0, 0.0, 0.0};
+      ld04_adj(e, bv, al, Eb, eb, bb, alb);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bb[2 + (q & 1)] += -eb[q] * u1[q];
+        bb[q >> 1] += eb[q] * u2[q];
+        const double u1b = -eb[q] * bv[2 + (q & 1)], u2b = eb[q] * bv[q >> 1];
+        X.ec[c][q][t] = 0.5 * u1b;                 // u_a, [x_a x_b]
+        X.ec[c][4 + perm[q]][t] = 0.5 * u1b;       // u_a, [x_b x_a]
+        X.ec[c][8 + q][t] = 0.5 * u2b;             // u_b, [x_a x_b]
+        X.ec[c][12 + perm[q]][t] = 0.5 * u2b;      // u_b, [x_b x_a]
+      }
     } else {
       double u[4];
       iface_along<RECON>(W.us[a], t, sb, u[0], u[1]);  // uaB, uaT
@@ -527,11 +564,11 @@ int cell_lines(hipStream_t st, const Geom& G, const AdjArrays& X, double* const 
 // through the line gathers above.  Finally the cell-EMF adjoint onto u and
 // the cell-centred field.
 // ---------------------------------------------------------------------------
-// First step along d1 at every position, for every edge direction c and
-// order (d1 = a then b): the values on both sides of the x_d1 interface at t
-// (upper value of the cell t - st_d1, lower value of t), 0 where the stencil
-// leaves the box.
-template <int RECON>
+// First step along d1 at every position, for every edge direction c, field
+// and order (d1 = a then b): the values on both sides of the x_d1 interface
+// at t (upper value of the cell t - st_d1, lower value of t), 0 where the
+// stencil leaves the box.
+template <int RECON, int EMF>
 __global__ void __launch_bounds__(kBlock)
     k_adj_iface(Geom G, Work<double> W, AdjArrays X, const int* stop) {
   if (*stop) return;
@@ -543,14 +580,26 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-      const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
-      double l = 0.0, h = 0.0;
-      if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
-        iface_along<RECON>(W.ecell[c], t, G.st[d1], l, h);
-      X.fv[c][o][0][t] = l;
-      X.fv[c][o][1][t] = h;
-    }
+    for (int f = 0; f < corner_fields(EMF); ++f)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+        double l = 0.0, h = 0.0;
+        if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
+          iface_along<RECON>(corner_src<EMF>(W, c, f), t, G.st[d1], l, h);
+        X.fv[c][f][o][0][t] = l;
+        X.fv[c][f][o][1][t] = h;
+      }
+}
+
+// FS18: the cell-velocity adjoints onto the primitive adjoints.
+__global__ void __launch_bounds__(kBlock)
+    k_adj_ucell(Geom G, AdjArrays X, PrimPtrs PB, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) PB.p[1 + d][t] += X.eb[d][t];
 }
 
 // e_c = -u_a b_b + u_b b_a in reverse, all three directions: adds to the
@@ -573,43 +622,69 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Per axis D, one launch of the second-step gathers (the orders whose second
-// axis is D) and one of the first-step gathers (the orders whose first axis
-// is D); the first of the two first-step gathers of a direction writes the
-// cell-EMF adjoint, the other adds.
-template <int RECON>
-int b25a_cell_emf_adj(hipStream_t st, const Geom& G, const Work<double>& W, const AdjArrays& X,
-                      const PrimPtrs& PB, const int* stop) {
+// axis is D), then the first-step gathers (the orders whose first axis is D)
+// in launches whose jobs write distinct cell-field adjoints; the first gather
+// into a cell-field adjoint writes it, the later ones add.
+template <int RECON, int EMF>
+int cell_corner_adj(hipStream_t st, const Geom& G, const Work<double>& W, const AdjArrays& X,
+                    const PrimPtrs& PB, const int* stop) {
+  constexpr int NF = corner_fields(EMF);
   const int nb = nblocks(G.elems);
-  LAUNCH(k_adj_iface<RECON>, nb, G, W, X, stop);
+  LAUNCH((k_adj_iface<RECON, EMF>), nb, G, W, X, stop);
   for (int D = 0; D < 3; ++D) {
     LineJobs J{};
     J.chunk = 16;
     int n = 0;
     for (int c = 0; c < 3; ++c)
-      for (int o = 0; o < 2; ++o) {
-        const int d2 = o == 0 ? (c + 2) % 3 : (c + 1) % 3;
-        if (d2 != D) continue;
-        double* const* E = X.ec[c] + 4 * o;  // LB, RB, LT, RT of this order
-        // the lower-d1 face values give the LB / LT corners, the upper RB / RT
-        J.j[n++] = LineJob{X.fv[c][o][0], E[0], E[2], X.fb[c][o][0], 0};
-        J.j[n++] = LineJob{X.fv[c][o][1], E[1], E[3], X.fb[c][o][1], 0};
-      }
+      for (int f = 0; f < NF; ++f)
+        for (int o = 0; o < 2; ++o) {
+          const int d2 = o == 0 ? (c + 2) % 3 : (c + 1) % 3;
+          if (d2 != D) continue;
+          double* const* E = X.ec[c] + 8 * f + 4 * o;  // LB, RB, LT, RT
+          // the lower-d1 face values give the LB / LT corners, the upper RB / RT
+          J.j[n++] = LineJob{X.fv[c][f][o][0], E[0], E[2], X.fb[c][f][o][0], 0};
+          J.j[n++] = LineJob{X.fv[c][f][o][1], E[1], E[3], X.fb[c][f][o][1], 0};
+        }
     if (const int rc = launch_lines<RECON>(st, G, D, J, n, stop)) return rc;
   }
+  bool written[3] = {false, false, false};
   for (int D = 0; D < 3; ++D) {
-    LineJobs J{};
-    J.chunk = 16;
-    int n = 0;
+    LineJob pend[12];
+    int dst[12], np = 0;
     for (int c = 0; c < 3; ++c)
-      for (int o = 0; o < 2; ++o) {
-        const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
-        const int other = o == 0 ? (c + 2) % 3 : (c + 1) % 3;
-        if (d1 != D) continue;
-        J.j[n++] = LineJob{W.ecell[c], X.fb[c][o][0], X.fb[c][o][1], X.eb[c], d1 > other};
+      for (int f = 0; f < NF; ++f)
+        for (int o = 0; o < 2; ++o) {
+          const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+          if (d1 != D) continue;
+          const int k = EMF == kB25A ? c : corner_comp(c, f);
+          pend[np] = LineJob{corner_src<EMF>(W, c, f), X.fb[c][f][o][0], X.fb[c][f][o][1], X.eb[k], 0};
+          dst[np++] = k;
+        }
+    while (np > 0) {  // launches with distinct destinations
+      LineJobs J{};
+      J.chunk = 16;
+      int n = 0;
+      bool used[3] = {false, false, false};
+      for (int i = 0; i < np;) {
+        if (!used[dst[i]] && n < kMaxLineJobs) {
+          used[dst[i]] = true;
+          J.j[n] = pend[i];
+          J.j[n++].acc = written[dst[i]] ? 1 : 0;
+          pend[i] = pend[np - 1];
+          dst[i] = dst[np - 1];
+          --np;
+        } else {
+          ++i;
+        }
       }
-    if (const int rc = launch_lines<RECON>(st, G, D, J, n, stop)) return rc;
+      for (int k = 0; k < 3; ++k) written[k] = written[k] || used[k];
+      if (const int rc = launch_lines<RECON>(st, G, D, J, n, stop)) return rc;
+    }
   }
-  LAUNCH(k_adj_ecell, nb, G, X, PB, stop);
+  if constexpr (EMF == kB25A)
+    LAUNCH(k_adj_ecell, nb, G, X, PB, stop);
+  else
+    LAUNCH(k_adj_ucell, nb, G, X, PB, stop);
   return CTMHD_OK;
 }
 
@@ -752,21 +827,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X, int z
 // ---------------------------------------------------------------------------
 // V, G1, prim, ea, fa, bn, bj, ca, cb, saved face arrays of S0
 constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3 + 9;
-// B25a: corner adjoints, first-step values and their adjoints, cell-EMF adjoint
-constexpr int kAdjArraysB25a = 24 + 12 + 12 + 3;
+// B25a / FS18: per cell field of the corner reconstructions, 24 corner
+// adjoints and 12 + 12 first-step values and adjoints; 3 cell-field adjoints
+constexpr int kAdjArraysPerField = 24 + 12 + 12;
 
 size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
   size_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
-  const int n = kAdjArrays + (p->emf_compute == CTMHD_EMF_B25A ? kAdjArraysB25a : 0);
+  const int nf = p->emf_compute == CTMHD_EMF_FS18 ? 2 : p->emf_compute == CTMHD_EMF_B25A ? 1 : 0;
+  const int n = kAdjArrays + nf * kAdjArraysPerField + (nf ? 3 : 0);
   return box_ws_bytes(b, 8, p->emf_compute) + (size_t)n * align256(e * 8);
 }
 
 int check_adjoint(const ctmhd_params* p) {
   if (p->precision != CTMHD_FP64)
     return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the FP64 form only");
-  if (p->emf_compute != CTMHD_EMF_Q26 && p->emf_compute != CTMHD_EMF_B25A)
-    return fail(CTMHD_EUNSUPPORTED, "the adjoint is built for the Q26 and B25a EMFs only");
   return CTMHD_OK;
 }
 
@@ -775,9 +850,9 @@ template <int RECON, int RIEMANN, int EMF>
 int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<double>& W,
           const AdjArrays& X) {
   const int nb = nblocks(G.elems);
-  LAUNCH(k_adj_zero3, nb, G, X, EMF == kB25A ? 1 : 0);
+  LAUNCH(k_adj_zero3, nb, G, X, EMF != kQ26 ? 1 : 0);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
-  if constexpr (EMF == kB25A) LAUNCH((k_prim<double, kB25A>), nb, S, G, W, p->gamma, W.stop);
+  if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, S, G, W, p->gamma, W.stop);
   LAUNCH((k_adj_edge<RECON, EMF>), nb, S, G, W, X, p->eta, W.stop);
   if (const int rc = face_lines<RECON>(st, G, S, W, X, EMF == kQ26, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
@@ -790,8 +865,8 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   PrimPtrs PB;
   for (int v = 0; v < 8; ++v) PB.p[v] = X.ea[0][v];
   if (const int rc = cell_lines<RECON>(st, G, X, PB.p, W.stop)) return rc;
-  if constexpr (EMF == kB25A)
-    if (const int rc = b25a_cell_emf_adj<RECON>(st, G, W, X, PB, W.stop)) return rc;
+  if constexpr (EMF != kQ26)
+    if (const int rc = cell_corner_adj<RECON, EMF>(st, G, W, X, PB, W.stop)) return rc;
   LAUNCH(k_adj_cfinish, nb, G, X, PB, p->gamma, W.stop);
   LAUNCH(k_adj_bsum, nb, G, X, W.stop);
   return CTMHD_OK;
@@ -828,15 +903,17 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   for (int a = 0; a < 3; ++a) X.bj[a] = cv.take<double>(e);
   for (int m = 0; m < 5; ++m) X.ca[m] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
-  for (int c = 0; c < 3; ++c)
-    for (int q = 0; q < 8; ++q) X.ec[c][q] = EMF == kB25A ? cv.take<double>(e) : nullptr;
-  for (int c = 0; c < 3; ++c)
-    for (int o = 0; o < 2; ++o)
-      for (int k = 0; k < 2; ++k) {
-        X.fv[c][o][k] = EMF == kB25A ? cv.take<double>(e) : nullptr;
-        X.fb[c][o][k] = EMF == kB25A ? cv.take<double>(e) : nullptr;
-      }
-  for (int c = 0; c < 3; ++c) X.eb[c] = EMF == kB25A ? cv.take<double>(e) : nullptr;
+  constexpr int NF = corner_fields(EMF);
+  for (int c = 0; c < 3; ++c) {
+    for (int q = 0; q < 16; ++q) X.ec[c][q] = q < 8 * NF ? cv.take<double>(e) : nullptr;
+    for (int f = 0; f < 2; ++f)
+      for (int o = 0; o < 2; ++o)
+        for (int k = 0; k < 2; ++k) {
+          X.fv[c][f][o][k] = f < NF ? cv.take<double>(e) : nullptr;
+          X.fb[c][f][o][k] = f < NF ? cv.take<double>(e) : nullptr;
+        }
+  }
+  for (int c = 0; c < 3; ++c) X.eb[c] = NF ? cv.take<double>(e) : nullptr;
   Work<double> W0 = W;  // W with the face arrays of S0 (saved after its face pass)
   for (int a = 0; a < 3; ++a) {
     W0.ap[a] = cv.take<double>(e);
@@ -874,7 +951,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
          (long long*)nullptr);
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   LAUNCH(k_adj_save9, nb, G, W, W0);
-  if constexpr (EMF == kB25A) LAUNCH((k_prim<double, kB25A>), nb, A, G, W, p->gamma, W.stop);
+  if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, A, G, W, p->gamma, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
@@ -902,6 +979,8 @@ int adjoint_riemann(const ctmhd_params* p, const ctmhd_box* box, const double* c
   adjoint_box<RECON, RI, EM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out, g_bface_out, ws, ws_bytes, st)
   if (p->emf_compute == CTMHD_EMF_B25A)
     return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kB25A) : CTMHD_ADJ(kLLF, kB25A);
+  if (p->emf_compute == CTMHD_EMF_FS18)
+    return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kFS18) : CTMHD_ADJ(kLLF, kFS18);
   return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kQ26) : CTMHD_ADJ(kLLF, kQ26);
 #undef CTMHD_ADJ
 }
