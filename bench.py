@@ -2,7 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb128|turb256|turb512]
                 [--precision fp64|fp32] [--emf q26|b25a|fs18] [--no-cpu-baseline]
-                [--no-fp32] [--no-batched] [--no-adjoint] [--copy-calibration]
+                [--no-fp32] [--no-batched] [--no-adjoint] [--no-level] [--copy-calibration]
 
 Prints ONE JSON line.  A step is one full RK2-SSP step with first-order flux
 correction on a seeded synthetic state already resident in HBM: CFL dt
@@ -20,13 +20,17 @@ around every launch inside the timed region.  The path is bound by FP64
 vector ALU throughput (peak 78.6 TFLOP/s on MI355X), not by HBM.
 traffic: HBM bytes per launch from the committed rocprofv3 counter summary
 of the same kernel source, or null if the kernel source has changed since.
+step_hbm_measured: the counters' bytes of every kernel of one step over the
+measured step time, against the 8 TB/s HBM peak (same guard).
 
 Beside the headline line's FP64 value the same JSON line carries the other
-forms: fp32_form (the same workload in the FP32 form), batched_form (2000
+forms: fp32_form (the same workload in the FP32 form), level_form (the same
+box cut into 64 boxes of 32^3 that exchange ghost layers), batched_form (2000
 AMR-like boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against
 one ctmhd_step call per box) and adjoint_form (64^3 gradient of the kinetic
-energy after 20 steps through the hand-written adjoint, PLM and PPM: backward /
-forward time of the rollout, and one adjoint step against one forward step).
+energy after 20 steps through the hand-written adjoint, PLM and PPM with Q26,
+PLM with B25a and FS18: backward / forward time of the rollout, and one
+adjoint step against one forward step).
 """
 from __future__ import annotations
 
@@ -75,9 +79,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(config, precision, emf):
-    """Per-launch HBM bytes of the face kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
+def read_traffic(config, precision, emf, what="bytes_per_launch"):
+    """HBM bytes from the committed counter summary (`bytes_per_launch`: one
+    launch of the face kernel; `bytes_per_step`: every kernel of one step), if
+    it was taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -88,7 +93,7 @@ def read_traffic(config, precision, emf):
     if kv.get("kernel_source_sha") != kernel_source_hash():
         return None
     key = f"{config}/{precision}/{emf}"
-    v = kv.get(f"bytes_per_launch[{key}]")
+    v = kv.get(f"{what}[{key}]")
     return float(v) if v else None
 
 
@@ -476,11 +481,19 @@ def main():
                      "faces_per_launch": 3 * n3},
         "step_alu_frac": value * 1e6 * cell_update_flops / (PEAK_FP64_TFLOPS * 1e12),
         "hbm_frac_algorithmic": value * 1e6 * ALG_BYTES_PER_CELL_UPDATE / (PEAK_HBM_GBS * 1e9),
+        "step_hbm_measured": None,
         "fofc_flagged_cells": res["flagged"],
         "hll_fallbacks": res["hll"],
         "paper_context": ">50 M cell-updates/s per GPU (one MI250X GCD, PPM-EP + HLLD + Q26, "
                          "512^3 on 4 GCDs); context, not the target",
     }
+    step_bytes = read_traffic(args.config, args.precision, args.emf, "bytes_per_step")
+    if step_bytes:
+        gbs = step_bytes / (res["elapsed"] / K) / 1e9
+        out["step_hbm_measured"] = {"bytes_per_step": step_bytes, "achieved_GBs": gbs,
+                                    "peak_GBs": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS,
+                                    "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of every "
+                                              "kernel of a step, profiles/traffic_face_kernel.txt"}
     if args.precision == "fp64" and not args.no_fp32:
         r32, _ = run_gpu(cfg, "fp32", args.emf, K, W)
         v32 = n3 * K / r32["elapsed"] / 1e6
