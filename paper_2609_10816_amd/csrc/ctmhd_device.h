@@ -46,6 +46,11 @@ Geom make_geom(const ctmhd_box& b) {
 
 __device__ __forceinline__ int gidx() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Storage stride of axis d.  The x stride is 1 by construction; returning it
+// as a constant (d is known at compile time at every call site) lets the
+// compiler fold x-neighbour offsets into the load instructions.
+__device__ __forceinline__ int gstride(const Geom& G, int d) { return d == 0 ? 1 : G.st[d]; }
+
 // Workgroups are dispatched to the 8 XCDs of the chip round-robin (workgroup
 // i on XCD i mod 8), and each XCD has its own L2.  This permutation of the
 // tiles of a launch gives each XCD a contiguous run of them, so that the
@@ -325,7 +330,8 @@ __global__ void __launch_bounds__(kBlock) k_prim(State S, Geom G, Work<T> W, dou
 template <typename T>
 __device__ __forceinline__ T eta_j(const State& S, const Geom& G, int s, int c, T eta) {
   int a = (c + 1) % 3, b = (c + 2) % 3;
-  double j = (S.b[b][s] - S.b[b][s - G.st[a]]) * G.idx[a] - (S.b[a][s] - S.b[a][s - G.st[b]]) * G.idx[b];
+  double j = (S.b[b][s] - S.b[b][s - gstride(G, a)]) * G.idx[a] -
+             (S.b[a][s] - S.b[a][s - gstride(G, b)]) * G.idx[b];
   return eta * (T)j;
 }
 
@@ -335,13 +341,14 @@ __device__ __forceinline__ T eta_j(const State& S, const Geom& G, int s, int c, 
 template <typename T>
 __device__ __forceinline__ T joule(const State& S, const Geom& G, int s, int a, T eta) {
   int b = (a + 1) % 3, c = (a + 2) % 3;
-  T eb = T(0.5) * (eta_j<T>(S, G, s, b, eta) + eta_j<T>(S, G, s + G.st[c], b, eta));
-  T ec = T(0.5) * (eta_j<T>(S, G, s, c, eta) + eta_j<T>(S, G, s + G.st[b], c, eta));
-  int l = s - G.st[a];
-  T bbl = (T)(0.5 * (S.b[b][l] + S.b[b][l + G.st[b]]));
-  T bbr = (T)(0.5 * (S.b[b][s] + S.b[b][s + G.st[b]]));
-  T bcl = (T)(0.5 * (S.b[c][l] + S.b[c][l + G.st[c]]));
-  T bcr = (T)(0.5 * (S.b[c][s] + S.b[c][s + G.st[c]]));
+  const int sb = gstride(G, b), sc = gstride(G, c);
+  T eb = T(0.5) * (eta_j<T>(S, G, s, b, eta) + eta_j<T>(S, G, s + sc, b, eta));
+  T ec = T(0.5) * (eta_j<T>(S, G, s, c, eta) + eta_j<T>(S, G, s + sb, c, eta));
+  int l = s - gstride(G, a);
+  T bbl = (T)(0.5 * (S.b[b][l] + S.b[b][l + sb]));
+  T bbr = (T)(0.5 * (S.b[b][s] + S.b[b][s + sb]));
+  T bcl = (T)(0.5 * (S.b[c][l] + S.b[c][l + sc]));
+  T bcr = (T)(0.5 * (S.b[c][s] + S.b[c][s + sc]));
   return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
 }
 
@@ -641,7 +648,7 @@ template <typename T, int RECON, int EMF>
 __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
                                       double eta_d) {
   const int a = (c + 1) % 3, b = (c + 2) % 3;
-  const int sa = G.st[a], sb = G.st[b];
+  const int sa = gstride(G, a), sb = gstride(G, b);
   T baB, baT, bbL, bbR;
   iface_along_d<RECON>(S.b[a], s, sb, baB, baT);
   iface_along_d<RECON>(S.b[b], s, sa, bbL, bbR);
@@ -723,7 +730,7 @@ __device__ __forceinline__ double dcons(const Geom& G, const Work<T>& W, int st,
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const T* Fa = W.F[st][a][m];
-    f += ((double)Fa[s] - (double)Fa[s + G.st[a]]) * G.idx[a];
+    f += ((double)Fa[s] - (double)Fa[s + gstride(G, a)]) * G.idx[a];
   }
   return dt * f;
 }
@@ -735,8 +742,8 @@ __device__ __forceinline__ double dface(const Geom& G, const Work<T>& W, int st,
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const T* Ec = W.E[st][c];
   const T* Eb = W.E[st][b];
-  double circ = ((double)Ec[s] - (double)Ec[s + G.st[b]]) * G.idx[b] +
-                ((double)Eb[s + G.st[c]] - (double)Eb[s]) * G.idx[c];
+  double circ = ((double)Ec[s] - (double)Ec[s + gstride(G, b)]) * G.idx[b] +
+                ((double)Eb[s + gstride(G, c)] - (double)Eb[s]) * G.idx[c];
   return dt * circ;
 }
 
@@ -821,7 +828,8 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
       // the neighbour that owns them
       double bu[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) bu[a] = new_face(base, half, G, W, stage, fixup, s + G.st[a], a, dt);
+      for (int a = 0; a < 3; ++a)
+        bu[a] = new_face(base, half, G, W, stage, fixup, s + gstride(G, a), a, dt);
       const double rho = c[0];
       double u[3], bc[3];
       bool nonfin = false;
