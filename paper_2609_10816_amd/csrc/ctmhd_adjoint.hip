@@ -105,9 +105,9 @@ __device__ __forceinline__ void etaj_adj(double* const bj[3], const Geom& G, int
                                          double coef) {
   const int a = (c + 1) % 3, b = (c + 2) % 3;
   atomicAdd(&bj[b][s], coef * G.idx[a]);
-  atomicAdd(&bj[b][s - G.st[a]], -coef * G.idx[a]);
+  atomicAdd(&bj[b][s - gstride(G, a)], -coef * G.idx[a]);
   atomicAdd(&bj[a][s], -coef * G.idx[b]);
-  atomicAdd(&bj[a][s - G.st[b]], coef * G.idx[b]);
+  atomicAdd(&bj[a][s - gstride(G, b)], coef * G.idx[b]);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kBlock)
       continue;
     }
     const int a = (c + 1) % 3, b = (c + 2) % 3;
-    const int sa = G.st[a], sb = G.st[b];
+    const int sa = gstride(G, a), sb = gstride(G, b);
     // the EMF enters the new face fields b_a at t, t - sb and b_b at t, t - sa
     const double Eb = dt * ((X.v[5 + a][t] - X.v[5 + a][t - sb]) * G.idx[b] -
                             (X.v[5 + b][t] - X.v[5 + b][t - sa]) * G.idx[a]);
@@ -586,7 +586,7 @@ __global__ void __launch_bounds__(kBlock)
         const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
         double l = 0.0, h = 0.0;
         if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
-          iface_along<RECON>(corner_src<EMF>(W, c, f), t, G.st[d1], l, h);
+          iface_along<RECON>(corner_src<EMF>(W, c, f), t, gstride(G, d1), l, h);
         X.fv[c][f][o][0][t] = l;
         X.fv[c][f][o][1][t] = h;
       }
