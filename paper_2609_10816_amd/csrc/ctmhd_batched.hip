@@ -194,6 +194,7 @@ int level_blocks(const ctmhd_box* boxes, int nbox, const LevelSpec& L, std::vect
   blk.clear();
   xbox.assign((size_t)nbox + 1, 0);
   struct Piece { int lo, hi, shift; };
+  constexpr int kMaxPieces = 32;  // per axis: images k in [-K, K], K = g / D + 2
   for (int b = 0; b < nbox; ++b) {
     xbox[b] = (int)blk.size();
     const ctmhd_box& B = boxes[b];
@@ -201,23 +202,28 @@ int level_blocks(const ctmhd_box* boxes, int nbox, const LevelSpec& L, std::vect
     long long vol = 0;
     for (int c = 0; c < nbox; ++c) {
       const ctmhd_box& C = boxes[c];
-      std::vector<Piece> pc[3];
+      Piece pc[3][kMaxPieces];
+      int np[3] = {0, 0, 0};
       bool any = true;
       for (int d = 0; d < 3 && any; ++d) {
         const int D = L.domain[d];
         const int lo = L.origin[3 * b + d] - g, hi = L.origin[3 * b + d] + B.n[d] + g;
         const int K = g / D + 2;
+        if (2 * K + 1 > kMaxPieces) return fail(CTMHD_EARG, "ghost width too large for the level domain");
         for (int k = -K; k <= K; ++k) {
           const int clo = L.origin[3 * c + d] + k * D, chi = clo + C.n[d];
           const int a0 = lo > clo ? lo : clo, a1 = hi < chi ? hi : chi;
-          if (a0 < a1) pc[d].push_back({a0, a1, k});
+          if (a0 < a1) pc[d][np[d]++] = Piece{a0, a1, k};
         }
-        any = !pc[d].empty();
+        any = np[d] > 0;
       }
       if (!any) continue;
-      for (const Piece& z : pc[2])
-        for (const Piece& y : pc[1])
-          for (const Piece& x : pc[0]) {
+      for (int iz = 0; iz < np[2]; ++iz)
+        for (int iy = 0; iy < np[1]; ++iy)
+          for (int ix = 0; ix < np[0]; ++ix) {
+            const Piece& x = pc[0][ix];
+            const Piece& y = pc[1][iy];
+            const Piece& z = pc[2][iz];
             if (c == b && x.shift == 0 && y.shift == 0 && z.shift == 0) continue;  // the interior
             const Piece* q[3] = {&x, &y, &z};
             int dst0[3], src0[3];
