@@ -335,24 +335,24 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
            "loss": "total kinetic energy after the steps",
            "gradient": "d loss / d (initial velocity, initial face field)",
            "timing": f"fastest of {reps} repetitions"}
-    for recon, prec, emf in (("plm", "fp64", "q26"), ("ppm", "fp64", "q26"),
-                             ("plm", "fp64", "b25a"), ("plm", "fp64", "fs18"),
-                             ("plm", "fp32", "q26")):
+    for recon, prec, emf, tape in (("plm", "fp64", "q26", False), ("ppm", "fp64", "q26", False),
+                                   ("plm", "fp64", "b25a", False), ("plm", "fp64", "fs18", False),
+                                   ("plm", "fp32", "q26", False), ("plm", "fp64", "q26", True),
+                                   ("ppm", "fp64", "q26", True)):
         P = ctmhd.make_params(recon=recon, riemann="hlld", emf=emf, eta=0.0, fofc=False,
                               precision=prec)
+        kw = dict(tape=True) if tape else dict(every=every)
         tf_best = tb_best = None
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             with torch.no_grad():
-                ad.rollout(ad.conserved_from_primitives(rho, u0, p, b0), b0, P, dx, nsteps,
-                           every=every)
+                ad.rollout(ad.conserved_from_primitives(rho, u0, p, b0), b0, P, dx, nsteps, **kw)
             torch.cuda.synchronize()
             tf = time.perf_counter() - t0
             u = u0.clone().requires_grad_(True)
             b = b0.clone().requires_grad_(True)
-            c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, nsteps,
-                              every=every)
+            c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, nsteps, **kw)
             ke = ad.kinetic_energy(c, dx)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -364,12 +364,21 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
         key = recon if prec == "fp64" else f"{recon}_fp32_form"
         if emf != "q26":
             key += f"_{emf}"
+        if tape:
+            key += "_tape"
         out[key] = {"forward_ms": tf_best * 1e3, "backward_ms": tb_best * 1e3,
                     "ratio_backward_to_forward": tb_best / tf_best,
                     "grad_norm_u": float(u.grad.norm()), "grad_norm_b": float(b.grad.norm())}
         msg = (f"adjoint form {key}: rollout forward {tf_best * 1e3:.1f} ms, backward "
                f"{tb_best * 1e3:.1f} ms (ratio {tb_best / tf_best:.2f})")
-        if prec == "fp64":
+        if tape:
+            out[key]["note"] = ("every forward step records its tape (ctmhd_step_record); the "
+                                "backward reverses each step from its tape, no recomputation")
+            if recon in out:
+                plain = out[recon]["forward_ms"]
+                out[key]["ratio_backward_to_plain_forward"] = tb_best * 1e3 / plain
+                msg += f"; backward / plain forward {tb_best * 1e3 / plain:.2f}"
+        elif prec == "fp64":
             f_ms, a_ms = _adjoint_step_times(P, cons, bf, dx)
             out[key].update({"step_forward_ms": f_ms, "step_adjoint_ms": a_ms,
                              "ratio_adjoint_step_to_forward_step": a_ms / f_ms})

@@ -231,6 +231,37 @@ int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,
                        double* const g_bface_out[3], void* workspace, size_t ws_bytes,
                        void* stream);
 
+/* Recorded steps for the adjoint (reverse-mode derivative of eqs. rk1:update
+ * and rk2:update, as ctmhd_step_adjoint) without recomputing the first
+ * stage.  ctmhd_step_record advances the box by ONE step exactly as
+ * ctmhd_step with nsteps = 1, dt_fixed = dt and fofc off (bitwise the same
+ * S^{n+1}), and writes its tape: S^n and the first-stage state S1 with their
+ * ghost layers, the face arrays (alpha+, alpha-, u*) of both stages and dt.
+ * ctmhd_step_adjoint_tape then gives dL/dS^n from dL/dS^{n+1} as
+ * ctmhd_step_adjoint on S^n would (bitwise the same result), reading that
+ * tape instead of recomputing it.
+ *   tape       : device, >= ctmhd_tape_bytes() bytes, 256-byte aligned,
+ *                caller-owned; one per recorded step that is to be reversed
+ *   dt         : device, one double (> 0, finite; a non-finite dt leaves the
+ *                state unchanged and makes the adjoint write NaN), or NULL
+ *                for the CFL dt of S^n (eq. resistivity:cfl); the tape holds
+ *                the dt used, as the double at byte offset
+ *                ctmhd_tape_bytes() - 256
+ *   workspace  : ctmhd_step_record: >= ctmhd_workspace_bytes(p, box, 1);
+ *                ctmhd_step_adjoint_tape: >= ctmhd_adjoint_workspace_bytes()
+ * Configurations as ctmhd_step_adjoint (FP64 form; any reconstruction,
+ * Riemann solver and EMF scheme); others return CTMHD_EUNSUPPORTED, and
+ * ctmhd_tape_bytes returns 0 for them. */
+size_t ctmhd_tape_bytes(const ctmhd_params* p, const ctmhd_box* box);
+int ctmhd_step_record(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
+                      double* const bface[3], const double* dt, void* tape, size_t tape_bytes,
+                      void* workspace, size_t ws_bytes, void* stream);
+int ctmhd_step_adjoint_tape(const ctmhd_params* p, const ctmhd_box* box, const void* tape,
+                            size_t tape_bytes, const double* const g_cons[5],
+                            const double* const g_bface[3], double* const g_cons_out[5],
+                            double* const g_bface_out[3], void* workspace, size_t ws_bytes,
+                            void* stream);
+
 /* Kernel timing hook (for benchmarks).  `events` holds 2*npairs hipEvent_t
  * handles created by the caller (timing enabled).  During subsequent
  * ctmhd_step calls in this process the library records pair i

@@ -872,28 +872,27 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   return CTMHD_OK;
 }
 
-template <int RECON, int RIEMANN, int EMF>
-int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* const cons_n[5],
-                const double* const bface_n[3], const double* dt, const double* const g_cons[5],
-                const double* const g_bface[3], double* const g_cons_out[5],
-                double* const g_bface_out[3], void* ws, size_t ws_bytes, hipStream_t st) {
-  ctmhd_params pp = *p_in;
-  pp.fofc = 0;  // the differentiated step takes no flux correction
-  const ctmhd_params* p = &pp;
-  const Geom G = make_geom(*box);
-  if (!ws || ws_bytes < adj_ws_bytes(p, *box)) return fail(CTMHD_EARG, "workspace too small");
-  Work<double> W;
-  State A, H;
-  int rc = build_work<double>(p, ws, ws_bytes, *box, W, A, H);
+// Everything an adjoint step works in, carved from the caller's workspace.
+struct AdjCtx {
+  Work<double> W, W0;  // forward work arrays; W0: W with the face arrays of S0
+  State A, H;          // S0 with ghosts, S1 (the recomputing form)
+  State V, G1;         // stage-2 cotangent / g1
+  AdjArrays X;
+};
+
+template <int EMF>
+int adj_setup(const ctmhd_params* p, const ctmhd_box& box, void* ws, size_t ws_bytes, AdjCtx& C) {
+  const Geom G = make_geom(box);
+  if (!ws || ws_bytes < adj_ws_bytes(p, box)) return fail(CTMHD_EARG, "workspace too small");
+  int rc = build_work<double>(p, ws, ws_bytes, box, C.W, C.A, C.H);
   if (rc) return rc;
   const size_t e = (size_t)G.elems;
-  Carve cv{(char*)ws + box_ws_bytes(*box, 8, p->emf_compute)};
-  State V, G1;
-  AdjArrays X;
-  for (int m = 0; m < 5; ++m) V.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) V.b[a] = cv.take<double>(e);
-  for (int m = 0; m < 5; ++m) G1.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) G1.b[a] = cv.take<double>(e);
+  Carve cv{(char*)ws + box_ws_bytes(box, 8, p->emf_compute)};
+  AdjArrays& X = C.X;
+  for (int m = 0; m < 5; ++m) C.V.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) C.V.b[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) C.G1.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) C.G1.b[a] = cv.take<double>(e);
   for (int v = 0; v < 8; ++v) X.prim[v] = cv.take<double>(e);
   for (int c = 0; c < 3; ++c)
     for (int q = 0; q < 13; ++q) X.ea[c][q] = cv.take<double>(e);
@@ -914,27 +913,16 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
         }
   }
   for (int c = 0; c < 3; ++c) X.eb[c] = NF ? cv.take<double>(e) : nullptr;
-  Work<double> W0 = W;  // W with the face arrays of S0 (saved after its face pass)
+  C.W0 = C.W;
   for (int a = 0; a < 3; ++a) {
-    W0.ap[a] = cv.take<double>(e);
-    W0.am[a] = cv.take<double>(e);
-    W0.us[a] = cv.take<double>(e);
+    C.W0.ap[a] = cv.take<double>(e);
+    C.W0.am[a] = cv.take<double>(e);
+    C.W0.us[a] = cv.take<double>(e);
   }
+  return CTMHD_OK;
+}
 
-  State S0, Gin, Gout;
-  for (int m = 0; m < 5; ++m) {
-    S0.c[m] = const_cast<double*>(cons_n[m]);
-    Gin.c[m] = const_cast<double*>(g_cons[m]);
-    Gout.c[m] = g_cons_out[m];
-  }
-  for (int a = 0; a < 3; ++a) {
-    S0.b[a] = const_cast<double*>(bface_n[a]);
-    Gin.b[a] = const_cast<double*>(g_bface[a]);
-    Gout.b[a] = g_bface_out[a];
-  }
-  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
-  const int ninter = G.n[0] * G.n[1] * G.n[2];
-  const int nb = nblocks(G.elems);
+UpdateCfg adj_update_cfg(const ctmhd_params* p) {
   UpdateCfg U;
   U.fofc = 0;
   U.crit = p->flag_criteria;
@@ -942,30 +930,184 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   U.sres = 0.0;
   U.force = nullptr;
   U.flag_storage = 0;
+  return U;
+}
 
-  // forward: S0 with ghosts, the caller's dt, stage 1 into H = S1
+// Both VJPs of the step and the folds, given S0 (A) and S1 (H) with ghosts
+// and the forward face arrays of S1 (in W1) and of S0 (in W0); W1.dt holds dt.
+template <int RECON, int RIEMANN, int EMF>
+int adj_reverse(hipStream_t st, const ctmhd_params* p, const Geom& G, AdjCtx& C,
+                const Work<double>& W1, const Work<double>& W0, State A, State H, State Gin,
+                State Gout) {
+  const int nb = nblocks(G.elems);
+  AdjArrays& X = C.X;
+  int rc;
+  // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
+  LAUNCH(k_adj_load, nb, G, C.V, Gin, 0.5, W1.stop);
+  for (int m = 0; m < 5; ++m) X.v[m] = C.V.c[m];
+  for (int a = 0; a < 3; ++a) X.v[5 + a] = C.V.b[a];
+  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, H, G, W1, X))) return rc;
+  LAUNCH(k_adj_fold, nb, G, C.G1, Gin, 0.5, Gin, 0.0, X, W1.stop);
+  // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
+  for (int m = 0; m < 5; ++m) X.v[m] = C.G1.c[m];
+  for (int a = 0; a < 3; ++a) X.v[5 + a] = C.G1.b[a];
+  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, A, G, W0, X))) return rc;
+  LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, C.G1, 1.0, X, W1.stop);
+  return CTMHD_OK;
+}
+
+// The tape of one recorded step: S0 and S1 with ghosts, the face arrays
+// (alpha+, alpha-, u*) of S0 and of S1, and dt.
+struct Tape {
+  State S0, S1;
+  double* ap[2][3];
+  double* am[2][3];
+  double* us[2][3];
+  double* dt;
+};
+constexpr int kTapeArrays = 8 + 8 + 18;
+
+size_t tape_bytes_of(const ctmhd_box& b) {
+  size_t e = 1;
+  for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
+  return (size_t)kTapeArrays * align256(e * 8) + 256;
+}
+
+Tape carve_tape(void* tape, const Geom& G) {
+  Tape T;
+  Carve cv{(char*)tape};
+  const size_t e = (size_t)G.elems;
+  for (int m = 0; m < 5; ++m) T.S0.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) T.S0.b[a] = cv.take<double>(e);
+  for (int m = 0; m < 5; ++m) T.S1.c[m] = cv.take<double>(e);
+  for (int a = 0; a < 3; ++a) T.S1.b[a] = cv.take<double>(e);
+  for (int k = 0; k < 2; ++k)
+    for (int a = 0; a < 3; ++a) {
+      T.ap[k][a] = cv.take<double>(e);
+      T.am[k][a] = cv.take<double>(e);
+      T.us[k][a] = cv.take<double>(e);
+    }
+  T.dt = cv.take<double>(1);
+  return T;
+}
+
+Work<double> with_face_arrays(const Work<double>& W, const Tape& T, int k) {
+  Work<double> R = W;
+  for (int a = 0; a < 3; ++a) {
+    R.ap[a] = T.ap[k][a];
+    R.am[a] = T.am[k][a];
+    R.us[a] = T.us[k][a];
+  }
+  return R;
+}
+
+template <int RECON, int RIEMANN, int EMF>
+int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* const cons_n[5],
+                const double* const bface_n[3], const double* dt, const double* const g_cons[5],
+                const double* const g_bface[3], double* const g_cons_out[5],
+                double* const g_bface_out[3], const void* tape, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+  ctmhd_params pp = *p_in;
+  pp.fofc = 0;  // the differentiated step takes no flux correction
+  const ctmhd_params* p = &pp;
+  const Geom G = make_geom(*box);
+  AdjCtx C;
+  int rc = adj_setup<EMF>(p, *box, ws, ws_bytes, C);
+  if (rc) return rc;
+  Work<double>& W = C.W;
+  State Gin, Gout;
+  for (int m = 0; m < 5; ++m) {
+    Gin.c[m] = const_cast<double*>(g_cons[m]);
+    Gout.c[m] = g_cons_out[m];
+  }
+  for (int a = 0; a < 3; ++a) {
+    Gin.b[a] = const_cast<double*>(g_bface[a]);
+    Gout.b[a] = g_bface_out[a];
+  }
   LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
+  if (tape) {
+    // everything the reverse needs was recorded by ctmhd_step_record
+    const Tape T = carve_tape(const_cast<void*>(tape), G);
+    LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, T.dt, W.dt, (double*)nullptr, W.stop,
+           (long long*)nullptr);
+    return adj_reverse<RECON, RIEMANN, EMF>(st, p, G, C, with_face_arrays(W, T, 1),
+                                            with_face_arrays(C.W0, T, 0), T.S0, T.S1, Gin, Gout);
+  }
+  State S0;
+  for (int m = 0; m < 5; ++m) S0.c[m] = const_cast<double*>(cons_n[m]);
+  for (int a = 0; a < 3; ++a) S0.b[a] = const_cast<double*>(bface_n[a]);
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
+  const int ninter = G.n[0] * G.n[1] * G.n[2];
+  const int nb = nblocks(G.elems);
+  const UpdateCfg U = adj_update_cfg(p);
+  State A = C.A, H = C.H;
+  // forward: S0 with ghosts, the caller's dt, stage 1 into H = S1
   LAUNCH(k_copy, nb, A, S0, G.elems, (const int*)nullptr);
   LAUNCH(k_wrap, nb, A, G, W.stop);
   LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, (double*)nullptr, W.stop,
          (long long*)nullptr);
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
-  LAUNCH(k_adj_save9, nb, G, W, W0);
+  LAUNCH(k_adj_save9, nb, G, W, C.W0);
   if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, A, G, W, p->gamma, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
-  // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
   if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
-  LAUNCH(k_adj_load, nb, G, V, Gin, 0.5, W.stop);
-  for (int m = 0; m < 5; ++m) X.v[m] = V.c[m];
-  for (int a = 0; a < 3; ++a) X.v[5 + a] = V.b[a];
-  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, H, G, W, X))) return rc;
-  LAUNCH(k_adj_fold, nb, G, G1, Gin, 0.5, Gin, 0.0, X, W.stop);
-  // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
-  for (int m = 0; m < 5; ++m) X.v[m] = G1.c[m];
-  for (int a = 0; a < 3; ++a) X.v[5 + a] = G1.b[a];
-  if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, A, G, W0, X))) return rc;
-  LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, G1, 1.0, X, W.stop);
+  return adj_reverse<RECON, RIEMANN, EMF>(st, p, G, C, W, C.W0, A, H, Gin, Gout);
+}
+
+// One forward step (frozen dt, no flux correction) that records its tape:
+// S0 and S1 with ghosts and the face arrays of both stages go to the tape,
+// S^{n+1} to the caller's arrays.  The same kernels and arithmetic as
+// ctmhd_step.
+template <int RECON>
+int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const cons[5],
+               double* const bface[3], const double* dt, void* tape, void* ws, size_t ws_bytes,
+               hipStream_t st) {
+  ctmhd_params pp = *p_in;
+  pp.fofc = 0;
+  const ctmhd_params* p = &pp;
+  const Geom G = make_geom(*box);
+  Work<double> W;
+  State A_unused, H_unused;
+  int rc = build_work<double>(p, ws, ws_bytes, *box, W, A_unused, H_unused);
+  if (rc) return rc;
+  const Tape T = carve_tape(tape, G);
+  State user;
+  for (int m = 0; m < 5; ++m) user.c[m] = cons[m];
+  for (int a = 0; a < 3; ++a) user.b[a] = bface[a];
+  const FacePlan FP = make_face_plan(G, p->recon, p->emf_compute, tile_chunk(p), tile_xrows(p));
+  const int ninter = G.n[0] * G.n[1] * G.n[2];
+  const int nb = nblocks(G.elems);
+  const UpdateCfg U = adj_update_cfg(p);
+  const Work<double> W0 = with_face_arrays(W, T, 0), W1 = with_face_arrays(W, T, 1);
+  LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
+  LAUNCH(k_copy, nb, T.S0, user, G.elems, (const int*)nullptr);
+  LAUNCH(k_wrap, nb, T.S0, G, W.stop);
+  if (!dt) {  // the CFL dt of S^n, as ctmhd_step computes it
+    const double dxmin = fmin(G.dx[0], fmin(G.dx[1], G.dx[2]));
+    const double sres = p->eta > 0.0 ? 2.0 * p->eta / (dxmin * dxmin) : 0.0;
+    int dtb = nblocks(ninter);
+    if (dtb > 2048) dtb = 2048;
+    LAUNCH(k_dt, dtb, T.S0, G, p->gamma, sres, W.smax, W.stop);
+  }
+  LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, T.dt, W.stop, (long long*)nullptr);
+  if (p->emf_compute == CTMHD_EMF_B25A)
+    LAUNCH((k_prim<double, kB25A>), nb, T.S0, G, W0, p->gamma, W.stop);
+  else if (p->emf_compute == CTMHD_EMF_FS18)
+    LAUNCH((k_prim<double, kFS18>), nb, T.S0, G, W0, p->gamma, W.stop);
+  if ((rc = launch_faces<double, RECON>(st, p, T.S0, G, W0, FP, 0, nullptr))) return rc;
+  if ((rc = launch_emf<double, RECON>(st, p, T.S0, G, W0, 0))) return rc;
+  LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S0, T.S1, G, W0, 0, 0, U,
+         (long long*)nullptr, W.stop);
+  if (p->emf_compute == CTMHD_EMF_B25A)
+    LAUNCH((k_prim<double, kB25A>), nb, T.S1, G, W1, p->gamma, W.stop);
+  else if (p->emf_compute == CTMHD_EMF_FS18)
+    LAUNCH((k_prim<double, kFS18>), nb, T.S1, G, W1, p->gamma, W.stop);
+  if ((rc = launch_faces<double, RECON>(st, p, T.S1, G, W1, FP, 1, nullptr))) return rc;
+  if ((rc = launch_emf<double, RECON>(st, p, T.S1, G, W1, 1))) return rc;
+  // a stopped step (non-finite dt) leaves the caller's state as it was
+  LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S1, user, G, W1, 1, 0, U,
+         (long long*)nullptr, W.stop);
   return CTMHD_OK;
 }
 
@@ -973,16 +1115,48 @@ template <int RECON>
 int adjoint_riemann(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],
                     const double* const bface_n[3], const double* dt,
                     const double* const g_cons[5], const double* const g_bface[3],
-                    double* const g_cons_out[5], double* const g_bface_out[3], void* ws,
-                    size_t ws_bytes, hipStream_t st) {
+                    double* const g_cons_out[5], double* const g_bface_out[3], const void* tape,
+                    void* ws, size_t ws_bytes, hipStream_t st) {
 #define CTMHD_ADJ(RI, EM) \
-  adjoint_box<RECON, RI, EM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out, g_bface_out, ws, ws_bytes, st)
+  adjoint_box<RECON, RI, EM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out, g_bface_out, tape, ws, ws_bytes, st)
   if (p->emf_compute == CTMHD_EMF_B25A)
     return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kB25A) : CTMHD_ADJ(kLLF, kB25A);
   if (p->emf_compute == CTMHD_EMF_FS18)
     return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kFS18) : CTMHD_ADJ(kLLF, kFS18);
   return p->riemann == CTMHD_RIEMANN_HLLD ? CTMHD_ADJ(kHLLD, kQ26) : CTMHD_ADJ(kLLF, kQ26);
 #undef CTMHD_ADJ
+}
+
+int adjoint_dispatch(const ctmhd_params* p, const ctmhd_box* box, const double* const cons_n[5],
+                     const double* const bface_n[3], const double* dt,
+                     const double* const g_cons[5], const double* const g_bface[3],
+                     double* const g_cons_out[5], double* const g_bface_out[3], const void* tape,
+                     void* ws, size_t ws_bytes, hipStream_t st) {
+  switch (p->recon) {
+    case CTMHD_RECON_PC:
+      return adjoint_riemann<kPC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                  g_bface_out, tape, ws, ws_bytes, st);
+    case CTMHD_RECON_PLM_MC:
+      return adjoint_riemann<kPLM_MC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                      g_bface_out, tape, ws, ws_bytes, st);
+    case CTMHD_RECON_PLM_MINMOD:
+      return adjoint_riemann<kPLM_MM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                      g_bface_out, tape, ws, ws_bytes, st);
+    default:
+      return adjoint_riemann<kPPM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
+                                   g_bface_out, tape, ws, ws_bytes, st);
+  }
+}
+
+int check_gradients(const double* const g_cons[5], const double* const g_bface[3],
+                    double* const g_cons_out[5], double* const g_bface_out[3]) {
+  if (!g_cons || !g_bface || !g_cons_out || !g_bface_out)
+    return fail(CTMHD_EARG, "a pointer argument is NULL");
+  for (int m = 0; m < 5; ++m)
+    if (!g_cons[m] || !g_cons_out[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!g_bface[a] || !g_bface_out[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
+  return CTMHD_OK;
 }
 
 }  // namespace
@@ -1004,29 +1178,69 @@ int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box, const double
   if (rc) return rc;
   if ((rc = check_adjoint(p))) return rc;
   if ((rc = check_box(p, box))) return rc;
-  if (!cons_n || !bface_n || !g_cons || !g_bface || !g_cons_out || !g_bface_out || !dt)
-    return fail(CTMHD_EARG, "a pointer argument is NULL");
+  if (!cons_n || !bface_n || !dt) return fail(CTMHD_EARG, "a pointer argument is NULL");
+  if ((rc = check_gradients(g_cons, g_bface, g_cons_out, g_bface_out))) return rc;
   for (int m = 0; m < 5; ++m)
-    if (!cons_n[m] || !g_cons[m] || !g_cons_out[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
+    if (!cons_n[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
   for (int a = 0; a < 3; ++a)
-    if (!bface_n[a] || !g_bface[a] || !g_bface_out[a])
-      return fail(CTMHD_EARG, "a bface pointer is NULL");
+    if (!bface_n[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
+  return adjoint_dispatch(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out, g_bface_out,
+                          nullptr, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+size_t ctmhd_tape_bytes(const ctmhd_params* p, const ctmhd_box* box) {
+  if (check_params(p) || check_adjoint(p) || check_box(p, box)) return 0;
+  return tape_bytes_of(*box);
+}
+
+int ctmhd_step_record(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
+                      double* const bface[3], const double* dt, void* tape, size_t tape_bytes,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_adjoint(p))) return rc;
+  if ((rc = check_box(p, box))) return rc;
+  if (!cons || !bface) return fail(CTMHD_EARG, "a pointer argument is NULL");
+  for (int m = 0; m < 5; ++m)
+    if (!cons[m]) return fail(CTMHD_EARG, "a cons pointer is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!bface[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
+  if (!tape || tape_bytes < tape_bytes_of(*box)) return fail(CTMHD_EARG, "tape too small");
+  if (((uintptr_t)tape & 255) != 0) return fail(CTMHD_EARG, "tape must be 256-byte aligned");
+  if (!workspace || ws_bytes < box_ws_bytes(*box, 8, p->emf_compute))
+    return fail(CTMHD_EARG, "workspace too small");
   if (((uintptr_t)workspace & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   switch (p->recon) {
     case CTMHD_RECON_PC:
-      return adjoint_riemann<kPC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                  g_bface_out, workspace, ws_bytes, st);
+      return record_box<kPC>(p, box, cons, bface, dt, tape, workspace, ws_bytes, st);
     case CTMHD_RECON_PLM_MC:
-      return adjoint_riemann<kPLM_MC>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                      g_bface_out, workspace, ws_bytes, st);
+      return record_box<kPLM_MC>(p, box, cons, bface, dt, tape, workspace, ws_bytes, st);
     case CTMHD_RECON_PLM_MINMOD:
-      return adjoint_riemann<kPLM_MM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                      g_bface_out, workspace, ws_bytes, st);
+      return record_box<kPLM_MM>(p, box, cons, bface, dt, tape, workspace, ws_bytes, st);
     default:
-      return adjoint_riemann<kPPM>(p, box, cons_n, bface_n, dt, g_cons, g_bface, g_cons_out,
-                                   g_bface_out, workspace, ws_bytes, st);
+      return record_box<kPPM>(p, box, cons, bface, dt, tape, workspace, ws_bytes, st);
   }
+}
+
+int ctmhd_step_adjoint_tape(const ctmhd_params* p, const ctmhd_box* box, const void* tape,
+                            size_t tape_bytes, const double* const g_cons[5],
+                            const double* const g_bface[3], double* const g_cons_out[5],
+                            double* const g_bface_out[3], void* workspace, size_t ws_bytes,
+                            void* stream) {
+  g_err[0] = 0;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_adjoint(p))) return rc;
+  if ((rc = check_box(p, box))) return rc;
+  if ((rc = check_gradients(g_cons, g_bface, g_cons_out, g_bface_out))) return rc;
+  if (!tape || tape_bytes < tape_bytes_of(*box)) return fail(CTMHD_EARG, "tape too small");
+  if (((uintptr_t)tape & 255) != 0) return fail(CTMHD_EARG, "tape must be 256-byte aligned");
+  if (((uintptr_t)workspace & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
+  return adjoint_dispatch(p, box, nullptr, nullptr, nullptr, g_cons, g_bface, g_cons_out,
+                          g_bface_out, tape, workspace, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -82,6 +82,14 @@ def lib():
         L.ctmhd_step_adjoint.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _PTR5, _PTR3, _PTR5, _PTR3,
                                          _vp, ctypes.c_size_t, _vp]
         L.ctmhd_step_adjoint.restype = ctypes.c_int
+        L.ctmhd_tape_bytes.argtypes = [_P, _B]
+        L.ctmhd_tape_bytes.restype = ctypes.c_size_t
+        L.ctmhd_step_record.argtypes = [_P, _B, _PTR5, _PTR3, _vp, _vp, ctypes.c_size_t, _vp,
+                                        ctypes.c_size_t, _vp]
+        L.ctmhd_step_record.restype = ctypes.c_int
+        L.ctmhd_step_adjoint_tape.argtypes = [_P, _B, _vp, ctypes.c_size_t, _PTR5, _PTR3, _PTR5,
+                                              _PTR3, _vp, ctypes.c_size_t, _vp]
+        L.ctmhd_step_adjoint_tape.restype = ctypes.c_int
         L.ctmhd_adjoint_workspace_bytes.argtypes = [_P, _B]
         L.ctmhd_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.ctmhd_profile_events.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
@@ -97,7 +105,8 @@ def lib():
 EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes", "ctmhd_step",
             "ctmhd_batch_plan_bytes", "ctmhd_batch_plan", "ctmhd_step_batched",
             "ctmhd_level_plan_bytes", "ctmhd_level_plan", "ctmhd_step_level",
-            "ctmhd_step_adjoint", "ctmhd_adjoint_workspace_bytes", "ctmhd_profile_events",
+            "ctmhd_step_adjoint", "ctmhd_tape_bytes", "ctmhd_step_record",
+            "ctmhd_step_adjoint_tape", "ctmhd_adjoint_workspace_bytes", "ctmhd_profile_events",
             "ctmhd_profile_recorded", "ctmhd_last_error")
 
 
@@ -235,6 +244,29 @@ def ctmhd_step_adjoint(params: Params, box: Box, cons_n, bface_n, dt, g_cons, g_
                                   _PTR5(*[_p(t) for t in g_cons_out]),
                                   _PTR3(*[_p(t) for t in g_bface_out]), _p(ws),
                                   ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+def tape_bytes(params: Params, box: Box) -> int:
+    return int(lib().ctmhd_tape_bytes(ctypes.byref(params), ctypes.byref(box)))
+
+
+def ctmhd_step_record(params: Params, box: Box, cons, bface, dt, tape, workspace, stream=None):
+    rc = lib().ctmhd_step_record(ctypes.byref(params), ctypes.byref(box),
+                                 _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
+                                 _p(dt), _p(tape), tape.numel(), _p(workspace), workspace.numel(),
+                                 _stream(stream))
+    return _check(rc)
+
+
+def ctmhd_step_adjoint_tape(params: Params, box: Box, tape, g_cons, g_bface, g_cons_out,
+                            g_bface_out, workspace, stream=None):
+    rc = lib().ctmhd_step_adjoint_tape(ctypes.byref(params), ctypes.byref(box), _p(tape),
+                                       tape.numel(), _PTR5(*[_p(t) for t in g_cons]),
+                                       _PTR3(*[_p(t) for t in g_bface]),
+                                       _PTR5(*[_p(t) for t in g_cons_out]),
+                                       _PTR3(*[_p(t) for t in g_bface_out]), _p(workspace),
+                                       workspace.numel(), _stream(stream))
     return _check(rc)
 
 

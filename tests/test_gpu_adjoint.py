@@ -315,3 +315,88 @@ def test_rollout_fp32_form_gradient():
     rel = float((grads["fp32"] - grads["fp64"]).norm() / grads["fp64"].norm())
     print(f"[rollout] FP32-form gradient vs FP64: relative L2 difference {rel:.2e}", flush=True)
     assert rel <= 1e-4
+
+
+TAPE_CONFIGS = [("plm", "hlld", 0.0, "q26"), ("ppm", "hlld", 1e-3, "b25a"),
+                ("pc", "llf", 0.0, "fs18"), ("plm_minmod", "hlld", 1e-3, "q26")]
+
+
+def _tape_setup(recon, riemann, eta, emf):
+    import torch
+    cons, bf, dx = _state()
+    P = ctmhd.make_params(recon=recon, riemann=riemann, eta=eta, emf=emf, fofc=False)
+    Q = oracle.make_params(recon=recon, riemann=riemann, eta=eta, emf=emf, fofc=False)
+    dt = 0.5 * oracle.cfl_dt(Q, cons, bf, dx)
+    ng = ctmhd.required_ghosts(P)
+    S = ctmhd.BoxState.from_numpy(cons, bf, ng, dx)
+    tape = torch.empty(ctmhd.tape_bytes(P, S.box), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ctmhd.workspace_bytes(P, S.box), dtype=torch.uint8, device="cuda")
+    return P, cons, bf, dx, dt, S, tape, ws
+
+
+@pytest.mark.parametrize("recon,riemann,eta,emf", TAPE_CONFIGS)
+def test_recorded_step_is_the_plain_step(recon, riemann, eta, emf):
+    """ctmhd_step_record advances the state bitwise as ctmhd_step (one step,
+    the same frozen dt, no flux correction); without a dt it takes the CFL dt
+    of ctmhd_step and keeps it in the tape."""
+    import torch
+    P, cons, bf, dx, dt, S, tape, ws = _tape_setup(recon, riemann, eta, emf)
+    dtt = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ctmhd.ctmhd_step_record(P, S.box, S.cons, S.bface, dtt, tape, ws)
+    torch.cuda.synchronize()
+    rc, rb = S.to_numpy()
+    pc_, pb_, _, _ = ctmhd.run(P, cons, bf, dx, 1, dt_fixed=[dt])
+    assert np.array_equal(rc, pc_) and np.array_equal(rb, pb_)
+    # CFL dt
+    S2 = ctmhd.BoxState.from_numpy(cons, bf, S.ng, dx)
+    ctmhd.ctmhd_step_record(P, S2.box, S2.cons, S2.bface, None, tape, ws)
+    torch.cuda.synchronize()
+    c2, b2 = S2.to_numpy()
+    c3, b3, dts, _ = ctmhd.run(P, cons, bf, dx, 1)
+    tdt = float(tape[-256:-248].view(torch.float64).item())
+    assert tdt == float(np.asarray(dts).reshape(-1)[0])
+    assert np.array_equal(c2, c3) and np.array_equal(b2, b3)
+
+
+@pytest.mark.parametrize("recon,riemann,eta,emf", TAPE_CONFIGS)
+def test_adjoint_from_tape_is_the_adjoint(recon, riemann, eta, emf):
+    """ctmhd_step_adjoint_tape on a recorded step gives the result of
+    ctmhd_step_adjoint at S^n (bitwise without resistivity; the Ohmic adjoint
+    terms accumulate with atomics in no fixed order)."""
+    import torch
+    P, cons, bf, dx, dt, S, tape, ws = _tape_setup(recon, riemann, eta, emf)
+    rng = np.random.default_rng(3)
+    gc = rng.standard_normal(cons.shape)
+    gb = rng.standard_normal(bf.shape)
+    ac, ab = adjoint(P, cons, bf, dx, dt, gc, gb)
+    dtt = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ctmhd.ctmhd_step_record(P, S.box, S.cons, S.bface, dtt, tape, ws)
+    G = ctmhd.BoxState.from_numpy(gc, gb, S.ng, dx)
+    O = ctmhd.BoxState(S.n, S.ng, dx)
+    aws = torch.empty(ctmhd.adjoint_workspace_bytes(P, S.box), dtype=torch.uint8, device="cuda")
+    ctmhd.ctmhd_step_adjoint_tape(P, S.box, tape, G.cons, G.bface, O.cons, O.bface, aws)
+    torch.cuda.synchronize()
+    tc, tb = O.to_numpy()
+    if eta == 0.0:
+        assert np.array_equal(tc, ac) and np.array_equal(tb, ab)
+    else:
+        scale = max(np.abs(ac).max(), np.abs(ab).max())
+        assert max(np.abs(tc - ac).max(), np.abs(tb - ab).max()) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("recon", ["plm", "ppm"])
+def test_rollout_with_tapes_equals_checkpoints(recon):
+    """The 6-step kinetic-energy gradient through recorded tapes equals the
+    one through checkpoints every 2 steps, bitwise."""
+    import torch
+    from paper_2609_10816_amd import autograd as ad
+    rho, u0, p, b0, dx = _rollout_inputs()
+    P = ctmhd.make_params(recon=recon, riemann="hlld", eta=0.0, fofc=False)
+    grads = []
+    for kw in (dict(every=2), dict(tape=True)):
+        u = u0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        c, _ = ad.rollout(ad.conserved_from_primitives(rho, u, p, b), b, P, dx, 6, **kw)
+        ad.kinetic_energy(c, dx).backward()
+        grads.append((u.grad.clone(), b.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
