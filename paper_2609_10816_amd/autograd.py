@@ -79,14 +79,19 @@ class _Box:
         ctmhd.ctmhd_step_record(self.adj_params, self.state.box, self.state.cons,
                                 self.state.bface, dt_fixed, tape, self.rec_ws)
 
-    def adjoint_tape(self, tape, gc, gb):
-        """dL/dS^n of a recorded step given dL/dS^{n+1} (interior tensors)."""
+    def reverse_tapes(self, tapes, gc, gb):
+        """dL/dS^0 of the recorded steps tapes[0..] given dL/dS^N (interior
+        tensors).  The output of one step is the input of the next one back
+        (the adjoint reads interior values only), so the two cotangent
+        buffers alternate without copies."""
         self.gin_buf[(slice(0, 5),) + self.sl[1:]] = gc
         self.gin_buf[(slice(5, 8),) + self.sl[1:]] = gb
-        ctmhd.ctmhd_step_adjoint_tape(self.adj_params, self.state.box, tape, self.g_in.cons,
-                                      self.g_in.bface, self.g_out.cons, self.g_out.bface,
-                                      self.adj_ws)
-        v = self.gout_buf[self.sl]
+        src, dst = (self.g_in, self.gin_buf), (self.g_out, self.gout_buf)
+        for tape in reversed(tapes):
+            ctmhd.ctmhd_step_adjoint_tape(self.adj_params, self.state.box, tape, src[0].cons,
+                                          src[0].bface, dst[0].cons, dst[0].bface, self.adj_ws)
+            src, dst = dst, src
+        v = src[1][self.sl]
         return v[:5].clone(), v[5:].clone()
 
     def load(self, cons, bface):
@@ -156,9 +161,7 @@ class _Rollout(torch.autograd.Function):
         gc = gc.contiguous() if gc is not None else torch.zeros_like(box.interior()[0])
         gb = gb.contiguous() if gb is not None else torch.zeros_like(box.interior()[1])
         if ctx.tapes is not None:
-            for i in range(ctx.nsteps - 1, -1, -1):
-                gc, gb = box.adjoint_tape(ctx.tapes[i], gc, gb)
-            return gc, gb, None, None, None, None, None, None
+            return box.reverse_tapes(ctx.tapes, gc, gb) + (None,) * 6
         dts, every = ctx.dts, ctx.every
         nseg = len(ctx.checkpoints)
         for s in range(nseg - 1, -1, -1):
