@@ -221,9 +221,10 @@ size_t ctmhd_adjoint_workspace_bytes(const ctmhd_params* p, const ctmhd_box* box
  * (limiter cases, Riemann-fan regions, min / max selections).  Built for the
  * FP64 form with PC, PLM (MC or minmod) or PPM reconstruction, HLLD or LLF,
  * Q26, B25a or FS18 corner EMFs and LD04, eta >= 0; the FP32 form returns
- * CTMHD_EUNSUPPORTED.  A
- * non-finite dt writes NaN.  Deterministic except for the Ohmic terms (eta >
- * 0), whose face-field adjoints are accumulated with atomics. */
+ * CTMHD_EUNSUPPORTED.  A non-finite dt writes NaN.  Deterministic except for
+ * the Ohmic terms (eta > 0), whose face-field adjoints are accumulated with
+ * atomics.  The call recomputes the step's first stage; a step recorded by
+ * ctmhd_step_record is reversed without that by ctmhd_step_adjoint_tape. */
 int ctmhd_step_adjoint(const ctmhd_params* p, const ctmhd_box* box,
                        const double* const cons_n[5], const double* const bface_n[3],
                        const double* dt, const double* const g_cons[5],
