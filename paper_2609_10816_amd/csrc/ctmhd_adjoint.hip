@@ -1049,6 +1049,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   LAUNCH(k_adj_save9, nb, G, W, C.W0);
   if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, A, G, W, p->gamma, W.stop);
+  if constexpr (EMF == kB25A) LAUNCH((k_b25a_first<double, RECON>), nb, G, W, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
@@ -1091,16 +1092,20 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
     LAUNCH(k_dt, dtb, T.S0, G, p->gamma, sres, W.smax, W.stop);
   }
   LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, T.dt, W.stop, (long long*)nullptr);
-  if (p->emf_compute == CTMHD_EMF_B25A)
+  if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S0, G, W0, p->gamma, W.stop);
+    LAUNCH((k_b25a_first<double, RECON>), nb, G, W0, W.stop);
+  }
   else if (p->emf_compute == CTMHD_EMF_FS18)
     LAUNCH((k_prim<double, kFS18>), nb, T.S0, G, W0, p->gamma, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, T.S0, G, W0, FP, 0, nullptr))) return rc;
   if ((rc = launch_emf<double, RECON>(st, p, T.S0, G, W0, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S0, T.S1, G, W0, 0, 0, U,
          (long long*)nullptr, W.stop);
-  if (p->emf_compute == CTMHD_EMF_B25A)
+  if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S1, G, W1, p->gamma, W.stop);
+    LAUNCH((k_b25a_first<double, RECON>), nb, G, W1, W.stop);
+  }
   else if (p->emf_compute == CTMHD_EMF_FS18)
     LAUNCH((k_prim<double, kFS18>), nb, T.S1, G, W1, p->gamma, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, T.S1, G, W1, FP, 1, nullptr))) return rc;

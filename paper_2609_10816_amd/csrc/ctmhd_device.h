@@ -76,6 +76,10 @@ template <typename T>
 struct Work {
   T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2 (B25a / FS18 only)
   T* ecell[3];      // cell-centred ideal EMF (B25a)
+  // B25a: the first step of the two-step reconstructions of ecell[c] (order
+  // 0 along a = c+1 first, order 1 along b = c+2 first), the values on both
+  // sides (0 lower, 1 upper) of the interface at each position
+  T* b25f[3][2][2];
   T* F[2][3][5];    // per stage, direction, component (global momentum order)
   T* ap[3];
   T* am[3];
@@ -644,6 +648,52 @@ __device__ __forceinline__ void two_step(const T* A, int s, int st1, int st2, T 
   out[3] = h1;  // (upper, upper)
 }
 
+// First step of the B25a two-step reconstructions at position t, for every
+// edge direction and order; 0 where the stencil leaves the box.
+template <typename T, int RECON>
+__device__ __forceinline__ void b25a_first_at(const Geom& G, const Work<T>& W, int t) {
+  if (t >= G.elems) return;
+  const int s3[3] = {t % G.N[0], (t / G.N[0]) % G.N[1], t / (G.N[0] * G.N[1])};
+  constexpr int r = recon_halfwidth(RECON);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+      T lo = T(0), hi = T(0);
+      if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
+        iface_along<RECON>(W.ecell[c], t, gstride(G, d1), lo, hi);
+      W.b25f[c][o][0][t] = lo;
+      W.b25f[c][o][1][t] = hi;
+    }
+}
+
+template <typename T, int RECON>
+__global__ void __launch_bounds__(kBlock) k_b25a_first(Geom G, Work<T> W, const int* stop) {
+  if (*stop) return;
+  b25a_first_at<T, RECON>(G, W, gidx());
+}
+
+// Second step of a two-step reconstruction from the stored first-step
+// values F[0] (lower side) and F[1] (upper side along d1), along d2 with
+// stride st2: the same values as two_step.
+template <int RECON, typename T>
+__device__ __forceinline__ void second_step(T* const F[2], int s, int st2, T out[4]) {
+  T seqlo[6], seqhi[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    seqlo[m] = stencil_uses<RECON>(m) ? F[0][s + (m - 3) * st2] : T(0);
+    seqhi[m] = stencil_uses<RECON>(m) ? F[1][s + (m - 3) * st2] : T(0);
+  }
+  T l0, l1, h0, h1;
+  recon_iface<RECON>(seqlo, l0, l1);
+  recon_iface<RECON>(seqhi, h0, h1);
+  out[0] = l0;
+  out[1] = h0;
+  out[2] = l1;
+  out[3] = h1;
+}
+
 template <typename T, int RECON, int EMF>
 __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
                                       double eta_d) {
@@ -663,8 +713,8 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
     e[3] = -uaT * bbR + ubR * baT;
   } else if (EMF == kB25A) {
     T ab[4], ba[4];
-    two_step<RECON>(W.ecell[c], s, sa, sb, ab);  // [x_a x_b]: index sa_side + 2 sb_side
-    two_step<RECON>(W.ecell[c], s, sb, sa, ba);  // [x_b x_a]: index sb_side + 2 sa_side
+    second_step<RECON>(W.b25f[c][0], s, sb, ab);  // [x_a x_b]: index sa_side + 2 sb_side
+    second_step<RECON>(W.b25f[c][1], s, sa, ba);  // [x_b x_a]: index sb_side + 2 sa_side
     e[0] = T(0.5) * (ab[0] + ba[0]);
     e[1] = T(0.5) * (ab[1] + ba[2]);
     e[2] = T(0.5) * (ab[2] + ba[1]);
@@ -1037,7 +1087,7 @@ __global__ void __launch_bounds__(kBlock)
 // layers of every box are filled from the interiors of the boxes that own
 // those cells (exchange phases after every update).
 // ---------------------------------------------------------------------------
-enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG };
+enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_B };
 constexpr int kMaxPhases = 24;
 
 // Exchange phase argument (PlanHeader::xarg): which state to fill, whether
@@ -1135,6 +1185,13 @@ __device__ __forceinline__ Work<T> shift_work(const Work<T>& W0, long long off) 
   for (int v = 0; v < 8; ++v) W.prim[v] = W0.prim[v] ? W0.prim[v] + off : nullptr;
 #pragma unroll
   for (int c = 0; c < 3; ++c) W.ecell[c] = W0.ecell[c] ? W0.ecell[c] + off : nullptr;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        W.b25f[c][o][k] = W0.b25f[c][o][k] ? W0.b25f[c][o][k] + off : nullptr;
 #pragma unroll
   for (int st = 0; st < 2; ++st)
 #pragma unroll
@@ -1241,6 +1298,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kin
     if constexpr (KIND == PH_P) {
       for (int s = 0; s < strips; ++s)
         prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
+    } else if constexpr (KIND == PH_B) {
+      for (int s = 0; s < strips; ++s)
+        b25a_first_at<T, RECON>(G, W, (tile * strips + s) * kBlock + threadIdx.x);
     } else if constexpr (KIND == PH_F) {
       int nfb = 0;
       faces_block<T, RECON, RIEMANN>(in, G, W, tb.FP, tile, stage, A.gamma, A.eta, nfb);
@@ -1366,6 +1426,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
     const int kind = P->kind[p], stage = P->stage[p];
     switch (kind) {
       case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_B: batch_item<T, RECON, RIEMANN, EMF, PH_B>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_U:

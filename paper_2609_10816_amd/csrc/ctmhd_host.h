@@ -80,7 +80,7 @@ size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, int emf) {
   size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
   size_t bytes = 0;
   bytes += 2 * 8 * align256(e * 8);           // two state buffers
-  if (emf == CTMHD_EMF_B25A) bytes += 3 * align256(e * tbytes);  // cell EMF
+  if (emf == CTMHD_EMF_B25A) bytes += (3 + 12) * align256(e * tbytes);  // cell EMF, first step
   if (emf == CTMHD_EMF_FS18) bytes += 3 * align256(e * tbytes);  // cell velocity
   bytes += 2 * 15 * align256(e * tbytes);     // fluxes, two stages
   bytes += 9 * align256(e * tbytes);          // alpha+, alpha-, u*
@@ -116,8 +116,14 @@ int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_b
   for (int a = 0; a < 3; ++a) H.b[a] = cv.take<double>(e);
   for (int v = 0; v < 8; ++v) W.prim[v] = nullptr;
   for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
-  if (prm->emf_compute == CTMHD_EMF_B25A)
+  for (int c = 0; c < 3; ++c)
+    for (int o = 0; o < 2; ++o) W.b25f[c][o][0] = W.b25f[c][o][1] = nullptr;
+  if (prm->emf_compute == CTMHD_EMF_B25A) {
     for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
+    for (int c = 0; c < 3; ++c)
+      for (int o = 0; o < 2; ++o)
+        for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
+  }
   if (prm->emf_compute == CTMHD_EMF_FS18)
     for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
   for (int st = 0; st < 2; ++st)

@@ -6,7 +6,7 @@ import pytest
 
 from paper_2609_10816_amd import ctmhd
 
-PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P = range(9)
+PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_B = range(11)
 
 
 def _boxes(seed, nbox, ng=4):
@@ -40,7 +40,8 @@ def test_plan_queue_invariants(fofc, emf, tile):
     assert d["magic"] == 0x43544D48 and d["nbox"] == len(boxes)
     kinds = d["kind"]
     step = kinds[d["range"][1][0]:d["range"][1][1]]
-    expect = ([PH_P] if emf != "q26" else []) + [PH_F, PH_E, PH_U] + ([PH_O, PH_X] if fofc else [])
+    expect = ([PH_P] if emf != "q26" else []) + ([PH_B] if emf == "b25a" else [])
+    expect += [PH_F, PH_E, PH_U] + ([PH_O, PH_X] if fofc else [])
     assert step == expect * 2
     assert kinds[d["range"][0][0]:d["range"][0][1]] == [PH_WRAP, PH_DT]
     # largest boxes first
@@ -62,7 +63,7 @@ def test_plan_queue_invariants(fofc, emf, tile):
                 ninter = b.n[0] * b.n[1] * b.n[2]
                 if kinds[p] in (PH_U, PH_O, PH_X, PH_DT):
                     assert cnt == -(-ninter // (256 * strips))
-                elif kinds[p] in (PH_P, PH_WRAP, PH_COPY):
+                elif kinds[p] in (PH_P, PH_B, PH_WRAP, PH_COPY):
                     elems = int(np.prod([v + 2 * b.ng for v in b.n]))
                     assert cnt == -(-elems // (256 * strips))
                 elif kinds[p] == PH_E:
