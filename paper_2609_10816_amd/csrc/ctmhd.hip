@@ -49,7 +49,8 @@ int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T
   int rc;
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<T, kB25A>), nblocks(G.elems), in, G, W, p->gamma, W.stop);
-    LAUNCH((k_b25a_first<T, RECON>), nblocks(G.elems), G, W, W.stop);
+    if constexpr (b25a_first_stored(RECON))
+      LAUNCH((k_b25a_first<T, RECON>), nblocks(G.elems), G, W, W.stop);
   }
   else if (p->emf_compute == CTMHD_EMF_FS18)
     LAUNCH((k_prim<T, kFS18>), nblocks(G.elems), in, G, W, p->gamma, W.stop);

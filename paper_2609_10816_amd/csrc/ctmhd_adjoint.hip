@@ -836,7 +836,7 @@ size_t adj_ws_bytes(const ctmhd_params* p, const ctmhd_box& b) {
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
   const int nf = p->emf_compute == CTMHD_EMF_FS18 ? 2 : p->emf_compute == CTMHD_EMF_B25A ? 1 : 0;
   const int n = kAdjArrays + nf * kAdjArraysPerField + (nf ? 3 : 0);
-  return box_ws_bytes(b, 8, p->emf_compute) + (size_t)n * align256(e * 8);
+  return box_ws_bytes(b, 8, p) + (size_t)n * align256(e * 8);
 }
 
 int check_adjoint(const ctmhd_params* p) {
@@ -887,7 +887,7 @@ int adj_setup(const ctmhd_params* p, const ctmhd_box& box, void* ws, size_t ws_b
   int rc = build_work<double>(p, ws, ws_bytes, box, C.W, C.A, C.H);
   if (rc) return rc;
   const size_t e = (size_t)G.elems;
-  Carve cv{(char*)ws + box_ws_bytes(box, 8, p->emf_compute)};
+  Carve cv{(char*)ws + box_ws_bytes(box, 8, p)};
   AdjArrays& X = C.X;
   for (int m = 0; m < 5; ++m) C.V.c[m] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) C.V.b[a] = cv.take<double>(e);
@@ -1049,7 +1049,8 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   LAUNCH(k_adj_save9, nb, G, W, C.W0);
   if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, A, G, W, p->gamma, W.stop);
-  if constexpr (EMF == kB25A) LAUNCH((k_b25a_first<double, RECON>), nb, G, W, W.stop);
+  if constexpr (EMF == kB25A && b25a_first_stored(RECON))
+    LAUNCH((k_b25a_first<double, RECON>), nb, G, W, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
@@ -1094,7 +1095,7 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
   LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, T.dt, W.stop, (long long*)nullptr);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S0, G, W0, p->gamma, W.stop);
-    LAUNCH((k_b25a_first<double, RECON>), nb, G, W0, W.stop);
+    if constexpr (b25a_first_stored(RECON)) LAUNCH((k_b25a_first<double, RECON>), nb, G, W0, W.stop);
   }
   else if (p->emf_compute == CTMHD_EMF_FS18)
     LAUNCH((k_prim<double, kFS18>), nb, T.S0, G, W0, p->gamma, W.stop);
@@ -1104,7 +1105,7 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
          (long long*)nullptr, W.stop);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S1, G, W1, p->gamma, W.stop);
-    LAUNCH((k_b25a_first<double, RECON>), nb, G, W1, W.stop);
+    if constexpr (b25a_first_stored(RECON)) LAUNCH((k_b25a_first<double, RECON>), nb, G, W1, W.stop);
   }
   else if (p->emf_compute == CTMHD_EMF_FS18)
     LAUNCH((k_prim<double, kFS18>), nb, T.S1, G, W1, p->gamma, W.stop);
@@ -1214,7 +1215,7 @@ int ctmhd_step_record(const ctmhd_params* p, const ctmhd_box* box, double* const
     if (!bface[a]) return fail(CTMHD_EARG, "a bface pointer is NULL");
   if (!tape || tape_bytes < tape_bytes_of(*box)) return fail(CTMHD_EARG, "tape too small");
   if (((uintptr_t)tape & 255) != 0) return fail(CTMHD_EARG, "tape must be 256-byte aligned");
-  if (!workspace || ws_bytes < box_ws_bytes(*box, 8, p->emf_compute))
+  if (!workspace || ws_bytes < box_ws_bytes(*box, 8, p))
     return fail(CTMHD_EARG, "workspace too small");
   if (((uintptr_t)workspace & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;

@@ -47,7 +47,7 @@ int plan_phases(const ctmhd_params* p, bool level, int kind[kMaxPhases], int sta
     if (p->emf_compute != CTMHD_EMF_Q26) {
       kind[n] = PH_P; stage[n++] = st;
     }
-    if (p->emf_compute == CTMHD_EMF_B25A) {
+    if (p->emf_compute == CTMHD_EMF_B25A && b25a_first_stored(p->recon)) {
       kind[n] = PH_B; stage[n++] = st;
     }
     kind[n] = PH_F; stage[n++] = st;
@@ -276,7 +276,8 @@ size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
   size_t bytes = 0;
   bytes += 2 * 8 * align256(e * 8);  // B and H states
   if (p->emf_compute != CTMHD_EMF_Q26) bytes += 3 * align256(e * tb);
-  if (p->emf_compute == CTMHD_EMF_B25A) bytes += 12 * align256(e * tb);  // first step
+  if (p->emf_compute == CTMHD_EMF_B25A && b25a_first_stored(p->recon))
+    bytes += 12 * align256(e * tb);  // B25a first-step face values
   bytes += (2 * 15 + 9 + 6) * align256(e * tb);
   bytes += align256(e);                                      // flags (packed positions)
   bytes += align256(sizeof(int) * (size_t)nphase * nbox);    // done
@@ -308,9 +309,10 @@ int batch_args(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* ws
     for (int o = 0; o < 2; ++o) W.b25f[c][o][0] = W.b25f[c][o][1] = nullptr;
   if (p->emf_compute == CTMHD_EMF_B25A) {
     for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-    for (int c = 0; c < 3; ++c)
-      for (int o = 0; o < 2; ++o)
-        for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
+    if (b25a_first_stored(p->recon))
+      for (int c = 0; c < 3; ++c)
+        for (int o = 0; o < 2; ++o)
+          for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
   }
   if (p->emf_compute == CTMHD_EMF_FS18)
     for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
@@ -637,7 +639,7 @@ size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int 
   size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
   // one box: enough for either entry point
   if (nbox == 1) {
-    const size_t one = box_ws_bytes(boxes[0], tb, p->emf_compute);
+    const size_t one = box_ws_bytes(boxes[0], tb, p);
     if (check_boxes(p, boxes, 1)) return one;
     const size_t bat = batch_ws_bytes(p, boxes, 1);
     return one > bat ? one : bat;

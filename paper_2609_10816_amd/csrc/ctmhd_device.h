@@ -76,9 +76,9 @@ template <typename T>
 struct Work {
   T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2 (B25a / FS18 only)
   T* ecell[3];      // cell-centred ideal EMF (B25a)
-  // B25a: the first step of the two-step reconstructions of ecell[c] (order
-  // 0 along a = c+1 first, order 1 along b = c+2 first), the values on both
-  // sides (0 lower, 1 upper) of the interface at each position
+  // B25a with PPM: the first step of the two-step reconstructions of
+  // ecell[c] (order 0 along a = c+1 first, order 1 along b = c+2 first), the
+  // values on both sides (0 lower, 1 upper) of the interface at each position
   T* b25f[3][2][2];
   T* F[2][3][5];    // per stage, direction, component (global momentum order)
   T* ap[3];
@@ -648,6 +648,11 @@ __device__ __forceinline__ void two_step(const T* A, int s, int st1, int st2, T 
   out[3] = h1;  // (upper, upper)
 }
 
+// Whether B25a stores the first step of its two-step reconstructions once per
+// stage (PPM) or the edge pass recomputes it for every edge (PC, PLM: there
+// the stored arrays cost more traffic than the short stencils they save).
+__host__ __device__ constexpr bool b25a_first_stored(int recon) { return recon == kPPM; }
+
 // First step of the B25a two-step reconstructions at position t, for every
 // edge direction and order; 0 where the stencil leaves the box.
 template <typename T, int RECON>
@@ -712,9 +717,14 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
     e[2] = -uaT * bbL + ubL * baT;
     e[3] = -uaT * bbR + ubR * baT;
   } else if (EMF == kB25A) {
-    T ab[4], ba[4];
-    second_step<RECON>(W.b25f[c][0], s, sb, ab);  // [x_a x_b]: index sa_side + 2 sb_side
-    second_step<RECON>(W.b25f[c][1], s, sa, ba);  // [x_b x_a]: index sb_side + 2 sa_side
+    T ab[4], ba[4];  // [x_a x_b]: index sa_side + 2 sb_side; [x_b x_a]: sb_side + 2 sa_side
+    if constexpr (b25a_first_stored(RECON)) {
+      second_step<RECON>(W.b25f[c][0], s, sb, ab);
+      second_step<RECON>(W.b25f[c][1], s, sa, ba);
+    } else {
+      two_step<RECON>(W.ecell[c], s, sa, sb, ab);
+      two_step<RECON>(W.ecell[c], s, sb, sa, ba);
+    }
     e[0] = T(0.5) * (ab[0] + ba[0]);
     e[1] = T(0.5) * (ab[1] + ba[2]);
     e[2] = T(0.5) * (ab[2] + ba[1]);

@@ -74,13 +74,16 @@ int check_box(const ctmhd_params* p, const ctmhd_box* b) {
 }
 
 // Workspace of one box for the stencil type of `tbytes` bytes.
-size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, int emf) {
+size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, const ctmhd_params* p) {
+  const int emf = p->emf_compute;
   size_t e = 1;
   for (int d = 0; d < 3; ++d) e *= (size_t)(b.n[d] + 2 * b.ng);
   size_t ninter = (size_t)b.n[0] * b.n[1] * b.n[2];
   size_t bytes = 0;
   bytes += 2 * 8 * align256(e * 8);           // two state buffers
-  if (emf == CTMHD_EMF_B25A) bytes += (3 + 12) * align256(e * tbytes);  // cell EMF, first step
+  if (emf == CTMHD_EMF_B25A) bytes += 3 * align256(e * tbytes);  // cell EMF
+  if (emf == CTMHD_EMF_B25A && b25a_first_stored(p->recon))
+    bytes += 12 * align256(e * tbytes);      // its first-step face values
   if (emf == CTMHD_EMF_FS18) bytes += 3 * align256(e * tbytes);  // cell velocity
   bytes += 2 * 15 * align256(e * tbytes);     // fluxes, two stages
   bytes += 9 * align256(e * tbytes);          // alpha+, alpha-, u*
@@ -103,7 +106,7 @@ struct Carve {
 template <typename T>
 int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_box& b, Work<T>& W,
                State& A2, State& H) {
-  size_t need = box_ws_bytes(b, sizeof(T), prm->emf_compute);
+  size_t need = box_ws_bytes(b, sizeof(T), prm);
   if (!ws || ws_bytes < need) return fail(CTMHD_EARG, "workspace too small");
   if (((uintptr_t)ws & 255) != 0) return fail(CTMHD_EARG, "workspace must be 256-byte aligned");
   size_t e = 1;
@@ -120,9 +123,10 @@ int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_b
     for (int o = 0; o < 2; ++o) W.b25f[c][o][0] = W.b25f[c][o][1] = nullptr;
   if (prm->emf_compute == CTMHD_EMF_B25A) {
     for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-    for (int c = 0; c < 3; ++c)
-      for (int o = 0; o < 2; ++o)
-        for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
+    if (b25a_first_stored(prm->recon))
+      for (int c = 0; c < 3; ++c)
+        for (int o = 0; o < 2; ++o)
+          for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
   }
   if (prm->emf_compute == CTMHD_EMF_FS18)
     for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);

@@ -88,6 +88,16 @@ def test_plan_queue_invariants(fofc, emf, tile):
                 assert last_of[(p - 1, k)] < q0
 
 
+@pytest.mark.parametrize("recon", ["pc", "plm", "plm_minmod", "ppm"])
+def test_b25a_first_step_phase_only_with_ppm(recon):
+    # B25a stores its first-step face values (a phase of their own) for PPM
+    # only; the shorter stencils recompute them in the edge pass
+    P = ctmhd.make_params(recon=recon, emf="b25a")
+    d = ctmhd.parse_plan(ctmhd.batch_plan(P, _boxes(2, 5)))
+    assert (PH_B in d["kind"]) == (recon == "ppm")
+    assert d["kind"].count(PH_P) == 2
+
+
 def test_plan_rejects_overlap_and_bad_buffers():
     P = ctmhd.make_params(recon="plm")
     b = [ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3, 0), ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3, 100)]
