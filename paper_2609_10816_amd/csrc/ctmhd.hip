@@ -49,11 +49,13 @@ int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T
   int rc;
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<T, kB25A>), nblocks(G.elems), in, G, W, p->gamma, W.stop);
-    if constexpr (b25a_first_stored(RECON))
-      LAUNCH((k_b25a_first<T, RECON>), nblocks(G.elems), G, W, W.stop);
-  }
-  else if (p->emf_compute == CTMHD_EMF_FS18)
+    if constexpr (first_step_stored(kB25A, RECON))
+      LAUNCH((k_first_step<T, RECON, kB25A>), nblocks(G.elems), G, W, W.stop);
+  } else if (p->emf_compute == CTMHD_EMF_FS18) {
     LAUNCH((k_prim<T, kFS18>), nblocks(G.elems), in, G, W, p->gamma, W.stop);
+    if constexpr (first_step_stored(kFS18, RECON))
+      LAUNCH((k_first_step<T, RECON, kFS18>), nblocks(G.elems), G, W, W.stop);
+  }
   if ((rc = launch_faces<T, RECON>(st, p, in, G, W, FP, stage, diag))) return rc;
   if ((rc = launch_emf<T, RECON>(st, p, in, G, W, stage))) return rc;
   const int ninter = G.n[0] * G.n[1] * G.n[2];

@@ -1049,8 +1049,8 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   if ((rc = launch_faces<double, RECON>(st, p, A, G, W, FP, 0, nullptr))) return rc;
   LAUNCH(k_adj_save9, nb, G, W, C.W0);
   if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, A, G, W, p->gamma, W.stop);
-  if constexpr (EMF == kB25A && b25a_first_stored(RECON))
-    LAUNCH((k_b25a_first<double, RECON>), nb, G, W, W.stop);
+  if constexpr (first_step_stored(EMF, RECON))
+    LAUNCH((k_first_step<double, RECON, EMF>), nb, G, W, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
@@ -1095,20 +1095,26 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
   LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, dt, W.dt, T.dt, W.stop, (long long*)nullptr);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S0, G, W0, p->gamma, W.stop);
-    if constexpr (b25a_first_stored(RECON)) LAUNCH((k_b25a_first<double, RECON>), nb, G, W0, W.stop);
-  }
-  else if (p->emf_compute == CTMHD_EMF_FS18)
+    if constexpr (first_step_stored(kB25A, RECON))
+      LAUNCH((k_first_step<double, RECON, kB25A>), nb, G, W0, W.stop);
+  } else if (p->emf_compute == CTMHD_EMF_FS18) {
     LAUNCH((k_prim<double, kFS18>), nb, T.S0, G, W0, p->gamma, W.stop);
+    if constexpr (first_step_stored(kFS18, RECON))
+      LAUNCH((k_first_step<double, RECON, kFS18>), nb, G, W0, W.stop);
+  }
   if ((rc = launch_faces<double, RECON>(st, p, T.S0, G, W0, FP, 0, nullptr))) return rc;
   if ((rc = launch_emf<double, RECON>(st, p, T.S0, G, W0, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S0, T.S1, G, W0, 0, 0, U,
          (long long*)nullptr, W.stop);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S1, G, W1, p->gamma, W.stop);
-    if constexpr (b25a_first_stored(RECON)) LAUNCH((k_b25a_first<double, RECON>), nb, G, W1, W.stop);
-  }
-  else if (p->emf_compute == CTMHD_EMF_FS18)
+    if constexpr (first_step_stored(kB25A, RECON))
+      LAUNCH((k_first_step<double, RECON, kB25A>), nb, G, W1, W.stop);
+  } else if (p->emf_compute == CTMHD_EMF_FS18) {
     LAUNCH((k_prim<double, kFS18>), nb, T.S1, G, W1, p->gamma, W.stop);
+    if constexpr (first_step_stored(kFS18, RECON))
+      LAUNCH((k_first_step<double, RECON, kFS18>), nb, G, W1, W.stop);
+  }
   if ((rc = launch_faces<double, RECON>(st, p, T.S1, G, W1, FP, 1, nullptr))) return rc;
   if ((rc = launch_emf<double, RECON>(st, p, T.S1, G, W1, 1))) return rc;
   // a stopped step (non-finite dt) leaves the caller's state as it was

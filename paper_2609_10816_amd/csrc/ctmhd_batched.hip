@@ -47,8 +47,8 @@ int plan_phases(const ctmhd_params* p, bool level, int kind[kMaxPhases], int sta
     if (p->emf_compute != CTMHD_EMF_Q26) {
       kind[n] = PH_P; stage[n++] = st;
     }
-    if (p->emf_compute == CTMHD_EMF_B25A && b25a_first_stored(p->recon)) {
-      kind[n] = PH_B; stage[n++] = st;
+    if (first_step_stored(p->emf_compute, p->recon)) {
+      kind[n] = PH_FIRST; stage[n++] = st;
     }
     kind[n] = PH_F; stage[n++] = st;
     kind[n] = PH_E; stage[n++] = st;
@@ -84,7 +84,7 @@ long long item_count(int kind, const Geom& G, const FacePlan& FP, long long per,
       if (level) return ((long long)(G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1) + per - 1) / per;
       return (ninter + per - 1) / per;
     case PH_P:
-    case PH_B:
+    case PH_FIRST:
     case PH_WRAP:
     case PH_COPY: return ((long long)G.elems + per - 1) / per;
     default: return ((long long)G.n[0] * G.n[1] * G.n[2] + per - 1) / per;
@@ -276,8 +276,8 @@ size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
   size_t bytes = 0;
   bytes += 2 * 8 * align256(e * 8);  // B and H states
   if (p->emf_compute != CTMHD_EMF_Q26) bytes += 3 * align256(e * tb);
-  if (p->emf_compute == CTMHD_EMF_B25A && b25a_first_stored(p->recon))
-    bytes += 12 * align256(e * tb);  // B25a first-step face values
+  if (first_step_stored(p->emf_compute, p->recon))  // stored first steps
+    bytes += (p->emf_compute == CTMHD_EMF_B25A ? 12 : 18) * align256(e * tb);
   bytes += (2 * 15 + 9 + 6) * align256(e * tb);
   bytes += align256(e);                                      // flags (packed positions)
   bytes += align256(sizeof(int) * (size_t)nphase * nbox);    // done
@@ -307,15 +307,23 @@ int batch_args(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, void* ws
   for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
   for (int c = 0; c < 3; ++c)
     for (int o = 0; o < 2; ++o) W.b25f[c][o][0] = W.b25f[c][o][1] = nullptr;
+  for (int v = 0; v < 3; ++v)
+    for (int d = 0; d < 3; ++d) W.fsf[v][d][0] = W.fsf[v][d][1] = nullptr;
+  const bool first = first_step_stored(p->emf_compute, p->recon);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-    if (b25a_first_stored(p->recon))
+    if (first)
       for (int c = 0; c < 3; ++c)
         for (int o = 0; o < 2; ++o)
           for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
   }
-  if (p->emf_compute == CTMHD_EMF_FS18)
+  if (p->emf_compute == CTMHD_EMF_FS18) {
     for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
+    if (first)
+      for (int v = 0; v < 3; ++v)
+        for (int d = 0; d < 3; ++d)
+          for (int k = 0; k < 2; ++k) W.fsf[v][d][k] = cv.take<T>(e);
+  }
   for (int st = 0; st < 2; ++st)
     for (int a = 0; a < 3; ++a)
       for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);
@@ -384,7 +392,7 @@ int launch_bphase(hipStream_t st, int kind, long long items, const BatchArgs<T>&
   const unsigned grid = (unsigned)items;
   switch (kind) {
     case PH_P: LAUNCH((k_bphase<T, kPC, kHLLD, EMF, PH_P>), grid, A, q); break;
-    case PH_B: LAUNCH((k_bphase<T, RECON, kHLLD, EMF, PH_B>), grid, A, q); break;
+    case PH_FIRST: LAUNCH((k_bphase<T, RECON, kHLLD, EMF, PH_FIRST>), grid, A, q); break;
     case PH_F: LAUNCH((k_bphase<T, RECON, RIEMANN, kQ26, PH_F>), grid, A, q); break;
     case PH_E: LAUNCH((k_bphase<T, RECON, kHLLD, EMF, PH_E>), grid, A, q); break;
     case PH_U:

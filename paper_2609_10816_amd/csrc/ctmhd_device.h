@@ -76,10 +76,12 @@ template <typename T>
 struct Work {
   T* prim[8];       // rho, u0, u1, u2, p, bc0, bc1, bc2 (B25a / FS18 only)
   T* ecell[3];      // cell-centred ideal EMF (B25a)
-  // B25a with PPM: the first step of the two-step reconstructions of
-  // ecell[c] (order 0 along a = c+1 first, order 1 along b = c+2 first), the
-  // values on both sides (0 lower, 1 upper) of the interface at each position
+  // Stored first steps of the two-step corner reconstructions (when
+  // first_step_stored), the values on both sides (0 lower, 1 upper) of the
+  // interface at each position.  B25a: ecell[c] with order 0 along a = c+1
+  // first, order 1 along b = c+2 first.  FS18: velocity u_v along axis d.
   T* b25f[3][2][2];
+  T* fsf[3][3][2];
   T* F[2][3][5];    // per stage, direction, component (global momentum order)
   T* ap[3];
   T* am[3];
@@ -648,35 +650,41 @@ __device__ __forceinline__ void two_step(const T* A, int s, int st1, int st2, T 
   out[3] = h1;  // (upper, upper)
 }
 
-// Whether B25a stores the first step of its two-step reconstructions once per
-// stage (PPM) or the edge pass recomputes it for every edge (PC, PLM: there
-// the stored arrays cost more traffic than the short stencils they save).
-__host__ __device__ constexpr bool b25a_first_stored(int recon) { return recon == kPPM; }
+// Whether the two-step corner reconstructions of B25a and FS18 store their
+// first step once per stage (PPM) or the edge pass recomputes it for every
+// edge that reads it (PC, PLM: there the stored arrays cost more traffic than
+// the short stencils they save).
+__host__ __device__ constexpr bool first_step_stored(int emf, int recon) {
+  return emf != kQ26 && recon == kPPM;
+}
 
-// First step of the B25a two-step reconstructions at position t, for every
-// edge direction and order; 0 where the stencil leaves the box.
-template <typename T, int RECON>
-__device__ __forceinline__ void b25a_first_at(const Geom& G, const Work<T>& W, int t) {
+// The first step of the two-step corner reconstructions at position t, for
+// every field and axis the edges use; 0 where the stencil leaves the box.
+template <typename T, int RECON, int EMF>
+__device__ __forceinline__ void first_step_at(const Geom& G, const Work<T>& W, int t) {
   if (t >= G.elems) return;
   const int s3[3] = {t % G.N[0], (t / G.N[0]) % G.N[1], t / (G.N[0] * G.N[1])};
   constexpr int r = recon_halfwidth(RECON);
+  constexpr int nf = EMF == kB25A ? 2 : 3;  // orders of ecell[c] / axes of u_v
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-      const int d1 = o == 0 ? (c + 1) % 3 : (c + 2) % 3;
+    for (int o = 0; o < nf; ++o) {
+      const int d1 = EMF == kB25A ? (o == 0 ? (c + 1) % 3 : (c + 2) % 3) : o;
+      const T* A = EMF == kB25A ? W.ecell[c] : W.prim[1 + c];
       T lo = T(0), hi = T(0);
       if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
-        iface_along<RECON>(W.ecell[c], t, gstride(G, d1), lo, hi);
-      W.b25f[c][o][0][t] = lo;
-      W.b25f[c][o][1][t] = hi;
+        iface_along<RECON>(A, t, gstride(G, d1), lo, hi);
+      T* const* out = EMF == kB25A ? W.b25f[c][o] : W.fsf[c][o];
+      out[0][t] = lo;
+      out[1][t] = hi;
     }
 }
 
-template <typename T, int RECON>
-__global__ void __launch_bounds__(kBlock) k_b25a_first(Geom G, Work<T> W, const int* stop) {
+template <typename T, int RECON, int EMF>
+__global__ void __launch_bounds__(kBlock) k_first_step(Geom G, Work<T> W, const int* stop) {
   if (*stop) return;
-  b25a_first_at<T, RECON>(G, W, gidx());
+  first_step_at<T, RECON, EMF>(G, W, gidx());
 }
 
 // Second step of a two-step reconstruction from the stored first-step
@@ -718,7 +726,7 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
     e[3] = -uaT * bbR + ubR * baT;
   } else if (EMF == kB25A) {
     T ab[4], ba[4];  // [x_a x_b]: index sa_side + 2 sb_side; [x_b x_a]: sb_side + 2 sa_side
-    if constexpr (b25a_first_stored(RECON)) {
+    if constexpr (first_step_stored(EMF, RECON)) {
       second_step<RECON>(W.b25f[c][0], s, sb, ab);
       second_step<RECON>(W.b25f[c][1], s, sa, ba);
     } else {
@@ -730,13 +738,20 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
     e[2] = T(0.5) * (ab[2] + ba[1]);
     e[3] = T(0.5) * (ab[3] + ba[3]);
   } else {
-    const T* ua = W.prim[1 + a];
-    const T* ub = W.prim[1 + b];
     T ua_ab[4], ua_ba[4], ub_ab[4], ub_ba[4];
-    two_step<RECON>(ua, s, sa, sb, ua_ab);
-    two_step<RECON>(ua, s, sb, sa, ua_ba);
-    two_step<RECON>(ub, s, sa, sb, ub_ab);
-    two_step<RECON>(ub, s, sb, sa, ub_ba);
+    if constexpr (first_step_stored(EMF, RECON)) {
+      second_step<RECON>(W.fsf[a][a], s, sb, ua_ab);
+      second_step<RECON>(W.fsf[a][b], s, sa, ua_ba);
+      second_step<RECON>(W.fsf[b][a], s, sb, ub_ab);
+      second_step<RECON>(W.fsf[b][b], s, sa, ub_ba);
+    } else {
+      const T* ua = W.prim[1 + a];
+      const T* ub = W.prim[1 + b];
+      two_step<RECON>(ua, s, sa, sb, ua_ab);
+      two_step<RECON>(ua, s, sb, sa, ua_ba);
+      two_step<RECON>(ub, s, sa, sb, ub_ab);
+      two_step<RECON>(ub, s, sb, sa, ub_ba);
+    }
     const int perm[4] = {0, 2, 1, 3};  // corner q = sa_side + 2 sb_side -> [x_b x_a] index
     const T bbX[2] = {bbL, bbR}, baY[2] = {baB, baT};
 #pragma unroll
@@ -1097,7 +1112,7 @@ __global__ void __launch_bounds__(kBlock)
 // layers of every box are filled from the interiors of the boxes that own
 // those cells (exchange phases after every update).
 // ---------------------------------------------------------------------------
-enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_B };
+enum : int { PH_F = 0, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_FIRST };
 constexpr int kMaxPhases = 24;
 
 // Exchange phase argument (PlanHeader::xarg): which state to fill, whether
@@ -1202,6 +1217,13 @@ __device__ __forceinline__ Work<T> shift_work(const Work<T>& W0, long long off) 
 #pragma unroll
       for (int k = 0; k < 2; ++k)
         W.b25f[c][o][k] = W0.b25f[c][o][k] ? W0.b25f[c][o][k] + off : nullptr;
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        W.fsf[v][d][k] = W0.fsf[v][d][k] ? W0.fsf[v][d][k] + off : nullptr;
 #pragma unroll
   for (int st = 0; st < 2; ++st)
 #pragma unroll
@@ -1308,9 +1330,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs<T>& A, int b, int kin
     if constexpr (KIND == PH_P) {
       for (int s = 0; s < strips; ++s)
         prim_at<T, EMF>(in, G, W, A.gamma, (tile * strips + s) * kBlock + threadIdx.x);
-    } else if constexpr (KIND == PH_B) {
+    } else if constexpr (KIND == PH_FIRST) {
       for (int s = 0; s < strips; ++s)
-        b25a_first_at<T, RECON>(G, W, (tile * strips + s) * kBlock + threadIdx.x);
+        first_step_at<T, RECON, EMF>(G, W, (tile * strips + s) * kBlock + threadIdx.x);
     } else if constexpr (KIND == PH_F) {
       int nfb = 0;
       faces_block<T, RECON, RIEMANN>(in, G, W, tb.FP, tile, stage, A.gamma, A.eta, nfb);
@@ -1436,7 +1458,7 @@ __global__ void __launch_bounds__(kBlock) k_batch(BatchArgs<T> A) {
     const int kind = P->kind[p], stage = P->stage[p];
     switch (kind) {
       case PH_P: batch_item<T, RECON, RIEMANN, EMF, PH_P>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
-      case PH_B: batch_item<T, RECON, RIEMANN, EMF, PH_B>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
+      case PH_FIRST: batch_item<T, RECON, RIEMANN, EMF, PH_FIRST>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_F: batch_item<T, RECON, RIEMANN, EMF, PH_F>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_E: batch_item<T, RECON, RIEMANN, EMF, PH_E>(A, b, kind, stage, tile, strips, cl, P->xarg[p]); break;
       case PH_U:

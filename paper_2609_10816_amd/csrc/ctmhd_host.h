@@ -82,8 +82,8 @@ size_t box_ws_bytes(const ctmhd_box& b, size_t tbytes, const ctmhd_params* p) {
   size_t bytes = 0;
   bytes += 2 * 8 * align256(e * 8);           // two state buffers
   if (emf == CTMHD_EMF_B25A) bytes += 3 * align256(e * tbytes);  // cell EMF
-  if (emf == CTMHD_EMF_B25A && b25a_first_stored(p->recon))
-    bytes += 12 * align256(e * tbytes);      // its first-step face values
+  if (first_step_stored(emf, p->recon))     // stored first steps
+    bytes += (emf == CTMHD_EMF_B25A ? 12 : 18) * align256(e * tbytes);
   if (emf == CTMHD_EMF_FS18) bytes += 3 * align256(e * tbytes);  // cell velocity
   bytes += 2 * 15 * align256(e * tbytes);     // fluxes, two stages
   bytes += 9 * align256(e * tbytes);          // alpha+, alpha-, u*
@@ -121,15 +121,23 @@ int build_work(const ctmhd_params* prm, void* ws, size_t ws_bytes, const ctmhd_b
   for (int c = 0; c < 3; ++c) W.ecell[c] = nullptr;
   for (int c = 0; c < 3; ++c)
     for (int o = 0; o < 2; ++o) W.b25f[c][o][0] = W.b25f[c][o][1] = nullptr;
+  for (int v = 0; v < 3; ++v)
+    for (int d = 0; d < 3; ++d) W.fsf[v][d][0] = W.fsf[v][d][1] = nullptr;
+  const bool first = first_step_stored(prm->emf_compute, prm->recon);
   if (prm->emf_compute == CTMHD_EMF_B25A) {
     for (int c = 0; c < 3; ++c) W.ecell[c] = cv.take<T>(e);
-    if (b25a_first_stored(prm->recon))
+    if (first)
       for (int c = 0; c < 3; ++c)
         for (int o = 0; o < 2; ++o)
           for (int k = 0; k < 2; ++k) W.b25f[c][o][k] = cv.take<T>(e);
   }
-  if (prm->emf_compute == CTMHD_EMF_FS18)
+  if (prm->emf_compute == CTMHD_EMF_FS18) {
     for (int v = 1; v < 4; ++v) W.prim[v] = cv.take<T>(e);
+    if (first)
+      for (int v = 0; v < 3; ++v)
+        for (int d = 0; d < 3; ++d)
+          for (int k = 0; k < 2; ++k) W.fsf[v][d][k] = cv.take<T>(e);
+  }
   for (int st = 0; st < 2; ++st)
     for (int a = 0; a < 3; ++a)
       for (int m = 0; m < 5; ++m) W.F[st][a][m] = cv.take<T>(e);

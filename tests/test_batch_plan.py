@@ -6,7 +6,7 @@ import pytest
 
 from paper_2609_10816_amd import ctmhd
 
-PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_B = range(11)
+PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_FIRST = range(11)
 
 
 def _boxes(seed, nbox, ng=4):
@@ -40,7 +40,7 @@ def test_plan_queue_invariants(fofc, emf, tile):
     assert d["magic"] == 0x43544D48 and d["nbox"] == len(boxes)
     kinds = d["kind"]
     step = kinds[d["range"][1][0]:d["range"][1][1]]
-    expect = ([PH_P] if emf != "q26" else []) + ([PH_B] if emf == "b25a" else [])
+    expect = [PH_P, PH_FIRST] if emf != "q26" else []  # PPM: first steps stored
     expect += [PH_F, PH_E, PH_U] + ([PH_O, PH_X] if fofc else [])
     assert step == expect * 2
     assert kinds[d["range"][0][0]:d["range"][0][1]] == [PH_WRAP, PH_DT]
@@ -63,7 +63,7 @@ def test_plan_queue_invariants(fofc, emf, tile):
                 ninter = b.n[0] * b.n[1] * b.n[2]
                 if kinds[p] in (PH_U, PH_O, PH_X, PH_DT):
                     assert cnt == -(-ninter // (256 * strips))
-                elif kinds[p] in (PH_P, PH_B, PH_WRAP, PH_COPY):
+                elif kinds[p] in (PH_P, PH_FIRST, PH_WRAP, PH_COPY):
                     elems = int(np.prod([v + 2 * b.ng for v in b.n]))
                     assert cnt == -(-elems // (256 * strips))
                 elif kinds[p] == PH_E:
@@ -89,13 +89,15 @@ def test_plan_queue_invariants(fofc, emf, tile):
 
 
 @pytest.mark.parametrize("recon", ["pc", "plm", "plm_minmod", "ppm"])
-def test_b25a_first_step_phase_only_with_ppm(recon):
-    # B25a stores its first-step face values (a phase of their own) for PPM
-    # only; the shorter stencils recompute them in the edge pass
-    P = ctmhd.make_params(recon=recon, emf="b25a")
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
+def test_first_step_phase_only_with_ppm(recon, emf):
+    # B25a and FS18 store the first steps of their two-step corner
+    # reconstructions (a phase of their own) for PPM only; the shorter
+    # stencils recompute them in the edge pass
+    P = ctmhd.make_params(recon=recon, emf=emf)
     d = ctmhd.parse_plan(ctmhd.batch_plan(P, _boxes(2, 5)))
-    assert (PH_B in d["kind"]) == (recon == "ppm")
-    assert d["kind"].count(PH_P) == 2
+    assert d["kind"].count(PH_FIRST) == (2 if recon == "ppm" and emf != "q26" else 0)
+    assert d["kind"].count(PH_P) == (2 if emf != "q26" else 0)
 
 
 def test_plan_rejects_overlap_and_bad_buffers():

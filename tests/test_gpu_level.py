@@ -45,6 +45,7 @@ def _same(a, b, label, tol=1e-13):
 @pytest.mark.parametrize("recon,riemann,emf,precision,fofc,eta", [
     ("ppm", "hlld", "q26", "fp64", True, 1e-3),
     ("plm", "hlld", "b25a", "fp64", False, 0.0),
+    ("ppm", "hlld", "b25a", "fp64", True, 1e-3),
     ("ppm", "hlld", "fs18", "fp64", True, 0.0),
     ("ppm", "hlld", "q26", "fp32", True, 1e-3),
     ("pc", "llf", "q26", "fp64", True, 0.0),

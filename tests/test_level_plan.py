@@ -11,7 +11,7 @@ import pytest
 
 from paper_2609_10816_amd import ctmhd
 
-PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_B = range(11)
+PH_F, PH_E, PH_U, PH_O, PH_X, PH_WRAP, PH_DT, PH_COPY, PH_P, PH_XCHG, PH_FIRST = range(11)
 XG_HALF, XG_NEXT, XG_CUR, XG_FLAGS, XG_IF_FIXUP = 0, 1, 2, 4, 8
 
 
@@ -119,7 +119,7 @@ def test_level_phases(fofc, emf):
     for st in range(2):
         tgt = XG_HALF if st == 0 else XG_NEXT
         expect += [(PH_P, 0)] if emf != "q26" else []
-        expect += [(PH_B, 0)] if emf == "b25a" else []
+        expect += [(PH_FIRST, 0)] if emf != "q26" else []  # PPM: first steps stored
         expect += [(PH_F, 0), (PH_E, 0), (PH_U, 0), (PH_XCHG, tgt | (XG_FLAGS if fofc else 0))]
         if fofc:
             expect += [(PH_O, 0), (PH_X, 0), (PH_XCHG, tgt | XG_IF_FIXUP)]
