@@ -40,6 +40,21 @@ def test_box_elems_and_workspace():
     assert ws64 > ws32 > 0
 
 
+def test_workspace_holds_the_stored_first_steps():
+    # B25a (12 arrays) and FS18 (18 arrays) store the first step of their
+    # two-step corner reconstructions with PPM only; one array per element of
+    # the ghosted box in the stencil type, 256-byte aligned
+    b = ctmhd.make_box((10, 7, 3), 4, (0.1, 0.2, 0.3))
+    e = 18 * 15 * 11
+    for prec, tb in (("fp64", 8), ("fp32", 4)):
+        one = -(-e * tb // 256) * 256
+        ws = {(r, emf): ctmhd.workspace_bytes(ctmhd.make_params(recon=r, emf=emf, precision=prec), b)
+              for r in ("plm", "ppm") for emf in ("q26", "b25a", "fs18")}
+        assert ws[("plm", "b25a")] == ws[("plm", "fs18")] == ws[("plm", "q26")] + 3 * one
+        assert ws[("ppm", "b25a")] == ws[("ppm", "q26")] + (3 + 12) * one
+        assert ws[("ppm", "fs18")] == ws[("ppm", "q26")] + (3 + 18) * one
+
+
 def _call_step(p, b, nsteps=1):
     L = ctmhd.lib()
     dummy = ctypes.c_void_p(256)  # never dereferenced: validation fails first
