@@ -424,14 +424,16 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
       in_upd = in_upd && s3[d] >= FP.ulo[d] && s3[d] < FP.ulo[d] + FP.ulen[d] + (d == a ? 1 : 0);
     if (in_upd) F[4] += joule<T>(S, G, s, a, (T)eta_d);
   }
-  W.F[stage][a][0][s] = F[0];
-  W.F[stage][a][1 + a][s] = F[1];
-  W.F[stage][a][1 + b][s] = F[2];
-  W.F[stage][a][1 + c][s] = F[3];
-  W.F[stage][a][4][s] = F[4];
-  W.ap[a][s] = ap;
-  W.am[a][s] = am;
-  W.us[a][s] = (ap * L.un + am * R.un) / (ap + am);
+  // Streaming stores: no later access of this kernel reads them, and keeping
+  // them out of the L2 leaves it to the state rows the marches re-read.
+  __builtin_nontemporal_store(F[0], &W.F[stage][a][0][s]);
+  __builtin_nontemporal_store(F[1], &W.F[stage][a][1 + a][s]);
+  __builtin_nontemporal_store(F[2], &W.F[stage][a][1 + b][s]);
+  __builtin_nontemporal_store(F[3], &W.F[stage][a][1 + c][s]);
+  __builtin_nontemporal_store(F[4], &W.F[stage][a][4][s]);
+  __builtin_nontemporal_store(ap, &W.ap[a][s]);
+  __builtin_nontemporal_store(am, &W.am[a][s]);
+  __builtin_nontemporal_store((ap * L.un + am * R.un) / (ap + am), &W.us[a][s]);
   return fb;
 }
 
@@ -676,8 +678,8 @@ __device__ __forceinline__ void first_step_at(const Geom& G, const Work<T>& W, i
       if (s3[d1] - 1 - r >= 0 && s3[d1] + r < G.N[d1])
         iface_along<RECON>(A, t, gstride(G, d1), lo, hi);
       T* const* out = EMF == kB25A ? W.b25f[c][o] : W.fsf[c][o];
-      out[0][t] = lo;
-      out[1][t] = hi;
+      __builtin_nontemporal_store(lo, &out[0][t]);  // read by the edge pass only
+      __builtin_nontemporal_store(hi, &out[1][t]);
     }
 }
 
