@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle, one at a time, each of which the oracle's
 pins must catch (opt-in: CTMHD_MUTATION_TESTS=1; from a second to about
-100 s per case, nine minutes for all twelve on 8 cores).
+100 s per case, about ten minutes for all sixteen on 8 cores).
 
 Each case edits one expression of a copy of oracle/ctmhd_oracle.cpp (a sign,
 an index, an operand, a dropped term), builds it as the oracle library and
@@ -38,6 +38,14 @@ MUTATIONS = {
         "R e_ba = recon_two_step(g, recon, ecell, p, b, a, sa, sb);"),
     "rk2_average": ("S.c[m][x] = Sn.c[m][x] + R(0.5) * (D1S[m][x] + D2S[m][x]);",
                     "S.c[m][x] = Sn.c[m][x] + R(0.5) * (D1S[m][x] + D1S[m][x]);"),
+    "no_hll_fallback": ("if (bad) { hll(UL, FL, UR, FR, SL, SR, F); return 1; }",
+                        "if (false) { hll(UL, FL, UR, FR, SL, SR, F); return 1; }"),
+    "fs18_order_side": (
+        "recon_two_step(g, recon, W.u[a], p, b, a, sb, sa));",
+        "recon_two_step(g, recon, W.u[a], p, b, a, sa, sb));"),
+    "fs18_face_field_side": ("R bbX = sa == 0 ? bbL : bbR;", "R bbX = sa == 0 ? bbR : bbL;"),
+    "dual_quotient_rule": ("return {q, (a.d - q * b.d) / b.v};",
+                           "return {q, (a.d + q * b.d) / b.v};"),
     "fofc_edge_rule": (
         "if (flag[c] || flag[g.idx(q1.v)] || flag[g.idx(q2.v)] || flag[g.idx(q3.v)]) {",
         "if (flag[c] || flag[g.idx(q1.v)] || flag[g.idx(q2.v)]) {"),

@@ -149,7 +149,7 @@ def test_fast_wave_second_order_1d(emf, recon):
     assert orders[-1] >= 1.8, (errs, orders)
 
 
-@pytest.mark.parametrize("emf", ["q26", "b25a"])
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
 def test_fast_wave_second_order_2d(emf):
     """Oblique fast wave k = 2 pi (1, 1, 0): multidimensional EMF coupling.
     Pre-asymptotic at these sizes (observed orders 1.53, 1.72), so the
@@ -363,7 +363,7 @@ def test_fofc_none_flagged_is_rk2():
     np.testing.assert_array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("emf", ["q26", "b25a"])
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
 def test_fofc_random_masks_keep_invariants(emf):
     cons, bf, info = inputs.turbulent_box((12, 10, 8), mach=3.0, seed_v=25, seed_a=26)
     dx = [1 / 12, 1 / 10, 1 / 8]
@@ -465,3 +465,124 @@ def test_supersonic_pc_step_is_upwind(emf):
         assert np.abs(c1[m] - ec[m]).max() <= 1e-13 * np.abs(ec[m]).max()
     for a in range(3):
         assert np.abs(b1[a] - eb[a]).max() <= 1e-13 * np.abs(eb[a]).max()
+
+
+def _cell_prims(cons, bf):
+    rho = cons[0]
+    u = cons[1:4] / rho
+    bcc = np.stack([0.5 * (bf[a] + np.roll(bf[a], -1, axis=2 - a)) for a in range(3)])
+    p = (GAMMA - 1) * (cons[4] - 0.5 * rho * (u ** 2).sum(0) - 0.5 * (bcc ** 2).sum(0))
+    return rho, u, p, bcc
+
+
+def _at(f, d, s):
+    """Value of f at p + s e_d for every cell p (periodic)."""
+    return np.roll(f, -s, axis=2 - d) if s else f
+
+
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1), (1, -1), (-1, -1)])
+def test_supersonic_pc_fluxes_and_emfs_are_upwind_2d(emf, signs):
+    """A 2D state (x0, x1 vary; one cell along x2) moving supersonically along
+    both x0 and x1 in each of the four diagonal directions, with PC
+    reconstruction.  Every x0 and x1 face then has one of alpha^{+/-} equal
+    to zero (eq. emf:alpha-pm), so HLLD returns the upwind cell's physical
+    flux and LD04 (eq. emf:ld04) keeps only the corner EMF on the upwind side
+    of both axes, with no dissipative term.  That corner is, for Q26 (eqs.
+    emf:q26-facevel, emf:q26) and FS18 (eqs. emf:fs18-average, emf:fs18),
+    -u_a b_b + u_b b_a from the velocity of the cell upwind of the edge in
+    both directions and the two face fields adjacent to the edge on the
+    upwind sides; for B25a (eq. emf:b25a-emf-centre) the cell-centred EMF of
+    that cell.  Along x2 (one cell) both sides of every face are the same
+    cell, so those fluxes are the cell's physical flux."""
+    sx, sy = signs
+    n0, n1 = 12, 10
+    x0 = (np.arange(n0) + 0.5) / n0
+    x1 = (np.arange(n1) + 0.5) / n1
+    X1, X0 = np.meshgrid(x1, x0, indexing="ij")
+    shape = (1, n1, n0)
+
+    def fld(f):
+        return f.reshape(shape)
+
+    rho = fld(1.0 + 0.2 * np.sin(2 * np.pi * X0) * np.cos(2 * np.pi * X1))
+    u = np.stack([fld(30.0 * sx + 0.5 * np.cos(2 * np.pi * X1)),
+                  fld(30.0 * sy + 0.4 * np.sin(2 * np.pi * X0)),
+                  fld(0.3 * np.sin(2 * np.pi * (X0 + 2 * X1)))])
+    p = fld(0.6 + 0.1 * np.cos(2 * np.pi * (X0 - X1)))
+    bf = np.stack([fld(0.7 + 0.2 * np.sin(2 * np.pi * X1)),
+                   fld(-0.4 + 0.3 * np.cos(2 * np.pi * X0) * np.sin(2 * np.pi * X1)),
+                   fld(0.25 + 0.15 * np.sin(2 * np.pi * (2 * X0 + X1)))])
+    cons = inputs.from_primitives(rho, u, p, bf)
+    dx = [1.0 / n0, 1.0 / n1, 1.0]
+    F, E, nfb = oracle.fluxes(dict(recon="pc", emf=emf), cons, bf, dx)
+    assert nfb == 0
+    r, uc, pc, bcc = _cell_prims(cons, bf)
+    off = {0: -1 if sx > 0 else 0, 1: -1 if sy > 0 else 0, 2: 0}
+
+    # face fluxes: physical flux of the upwind cell with the stored normal field
+    for a in range(3):
+        t1, t2 = (a + 1) % 3, (a + 2) % 3
+        q = lambda f: _at(f, a, off[a])
+        st = (q(r), q(uc[a]), q(uc[t1]), q(uc[t2]), q(pc), q(bcc[t1]), q(bcc[t2]))
+        bn = bf[a]
+        b2 = bn * bn + st[5] ** 2 + st[6] ** 2
+        e = st[4] / (GAMMA - 1) + 0.5 * st[0] * (st[1] ** 2 + st[2] ** 2 + st[3] ** 2) + 0.5 * b2
+        pt = st[4] + 0.5 * b2
+        vb = st[1] * bn + st[2] * st[5] + st[3] * st[6]
+        exp = np.zeros((5,) + shape)
+        exp[0] = st[0] * st[1]
+        exp[1 + a] = st[0] * st[1] * st[1] + pt - bn * bn
+        exp[1 + t1] = st[0] * st[1] * st[2] - bn * st[5]
+        exp[1 + t2] = st[0] * st[1] * st[3] - bn * st[6]
+        exp[4] = (e + pt) * st[1] - bn * vb
+        for m in range(5):
+            scale = np.abs(exp[m]).max() + np.abs(exp).max() * 1e-3
+            assert np.abs(F[a][m] - exp[m]).max() <= 1e-12 * scale, (a, m)
+
+    # edge EMFs: the upwind corner
+    for c in range(3):
+        a, b = (c + 1) % 3, (c + 2) % 3
+        cell = lambda f: _at(_at(f, a, off[a]), b, off[b])
+        if emf == "b25a":
+            exp = -cell(uc[a]) * cell(bcc[b]) + cell(uc[b]) * cell(bcc[a])
+        else:
+            bb_up = _at(bf[b], a, off[a])   # x_b face adjacent to the edge, upwind along x_a
+            ba_up = _at(bf[a], b, off[b])   # x_a face adjacent to the edge, upwind along x_b
+            exp = -cell(uc[a]) * bb_up + cell(uc[b]) * ba_up
+        scale = np.abs(exp).max()
+        assert np.abs(E[c] - exp).max() <= 1e-12 * scale, (c, np.abs(E[c] - exp).max() / scale)
+
+
+@pytest.mark.parametrize("recon", ["pc", "plm", "plm_minmod", "ppm"])
+@pytest.mark.parametrize("emf", ["q26", "b25a", "fs18"])
+def test_dual_number_step_is_the_derivative(recon, emf):
+    """The forward-mode (dual-number) step, oracle.step_dual, against
+    one-sided second-order differences of the plain step along the same
+    tangent, (-3 f(0) + 4 f(+-h) - f(+-2h)) / (+-2h), with the frozen dt.  The
+    step is only piecewise smooth (limiter cases, Riemann-fan regions, min /
+    max): at a switch within 2h of the base point the two one-sided
+    differences differ and the dual derivative follows the branch taken at
+    the base point, so each output entry must match the difference on at
+    least one side."""
+    cons, bf, info = inputs.smooth_modes_box((8, 6, 5), amp=0.05, beta=1.0, seed=11)
+    dx = info["dx"]
+    P = dict(recon=recon, emf=emf, eta=1e-3, fofc=True)
+    dts = [oracle.cfl_dt(P, cons, bf, dx)]
+    rng = np.random.default_rng(12)
+    tc = rng.normal(size=cons.shape) * np.abs(cons).mean(axis=(1, 2, 3))[:, None, None, None]
+    tb = rng.normal(size=bf.shape) * np.abs(bf).mean()
+    _, _, tc1, tb1 = oracle.step_dual(P, cons, bf, tc, tb, dx, dts)
+    dual = np.concatenate([tc1.reshape(5, -1), tb1.reshape(3, -1)])
+    h = 1e-6
+    f = {}
+    for k in (-2, -1, 0, 1, 2):
+        c, b, _, d = oracle.step(P, cons + k * h * tc, bf + k * h * tb, dx, nsteps=1,
+                                 dt_fixed=dts)
+        assert d[0] == d[1] == 0
+        f[k] = np.concatenate([c.reshape(5, -1), b.reshape(3, -1)])
+    d_plus = (-3 * f[0] + 4 * f[1] - f[2]) / (2 * h)
+    d_minus = (3 * f[0] - 4 * f[-1] + f[-2]) / (2 * h)
+    scale = np.abs(dual).max(axis=1, keepdims=True)
+    err = np.minimum(np.abs(d_plus - dual), np.abs(d_minus - dual)) / scale
+    assert err.max() <= 1e-7, err.max()

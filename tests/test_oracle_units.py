@@ -288,3 +288,98 @@ def test_hlld_fan_rankine_hugoniot():
             scale = np.abs(Fa).max() + np.abs(Fb).max() + abs(S) * (np.abs(Ua).max() + np.abs(Ub).max())
             np.testing.assert_allclose(S * (Ub - Ua), Fb - Fa, atol=1e-12 * scale)
     assert nchecked > 200
+
+
+# ------------------------------------------------------------ HLL fallback
+def _hll_numpy(L, R, bn, SL, SR):
+    """The HLL flux (Harten, Lax & van Leer) with given outer speeds, from
+    the physical fluxes of the two states: F_L if S_L >= 0, F_R if S_R <= 0,
+    else (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L)."""
+    FL, UL = physical_flux(L, bn)
+    FR, UR = physical_flux(R, bn)
+    if SL >= 0:
+        return FL
+    if SR <= 0:
+        return FR
+    return (SR * FL - SL * FR + SL * SR * (UR - UL)) / (SR - SL)
+
+
+def _symmetric_rarefaction(rho, u, p, vt, bt, bn):
+    """Left state moving at -u, right state at +u, equal transverse state."""
+    L = np.array([rho, -u, vt[0], vt[1], p, bt[0], bt[1]])
+    R = np.array([rho, u, vt[0], vt[1], p, bt[0], bt[1]])
+    return L, R
+
+
+@pytest.mark.parametrize("rho,p,vt,bt,bn", [
+    (1.0, 0.01, (0.0, 0.0), (0.1, 0.0), 0.05),
+    (0.3, 0.2, (0.4, -0.2), (0.5, -0.3), 0.8),
+    (2.0, 1e-3, (0.0, 0.1), (0.0, 0.0), -0.3),
+])
+def test_hlld_symmetric_rarefaction_falls_back_at_closed_form_threshold(rho, p, vt, bt, bn):
+    """Two equal states separating at -u and +u.  By symmetry S_M = 0 and the
+    HLLD star total pressure (Miyoshi & Kusano 2005) reduces to
+    p_T* = p_T - rho c u, with c the common fast speed (S_L = -u - c,
+    S_R = u + c).  The fan is unphysical for u > p_T / (rho c): there HLLD
+    must return the HLL flux with the same outer speeds and count a fallback;
+    just below the threshold it must not fall back."""
+    pt = p + 0.5 * (bn * bn + bt[0] ** 2 + bt[1] ** 2)
+    c = oracle.fast_speed(rho, p, bn, bt[0], bt[1], GAMMA)
+    u_star = pt / (rho * c)
+    for u, expect_fb in ((0.97 * u_star, 0), (1.03 * u_star, 1), (5.0 * u_star, 1),
+                         (50.0 * u_star, 1)):
+        L, R = _symmetric_rarefaction(rho, u, p, vt, bt, bn)
+        F, SL, SR, fb = oracle.hlld(L, R, bn, GAMMA)
+        assert fb == expect_fb, (u / u_star, fb)
+        assert SL == pytest.approx(-u - c, rel=1e-14) and SR == pytest.approx(u + c, rel=1e-14)
+        if expect_fb:
+            Fh = _hll_numpy(L, R, bn, SL, SR)
+            np.testing.assert_allclose(F, Fh, rtol=1e-13, atol=1e-13 * np.abs(Fh).max())
+            np.testing.assert_allclose(F, oracle.hll(L, R, bn, GAMMA), rtol=1e-13,
+                                       atol=1e-13 * np.abs(Fh).max())
+            # symmetric HLL: zero mass flux, energy flux -b_n (v_t . b_t),
+            # normal momentum flux p_T - b_n^2 - rho u c (it can be negative)
+            vb = vt[0] * bt[0] + vt[1] * bt[1]
+            assert abs(F[0]) <= 1e-14 * rho * u
+            assert F[4] == pytest.approx(-bn * vb, rel=1e-12, abs=1e-13 * np.abs(Fh).max())
+            assert F[1] == pytest.approx(pt - bn * bn - rho * u * c, rel=1e-12,
+                                         abs=1e-13 * pt)
+        else:
+            # below the threshold the HLLD flux differs from HLL (it resolves
+            # the rotational and contact structure HLL smears)
+            sp, st, _ = oracle.hlld_fan(L, R, bn, GAMMA)
+            assert sp["pTs"] == pytest.approx(pt - rho * c * u, rel=1e-12)
+
+
+def test_hlld_cold_dust_at_rest_falls_back():
+    """p = 0, b = 0, u_n = 0 on both sides: every signal speed is zero, the
+    star states are undefined (0/0), and the solver must fall back to HLL,
+    whose S_L >= 0 branch returns the left physical flux (zero for dust at
+    rest), and count the fallback."""
+    L = np.array([1.0, 0.0, 0.3, -0.2, 0.0, 0.0, 0.0])
+    R = np.array([2.5, 0.0, -0.1, 0.4, 0.0, 0.0, 0.0])
+    F, SL, SR, fb = oracle.hlld(L, R, 0.0, GAMMA)
+    assert fb == 1
+    assert SL == 0.0 and SR == 0.0
+    np.testing.assert_array_equal(F, physical_flux(L, 0.0)[0])
+
+
+def test_hlld_fallback_flux_is_hll_in_strong_rarefactions():
+    """Asymmetric strong rarefactions (random states pulled apart at several
+    times their sound speed): whenever HLLD reports a fallback its flux is
+    the HLL flux with the same outer speeds; and fallbacks do occur."""
+    rng = np.random.default_rng(8)
+    nfb = 0
+    for _ in range(400):
+        L, R = _rand_state(rng), _rand_state(rng)
+        L[4] *= 1e-2
+        R[4] *= 1e-2
+        L[1] = -abs(L[1]) - rng.uniform(2.0, 20.0)
+        R[1] = abs(R[1]) + rng.uniform(2.0, 20.0)
+        bn = 0.3 * rng.normal()
+        F, SL, SR, fb = oracle.hlld(L, R, bn, GAMMA)
+        if fb:
+            nfb += 1
+            Fh = _hll_numpy(L, R, bn, SL, SR)
+            np.testing.assert_allclose(F, Fh, rtol=1e-12, atol=1e-12 * np.abs(Fh).max())
+    assert nfb > 100, nfb
