@@ -83,9 +83,17 @@ def test_plan_queue_invariants(fofc, emf, tile):
             seen.add(key)
             last_of[(p, k)] = q
             first_of.setdefault((p, k), q)
+        count_of = {}
+        for key in seen:
+            count_of[key[:2]] = count_of.get(key[:2], 0) + 1
         for (p, k), q0 in first_of.items():
             if p > lo:
                 assert last_of[(p - 1, k)] < q0
+                # the persistent kernel's wait on (p - 1, box) counts to the
+                # prefix difference; exactly that many items of (p - 1, box)
+                # signal it
+                need = d["prefix"][p - 1][k + 1] - d["prefix"][p - 1][k]
+                assert need == count_of.get((p - 1, k), 0)
 
 
 @pytest.mark.parametrize("recon", ["pc", "plm", "plm_minmod", "ppm"])
