@@ -1,36 +1,40 @@
 """Throughput of the CT-MHD step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb128|turb256|turb512]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb512|turb256|turb128]
                 [--precision fp64|fp32] [--emf q26|b25a|fs18] [--no-cpu-baseline]
-                [--no-fp32] [--no-batched] [--no-adjoint] [--no-level] [--copy-calibration]
+                [--no-fp32] [--no-sweep] [--no-batched] [--no-adjoint] [--copy-calibration]
 
 Prints ONE JSON line.  A step is one full RK2-SSP step with first-order flux
 correction on a seeded synthetic state already resident in HBM: CFL dt
 reduction, ghost wrap, and for both stages primitives, reconstruction, HLLD
 fluxes, edge EMFs, LD04 averaging, Ohmic terms, CT and conserved updates and
 invalid-state flagging.  `value` is FP64 cell-updates per second of the
-default workload (the 128^3 Mach-5 turbulent box, PPM + HLLD + Q26 + LD04).
+default workload, the primary throughput box: 512^3, resistive (eta 1e-3),
+rms Mach 2, beta 1, PPM + HLLD + Q26 + LD04, FP64, K steps after W warm-up
+steps.
 
 roofline: the dominant kernel is the face kernel (reconstruction + HLLD at
 every x_a face of one stage).  Its algorithmic work is face_flops (from
 tests/golden/flops_per_unit.json, the oracle's operation count with each
 reconstruction charged once) times the 3 n^3 interior faces (all three
-directions) one launch resolves; its duration is measured with HIP events recorded by the library
-around every launch inside the timed region.  The path is bound by FP64
-vector ALU throughput (peak 78.6 TFLOP/s on MI355X), not by HBM.
-traffic: HBM bytes per launch from the committed rocprofv3 counter summary
-of the same kernel source, or null if the kernel source has changed since.
-step_hbm_measured: the counters' bytes of every kernel of one step over the
-measured step time, against the 8 TB/s HBM peak (same guard).
+directions) one launch resolves; its duration is measured with HIP events
+recorded by the library around every launch inside the timed region.  The
+path is bound by FP64 vector ALU throughput (peak 78.6 TFLOP/s on MI355X),
+not by HBM.  traffic: HBM bytes per launch from the committed rocprofv3
+counter summary of the same kernel source and workload, or null if the
+kernel source has changed since.  step_hbm_measured: the counters' bytes of
+every kernel of one step over the measured step time, against the 8 TB/s
+HBM peak (same guard).
 
-Beside the headline line's FP64 value the same JSON line carries the other
-forms: fp32_form (the same workload in the FP32 form), level_form (the same
-box cut into 64 boxes of 32^3 that exchange ghost layers), batched_form (2000
-AMR-like boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against
-one ctmhd_step call per box) and adjoint_form (64^3 gradient of the kinetic
-energy after 20 steps through the hand-written adjoint, PLM and PPM with Q26,
-PLM with B25a and FS18: backward / forward time of the rollout, and one
-adjoint step against one forward step).
+Beside the headline the same JSON line carries: fp32_form (the headline
+workload in the FP32 form), sweep (Q26 and B25a, FP64 and FP32 at 512^3 and
+256^3, and the 128^3 Mach-5 box), level_form (the 128^3 box cut into 64
+boxes of 32^3 that exchange ghost layers), batched_form (2000 AMR-like
+boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against one
+ctmhd_step call per box), adjoint_form (64^3 gradient of the kinetic energy
+after 20 steps through the hand-written adjoint) and cpu_baseline (the
+oracle on a 128^3 box of the headline recipe, on the host's cores, with the
+CPU model).
 """
 from __future__ import annotations
 
@@ -97,14 +101,21 @@ def read_traffic(config, precision, emf, what="bytes_per_launch"):
     return float(v) if v else None
 
 
-def run_gpu(cfg, precision, emf, K, W, timer_pairs=0, copy_calibration=False):
-    import torch
-
-    from paper_2609_10816_amd import ctmhd, inputs
+def make_state(cfg):
+    from paper_2609_10816_amd import inputs
 
     t0 = time.time()
-    cons, bf, info = getattr(inputs, cfg["recipe"])(cfg["n"])
+    state = getattr(inputs, cfg["recipe"])(cfg["n"])
     log(f"input {cfg['name']} generated in {time.time() - t0:.1f}s")
+    return state
+
+
+def run_gpu(cfg, state, precision, emf, K, W, timer_pairs=0, copy_calibration=False):
+    import torch
+
+    from paper_2609_10816_amd import ctmhd
+
+    cons, bf, info = state
     P = ctmhd.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3,
                           precision=precision)
     ng = ctmhd.required_ghosts(P)
@@ -144,7 +155,7 @@ def run_gpu(cfg, precision, emf, K, W, timer_pairs=0, copy_calibration=False):
                dt_first=float(dts[0].item()))
     del S, st
     torch.cuda.empty_cache()
-    return res, (cons, bf, info)
+    return res
 
 
 def run_batched_form(K, W, log_tune=True):
@@ -233,9 +244,9 @@ def run_batched_form(K, W, log_tune=True):
 
 
 def run_level_form(cfg, emf, state, K, W, box=32):
-    """The headline box cut into a level of box^3 boxes (ctmhd_step_level:
+    """A box cut into a level of box^3 boxes (ctmhd_step_level:
     ghosts exchanged between the boxes after every update), FP64, the same
-    scheme and steps as the single-box line."""
+    scheme and steps as the single-box run of that box."""
     import torch
 
     from paper_2609_10816_amd import ctmhd
@@ -390,14 +401,30 @@ def run_adjoint_form(nsteps=20, every=5, reps=3):
     return out
 
 
-def cpu_baseline(cfg, emf, state, min_seconds=10.0, max_steps=20):
-    """The oracle (plain FP64 C++, OpenMP over z-planes) on the same state,
-    one step at a time until at least `min_seconds` of CPU work (at most
-    `max_steps` steps)."""
+def cpu_model():
+    """The host CPU's model name and logical CPU count, from /proc/cpuinfo."""
+    name, n = "unknown", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                n += 1
+                if name == "unknown":
+                    name = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return name, n or os.cpu_count()
+
+
+def cpu_baseline(cfg, emf, n=128, min_seconds=12.0, max_steps=20):
+    """The oracle (plain FP64 C++, OpenMP over z-planes, all the threads it is
+    given) on an n^3 box of the headline recipe: the same scheme, rms Mach,
+    beta and eta, at a size the host holds in seconds per step.  Steps one at
+    a time until at least `min_seconds` of CPU work (at most `max_steps`)."""
     import oracle
-    cons, bf, info = state
+    from paper_2609_10816_amd import inputs
+    cons, bf, info = getattr(inputs, cfg["recipe"])(n)
     Q = oracle.make_params(recon=cfg["recon"], emf=emf, eta=cfg["eta"], cfl=0.3)
-    n3 = cfg["n"] ** 3
+    n3 = n ** 3
     el, steps = 0.0, 0
     c, b = cons, bf
     while el < min_seconds and steps < max_steps:
@@ -405,10 +432,12 @@ def cpu_baseline(cfg, emf, state, min_seconds=10.0, max_steps=20):
         c, b, _, _ = oracle.step(Q, c, b, info["dx"], nsteps=1)
         el += time.perf_counter() - t0
         steps += 1
-    return {"value": n3 * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the full {cfg['n']}^3 box "
-                      f"({n3 * steps / 1e6:.2f} M cell-updates), {el:.1f} s"}
+    model, ncpu = cpu_model()
+    return {"value": n3 * steps / el / 1e6, "unit": "Mcell-updates/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} steps of a {n}^3 box of the same recipe "
+                      f"({n3 * steps / 1e6:.2f} M cell-updates, {el:.1f} s)",
+            "cpu_model": model, "host_logical_cpus": ncpu}
 
 
 def cpu_baseline_one_core(cfg, emf, n=64):
@@ -430,21 +459,51 @@ def cpu_baseline_one_core(cfg, emf, n=64):
                       f"cell-updates), {el:.1f} s"}
 
 
+def run_sweep(primary, primary_state, emf, K, W, out):
+    """The throughput sweep beside the headline: both EMF schemes (Q26 and
+    B25a) and both forms (FP64, FP32) at 512^3 and 256^3 of the resistive
+    Mach-2 box, and the 128^3 Mach-5 box (Q26), each for K timed steps after
+    W warm-up steps."""
+    sweep = {}
+    for name in ("turb512", "turb256", "turb128"):
+        cfg = CONFIGS[name]
+        state = primary_state if name == primary else make_state(cfg)
+        for e in (("q26", "b25a") if name != "turb128" else ("q26",)):
+            row = {}
+            for prec in ("fp64", "fp32"):
+                if name == primary and e == emf and prec == "fp64":
+                    row[prec] = out["value"]
+                    continue
+                r = run_gpu(cfg, state, prec, e, K, W)
+                row[prec] = cfg["n"] ** 3 * K / r["elapsed"] / 1e6
+                log(f"sweep {name} {e} {prec}: {row[prec]:.1f} Mcell-updates/s")
+            row["fp32_speedup"] = row["fp32"] / row["fp64"]
+            sweep[f"{name}/{e}"] = row
+        if name == "turb128":
+            out["level_form"] = run_level_form(cfg, emf, state, K, W)
+            out["level_form"]["vs_single_box"] = (out["level_form"]["value"] /
+                                                  sweep["turb128/q26"]["fp64"])
+        del state
+    sweep["unit"] = "Mcell-updates/s"
+    sweep["steps"] = K
+    return sweep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="turb128", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="turb512", choices=sorted(CONFIGS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--emf", default="q26", choices=["q26", "b25a", "fs18"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=50)
-    ap.add_argument("--no-level", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -455,8 +514,9 @@ def main():
     cfg = CONFIGS[args.config]
     K, W = args.steps, args.warmup
     n3 = cfg["n"] ** 3
-    res, state = run_gpu(cfg, args.precision, args.emf, K, W, timer_pairs=64 * K,
-                         copy_calibration=args.copy_calibration)
+    state = make_state(cfg)
+    res = run_gpu(cfg, state, args.precision, args.emf, K, W, timer_pairs=64 * K,
+                  copy_calibration=args.copy_calibration)
     value = n3 * K / res["elapsed"] / 1e6
     log(f"{args.precision}: {value:.1f} Mcell-updates/s, face kernel "
         f"{res['kernel_ms']:.4f} ms avg over {res['nlaunch']} launches")
@@ -504,12 +564,12 @@ def main():
                                     "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of every "
                                               "kernel of a step, profiles/traffic_face_kernel.txt"}
     if args.precision == "fp64" and not args.no_fp32:
-        r32, _ = run_gpu(cfg, "fp32", args.emf, K, W)
+        r32 = run_gpu(cfg, state, "fp32", args.emf, K, W)
         v32 = n3 * K / r32["elapsed"] / 1e6
         out["fp32_form"] = {"value": v32, "unit": "Mcell-updates/s", "speedup": v32 / value}
-    if args.precision == "fp64" and not args.no_level:
-        out["level_form"] = run_level_form(cfg, args.emf, state, K, W)
-        out["level_form"]["vs_single_box"] = out["level_form"]["value"] / value
+    if args.precision == "fp64" and not args.no_sweep:
+        out["sweep"] = run_sweep(args.config, state, args.emf, K, W, out)
+    del state
     if not args.no_batched:
         bf = run_batched_form(args.batched_steps, W)
         bf["speedup_fp32_vs_fp64_single_box_step"] = bf["fp32"]["value"] / value
@@ -518,10 +578,10 @@ def main():
     if not args.no_adjoint:
         out["adjoint_form"] = run_adjoint_form()
     if rank == 0 and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.emf, state)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.emf)
         out["cpu_baseline_one_core"] = cpu_baseline_one_core(cfg, args.emf)
         log(f"oracle: {out['cpu_baseline']['value']:.3f} Mcell-updates/s on "
-            f"{out['cpu_baseline']['cores']} threads, "
+            f"{out['cpu_baseline']['cores']} threads ({out['cpu_baseline']['cpu_model']}), "
             f"{out['cpu_baseline_one_core']['value']:.3f} on one")
     print(json.dumps(out), flush=True)
 

@@ -53,3 +53,14 @@ def test_flop_table_has_every_bench_configuration(name, emf):
     key = f"{cfg['recon']}/{emf}/eta{'>0' if cfg['eta'] > 0 else '=0'}"
     assert key in tab
     assert tab[key]["face_flops"] > 0 and tab[key]["cell_update_flops"] > tab[key]["face_flops"]
+
+
+def test_cpu_model_is_read():
+    name, n = bench.cpu_model()
+    assert isinstance(name, str) and name and n >= 1
+
+
+def test_default_workload_is_the_512_box():
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--config", default="turb512"' in src
+    assert bench.CONFIGS["turb512"]["n"] == 512 and bench.CONFIGS["turb512"]["eta"] == 1e-3
