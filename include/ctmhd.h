@@ -263,6 +263,23 @@ int ctmhd_step_adjoint_tape(const ctmhd_params* p, const ctmhd_box* box, const v
                             double* const g_bface_out[3], void* workspace, size_t ws_bytes,
                             void* stream);
 
+/* ctmhd_step without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, layout, ownership, result and errors
+ * are those of ctmhd_step; the workspace is a fixed array of
+ * ctmhd_noalloc_scratch_bytes() (256 MiB) in the library's device memory,
+ * one per GPU, held from the first call on that GPU until the process ends.
+ * The call allocates and frees nothing.  A box whose
+ * ctmhd_workspace_bytes(p, box, 1) exceeds that size is rejected with
+ * CTMHD_EARG (in FP64 with PPM: up to 73^3 interior cells with Q26, 66^3 with
+ * FS18).  Every call on one GPU uses the same array: calls that overlap on
+ * one GPU (other host threads, or streams not ordered with each other) race
+ * and give wrong results; calls ordered on one stream are safe. */
+size_t ctmhd_noalloc_scratch_bytes(void);
+int ctmhd_step_noalloc(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
+                       double* const bface[3], int nsteps, const double* dt_fixed,
+                       double* dt_out, int64_t* diag, void* stream);
+
 /* Kernel timing hook (for benchmarks).  `events` holds 2*npairs hipEvent_t
  * handles created by the caller (timing enabled).  During subsequent
  * ctmhd_step calls in this process the library records pair i

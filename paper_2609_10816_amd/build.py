@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctmhd.so")
-SOURCES = ["ctmhd.hip", "ctmhd_batched.hip", "ctmhd_adjoint.hip"]
+SOURCES = ["ctmhd.hip", "ctmhd_batched.hip", "ctmhd_adjoint.hip", "ctmhd_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

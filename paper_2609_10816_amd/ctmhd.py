@@ -92,6 +92,10 @@ def lib():
         L.ctmhd_step_adjoint_tape.restype = ctypes.c_int
         L.ctmhd_adjoint_workspace_bytes.argtypes = [_P, _B]
         L.ctmhd_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        L.ctmhd_noalloc_scratch_bytes.argtypes = []
+        L.ctmhd_noalloc_scratch_bytes.restype = ctypes.c_size_t
+        L.ctmhd_step_noalloc.argtypes = [_P, _B, _PTR5, _PTR3, ctypes.c_int, _vp, _vp, _vp, _vp]
+        L.ctmhd_step_noalloc.restype = ctypes.c_int
         L.ctmhd_profile_events.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
         L.ctmhd_profile_events.restype = ctypes.c_int
         L.ctmhd_profile_recorded.argtypes = []
@@ -107,7 +111,8 @@ EXPORTED = ("ctmhd_required_ghosts", "ctmhd_box_elems", "ctmhd_workspace_bytes",
             "ctmhd_level_plan_bytes", "ctmhd_level_plan", "ctmhd_step_level",
             "ctmhd_step_adjoint", "ctmhd_tape_bytes", "ctmhd_step_record",
             "ctmhd_step_adjoint_tape", "ctmhd_adjoint_workspace_bytes", "ctmhd_profile_events",
-            "ctmhd_profile_recorded", "ctmhd_last_error")
+            "ctmhd_profile_recorded", "ctmhd_last_error", "ctmhd_noalloc_scratch_bytes",
+            "ctmhd_step_noalloc")
 
 
 def _check(rc):
@@ -171,6 +176,21 @@ def ctmhd_step(params: Params, box: Box, cons, bface, nsteps, dt_fixed=None, dt_
                           _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
                           int(nsteps), _p(dt_fixed), _p(dt_out), _p(diag), _p(ws),
                           ws.numel() if ws is not None else 0, _stream(stream))
+    return _check(rc)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().ctmhd_noalloc_scratch_bytes())
+
+
+def ctmhd_step_noalloc(params: Params, box: Box, cons, bface, nsteps, dt_fixed=None,
+                       dt_out=None, diag=None, stream=None):
+    """Direct binding of ctmhd_step_noalloc (ctmhd_step on the library's fixed
+    per-GPU scratch array instead of a caller workspace)."""
+    rc = lib().ctmhd_step_noalloc(ctypes.byref(params), ctypes.byref(box),
+                                  _PTR5(*[_p(t) for t in cons]), _PTR3(*[_p(t) for t in bface]),
+                                  int(nsteps), _p(dt_fixed), _p(dt_out), _p(diag),
+                                  _stream(stream))
     return _check(rc)
 
 
