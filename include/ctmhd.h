@@ -89,7 +89,10 @@ typedef struct ctmhd_params {
                             marching chunk of the face pass (default 32), bits 8-15
                             256-element strips per work item of the batched call (default 1),
                             bits 16-23 schedule of the batched call (0 one launch per phase,
-                            1 one persistent launch per step), bits 24-30 x-face row
+                            1 one persistent launch per step), bits 19-20 XCD mapping of
+                            the edge and update passes of ctmhd_step (0 automatic, 1 each
+                            XCD a contiguous range of tiles, 2 all XCDs on bands of one
+                            plane), bits 24-30 x-face row
                             segments per wavefront of the face pass (default 4); other
                             values are rejected with CTMHD_EARG */
   /* Test hook: NULL, or a DEVICE mask of 2 * n0*n1*n2 bytes (stage-1 mask then

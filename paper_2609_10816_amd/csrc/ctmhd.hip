@@ -29,15 +29,24 @@ int g_prof_used = 0;
 
 namespace {
 
+// Workgroups of the first-order and fix-up launches, which stride over the
+// box: enough to fill the chip when cells are flagged, few enough that the
+// usual launch with nothing flagged costs microseconds.
+inline int fix_blocks(int ninter) {
+  const int nb = nblocks(ninter);
+  return nb < 2048 ? nb : 2048;
+}
+
 template <typename T>
 int launch_fo(hipStream_t st, const ctmhd_params* p, State Sn, const Geom& G, const Work<T>& W,
               int stage, int ninter) {
+  const int nb = fix_blocks(ninter);
   if (p->emf_compute == CTMHD_EMF_Q26)
-    LAUNCH((k_fo<T, kQ26>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kQ26>), nb, Sn, G, W, stage, p->gamma, p->eta, W.stop);
   else if (p->emf_compute == CTMHD_EMF_B25A)
-    LAUNCH((k_fo<T, kB25A>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kB25A>), nb, Sn, G, W, stage, p->gamma, p->eta, W.stop);
   else
-    LAUNCH((k_fo<T, kFS18>), nblocks(ninter), Sn, G, W, stage, p->gamma, p->eta, W.stop);
+    LAUNCH((k_fo<T, kFS18>), nb, Sn, G, W, stage, p->gamma, p->eta, W.stop);
   return CTMHD_OK;
 }
 
@@ -66,10 +75,11 @@ int run_stage(hipStream_t st, const ctmhd_params* p, const Geom& G, const Work<T
   U.sres = sres;
   U.force = p->force_flags ? p->force_flags + (size_t)stage * ninter : nullptr;
   U.flag_storage = 0;
-  LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 0, U, diag, W.stop);
+  const int band = xcd_band(p, (long long)G.n[0] * G.n[1], ninter);
+  LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 0, U, diag, band, W.stop);
   if (p->fofc) {
     if ((rc = launch_fo<T>(st, p, base, G, W, stage, ninter))) return rc;
-    LAUNCH(k_update<T>, nblocks(ninter), base, in, out, G, W, stage, 1, U, diag, W.stop);
+    LAUNCH(k_update<T>, fix_blocks(ninter), base, in, out, G, W, stage, 1, U, diag, band, W.stop);
   }
   return CTMHD_OK;
 }

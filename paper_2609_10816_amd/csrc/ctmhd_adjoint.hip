@@ -1052,7 +1052,7 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
   if constexpr (first_step_stored(EMF, RECON))
     LAUNCH((k_first_step<double, RECON, EMF>), nb, G, W, W.stop);
   if ((rc = launch_emf<double, RECON>(st, p, A, G, W, 0))) return rc;
-  LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, W.stop);
+  LAUNCH(k_update<double>, nblocks(ninter), A, A, H, G, W, 0, 0, U, (long long*)nullptr, 0, W.stop);
   if ((rc = launch_faces<double, RECON>(st, p, H, G, W, FP, 1, nullptr))) return rc;
   return adj_reverse<RECON, RIEMANN, EMF>(st, p, G, C, W, C.W0, A, H, Gin, Gout);
 }
@@ -1105,7 +1105,7 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
   if ((rc = launch_faces<double, RECON>(st, p, T.S0, G, W0, FP, 0, nullptr))) return rc;
   if ((rc = launch_emf<double, RECON>(st, p, T.S0, G, W0, 0))) return rc;
   LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S0, T.S1, G, W0, 0, 0, U,
-         (long long*)nullptr, W.stop);
+         (long long*)nullptr, 0, W.stop);
   if (p->emf_compute == CTMHD_EMF_B25A) {
     LAUNCH((k_prim<double, kB25A>), nb, T.S1, G, W1, p->gamma, W.stop);
     if constexpr (first_step_stored(kB25A, RECON))
@@ -1119,7 +1119,7 @@ int record_box(const ctmhd_params* p_in, const ctmhd_box* box, double* const con
   if ((rc = launch_emf<double, RECON>(st, p, T.S1, G, W1, 1))) return rc;
   // a stopped step (non-finite dt) leaves the caller's state as it was
   LAUNCH(k_update<double>, nblocks(ninter), T.S0, T.S1, user, G, W1, 1, 0, U,
-         (long long*)nullptr, W.stop);
+         (long long*)nullptr, 0, W.stop);
   return CTMHD_OK;
 }
 

@@ -64,6 +64,22 @@ __device__ __forceinline__ int xcd_tile() {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// The banded alternative: XCD x takes tiles [j C + x m, j C + (x+1) m) of
+// every chunk j of C = 8 m consecutive tiles, so that all XCDs sweep the box
+// together, each on its own band of the same chunk.  With a chunk about one
+// plane of a large box, the planes a z stencil re-reads are then shared by the
+// whole chip in the Infinity Cache instead of being re-fetched from HBM by
+// each XCD on its own.  A bijection on [0, gridDim.x) (the tail beyond the
+// last complete chunk keeps its order); m = 0 gives xcd_tile().
+__device__ __forceinline__ int xcd_band_tile(int m) {
+  if (m <= 0) return xcd_tile();
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int C = kXcds * m;
+  if (b >= nb / C * C) return b;
+  const int k = b / kXcds;
+  return (k / m) * C + (b % kXcds) * m + k % m;
+}
+
 struct State {
   double* c[5];
   double* b[3];
@@ -709,6 +725,19 @@ __device__ __forceinline__ void second_step(T* const F[2], int s, int st2, T out
   out[3] = h1;
 }
 
+// Q26 corner EMFs (eq. emf:q26) from the edge-reconstructed face velocities
+// u*_a (B/T along x_b), u*_b (L/R along x_a) and face fields, combined by LD04
+// (eq. emf:ld04) with the edge wavespeeds (eq. emf:alpha-edge).
+template <typename T>
+__device__ __forceinline__ T q26_ld04(T uaB, T uaT, T ubL, T ubR, T baB, T baT, T bbL, T bbR,
+                                      T apa, T ama, T apb, T amb) {
+  const T e0 = -uaB * bbL + ubL * baB;
+  const T e1 = -uaB * bbR + ubR * baB;
+  const T e2 = -uaT * bbL + ubL * baT;
+  const T e3 = -uaT * bbR + ubR * baT;
+  return ld04(e0, e1, e2, e3, apa, ama, apb, amb, baB, baT, bbL, bbR);
+}
+
 template <typename T, int RECON, int EMF>
 __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
                                       double eta_d) {
@@ -717,16 +746,20 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
   T baB, baT, bbL, bbR;
   iface_along_d<RECON>(S.b[a], s, sb, baB, baT);
   iface_along_d<RECON>(S.b[b], s, sa, bbL, bbR);
-  T e[4];  // LB, RB, LT, RT
+  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
+  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
+  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
+  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
   if (EMF == kQ26) {
     T uaB, uaT, ubL, ubR;
     iface_along<RECON>(W.us[a], s, sb, uaB, uaT);
     iface_along<RECON>(W.us[b], s, sa, ubL, ubR);
-    e[0] = -uaB * bbL + ubL * baB;
-    e[1] = -uaB * bbR + ubR * baB;
-    e[2] = -uaT * bbL + ubL * baT;
-    e[3] = -uaT * bbR + ubR * baT;
-  } else if (EMF == kB25A) {
+    T eps = q26_ld04(uaB, uaT, ubL, ubR, baB, baT, bbL, bbR, apa, ama, apb, amb);
+    if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
+    return eps;
+  }
+  T e[4];  // LB, RB, LT, RT
+  if (EMF == kB25A) {
     T ab[4], ba[4];  // [x_a x_b]: index sa_side + 2 sb_side; [x_b x_a]: sb_side + 2 sa_side
     if constexpr (first_step_stored(EMF, RECON)) {
       second_step<RECON>(W.b25f[c][0], s, sb, ab);
@@ -763,10 +796,6 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
       e[q] = -u1 * bbX[q & 1] + u2 * baY[q >> 1];
     }
   }
-  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
-  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
-  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
-  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
   T eps = ld04(e[0], e[1], e[2], e[3], apa, ama, apb, amb, baB, baT, bbL, bbR);
   if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
   return eps;
@@ -788,9 +817,9 @@ __device__ __forceinline__ void emf_at(const State& S, const Geom& G, const Work
 
 template <typename T, int RECON, int EMF>
 __global__ void __launch_bounds__(kBlock)
-    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, const int* stop) {
+    k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, int band, const int* stop) {
   if (*stop) return;
-  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, xcd_tile() * kBlock + (int)threadIdx.x);
+  emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, xcd_band_tile(band) * kBlock + (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,11 +827,13 @@ __global__ void __launch_bounds__(kBlock)
 // rk2:update).  stage 0: out = S^n + D^n.  stage 1: out = S^n + (D^n +
 // D^{n+1/2})/2.  Increments are formed in FP64 from the stored fluxes and
 // EMFs (which are single-valued per face and edge: conservation and div b
-// hold to FP64 round-off in both precision forms).
+// hold to FP64 round-off in both precision forms), without contraction into
+// fused multiply-adds.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ double dcons(const Geom& G, const Work<T>& W, int st, int s, int m,
                                         double dt) {
+#pragma clang fp contract(off)
   double f = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -816,6 +847,7 @@ __device__ __forceinline__ double dcons(const Geom& G, const Work<T>& W, int st,
 template <typename T>
 __device__ __forceinline__ double dface(const Geom& G, const Work<T>& W, int st, int s, int a,
                                         double dt) {
+#pragma clang fp contract(off)
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const T* Ec = W.E[st][c];
   const T* Eb = W.E[st][b];
@@ -833,6 +865,7 @@ template <typename T>
 __device__ __forceinline__ double new_face(const State& base, const State& half, const Geom& G,
                                            const Work<T>& W, int stage, int fixup, int s, int a,
                                            double dt) {
+#pragma clang fp contract(off)
   if (stage == 0) return base.b[a][s] + dface(G, W, 0, s, a, dt);
   if (!fixup) return 0.5 * (base.b[a][s] + half.b[a][s] + dface(G, W, 1, s, a, dt));
   return base.b[a][s] + 0.5 * (dface(G, W, 0, s, a, dt) + dface(G, W, 1, s, a, dt));
@@ -855,6 +888,10 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
                                             const Geom& G, const Work<T>& W, int stage, int fixup,
                                             const UpdateCfg& U, long long* diag, int vb, int strips,
                                             unsigned long long* slots, int slot) {
+  // no fused multiply-adds: the update is memory-bound, and without them its
+  // results cannot depend on how a calling kernel is specialised (the main
+  // and fix-up calls, the single-box and batched kernels give the same bits)
+#pragma clang fp contract(off)
   const int ninter = G.n[0] * G.n[1] * G.n[2];
   const double dt = *W.dt;
   double sigmax = 0.0;
@@ -949,11 +986,20 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_update(State base, State half, State out, Geom G, Work<T> W, int stage, int fixup,
-             UpdateCfg U, long long* diag, const int* stop) {
+             UpdateCfg U, long long* diag, int band, const int* stop) {
   if (*stop) return;
-  if (fixup && W.nflag[stage] == 0) return;
-  update_item<T>(base, half, out, G, W, stage, fixup, U, diag, xcd_tile(), 1,
-                 W.smax + (fixup ? kMaxSlots : 0), blockIdx.x % kMaxSlots);
+  if (!fixup) {
+    update_item<T>(base, half, out, G, W, stage, 0, U, diag, xcd_band_tile(band), 1, W.smax,
+                   blockIdx.x % kMaxSlots);
+    return;
+  }
+  // fix-up: a capped grid strides over the tiles (usually nothing is flagged
+  // and every workgroup returns at once)
+  if (W.nflag[stage] == 0) return;
+  const int ntiles = (G.n[0] * G.n[1] * G.n[2] + kBlock - 1) / kBlock;
+  for (int vb = blockIdx.x; vb < ntiles; vb += (int)gridDim.x)
+    update_item<T>(base, half, out, G, W, stage, 1, U, diag, vb, 1, W.smax + kMaxSlots,
+                   blockIdx.x % kMaxSlots);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,7 +1146,11 @@ __global__ void __launch_bounds__(kBlock)
     k_fo(State Sn, Geom G, Work<T> W, int stage, double gamma, double eta_d, const int* stop) {
   if (*stop) return;
   if (W.nflag[stage] == 0) return;
-  fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, gidx(), false);
+  // grid-stride: the launch is capped, so that the usual case (nothing
+  // flagged) costs a few workgroups, not one per 256 cells
+  const int ninter = G.n[0] * G.n[1] * G.n[2];
+  for (int t = gidx(); t < ninter; t += (int)gridDim.x * kBlock)
+    fo_at<T, EMF>(Sn, G, W, stage, gamma, eta_d, t, false);
 }
 
 // ---------------------------------------------------------------------------

@@ -130,12 +130,18 @@ def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", 
                   0, int(bool(fofc)), int(flag_mask), PRECISION[precision], int(tile), ff)
 
 
-def make_tile(chunk=0, strips=0, persistent=False, xrows=0):
+XCD_MAP = {"auto": 0, "contiguous": 1, "banded": 2}
+
+
+def make_tile(chunk=0, strips=0, persistent=False, xrows=0, xcd_map="auto"):
     """The ctmhd_params.tile knob: minimum marching chunk, batched strips per
     work item, the batched schedule (per-phase launches or one persistent
-    launch per step) and the x-face row segments per wavefront (0: defaults)."""
+    launch per step), the XCD mapping of the single-box edge and update
+    passes ("auto", "contiguous": each XCD a contiguous range of tiles,
+    "banded": all XCDs on bands of the same plane) and the x-face row
+    segments per wavefront (0: defaults)."""
     return ((int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8) | ((1 if persistent else 0) << 16)
-            | ((int(xrows) & 0x7F) << 24))
+            | (XCD_MAP[xcd_map] << 19) | ((int(xrows) & 0x7F) << 24))
 
 
 def make_box(n, ng, dx, offset=0) -> Box:

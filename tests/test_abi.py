@@ -98,7 +98,10 @@ def test_tile_knob_validation():
     ok = ctmhd.make_params(tile=ctmhd.make_tile(chunk=16, strips=2, xrows=8))
     assert _call_step(ok, b) == -1  # passes the knob check, stops at the missing workspace
     assert b"workspace" in ctmhd.lib().ctmhd_last_error()
-    for bad in (1 << 17, 1 << 20, -1):
+    for m in ("contiguous", "banded"):
+        p = ctmhd.make_params(tile=ctmhd.make_tile(xcd_map=m))
+        assert _call_step(p, b) == -1 and b"workspace" in ctmhd.lib().ctmhd_last_error()
+    for bad in (1 << 17, 3 << 19, 1 << 21, -1):
         p = ctmhd.make_params(tile=bad)
         assert _call_step(p, b) == -1
         assert b"tile" in ctmhd.lib().ctmhd_last_error()

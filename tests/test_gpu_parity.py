@@ -120,6 +120,23 @@ def test_fofc_forced_masks():
         _stepwise(P, Q, cons, bf, dx, 2, f"fofc-forced {emf}", force=force)
 
 
+def test_fofc_forced_masks_beyond_one_grid():
+    """A box of more than 2048 x 256 cells with random forced flags: the
+    first-order and fix-up launches stride over it with a capped grid (more
+    than one tile per workgroup) and still follow the oracle."""
+    import torch
+    shape = (96, 80, 72)
+    assert shape[0] * shape[1] * shape[2] > 2048 * 256
+    cons, bf, info = inputs.turbulent_box(shape, mach=3.0, seed_v=44, seed_a=45)
+    dx = [1 / 96, 1 / 80, 1 / 72]
+    rng = np.random.default_rng(46)
+    force = (rng.random((2, 72, 80, 96)) < 0.02).astype(np.uint8)
+    ft = torch.from_numpy(force.reshape(-1).copy()).cuda()
+    P, Q = _params(recon="ppm", emf="q26", eta=1e-3)
+    P.force_flags = ft.data_ptr()
+    _stepwise(P, Q, cons, bf, dx, 1, "fofc-forced large", force=force)
+
+
 def test_fofc_all_cells():
     import torch
     cons, bf, info = inputs.turbulent_box((12, 12, 12), mach=3.0, seed_v=40, seed_a=41)
