@@ -1,7 +1,7 @@
 """Throughput of the CT-MHD step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config turb512|turb256|turb128]
-                [--precision fp64|fp32] [--emf q26|b25a|fs18] [--no-cpu-baseline]
+                [--precision fp64|fp32|fp32_r64] [--emf q26|b25a|fs18] [--no-cpu-baseline]
                 [--no-fp32] [--no-sweep] [--no-batched] [--no-adjoint] [--copy-calibration]
 
 Prints ONE JSON line.  A step is one full RK2-SSP step with first-order flux
@@ -26,11 +26,12 @@ kernel source has changed since.  step_hbm_measured: the counters' bytes of
 every kernel of one step over the measured step time, against the 8 TB/s
 HBM peak (same guard).
 
-Beside the headline the same JSON line carries: fp32_form (the headline
-workload in the FP32 form), sweep (Q26 and B25a, FP64 and FP32 at 512^3 and
+Beside the headline the same JSON line carries: fp32_form and
+fp32_r64_form (the headline workload in the FP32 form, and in the FP32 form
+with its Riemann solve in FP64), sweep (Q26 and B25a, FP64 and FP32 at 512^3 and
 256^3, and the 128^3 Mach-5 box), level_form (the 128^3 box cut into 64
 boxes of 32^3 that exchange ghost layers), batched_form (2000 AMR-like
-boxes, FP32 and FP64, 50 steps replayed from one HIP graph, against one
+boxes, both FP32 forms and FP64, 50 steps replayed from one HIP graph, against one
 ctmhd_step call per box), adjoint_form (64^3 gradient of the kinetic energy
 after 20 steps through the hand-written adjoint) and cpu_baseline (the
 oracle on a 128^3 box of the headline recipe, on the host's cores, with the
@@ -176,7 +177,7 @@ def run_batched_form(K, W, log_tune=True):
         f"{time.time() - t0:.1f}s")
     out = {"workload": "amr-like-2000-boxes-8..64-ppm", "boxes": len(states), "cells": cells,
            "steps": K}
-    for precision in ("fp32", "fp64"):
+    for precision in ("fp32", "fp32_r64", "fp64"):
         P = ctmhd.make_params(recon="ppm", emf="q26", cfl=0.3, precision=precision)
         st = ctmhd.BatchedState.from_numpy(states, ctmhd.required_ghosts(P))
         if precision == "fp32":
@@ -495,7 +496,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="turb512", choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp32_r64"])
     ap.add_argument("--emf", default="q26", choices=["q26", "b25a", "fs18"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -567,6 +568,11 @@ def main():
         r32 = run_gpu(cfg, state, "fp32", args.emf, K, W)
         v32 = n3 * K / r32["elapsed"] / 1e6
         out["fp32_form"] = {"value": v32, "unit": "Mcell-updates/s", "speedup": v32 / value}
+        r3r = run_gpu(cfg, state, "fp32_r64", args.emf, K, W)
+        v3r = n3 * K / r3r["elapsed"] / 1e6
+        out["fp32_r64_form"] = {"value": v3r, "unit": "Mcell-updates/s", "speedup": v3r / value,
+                                "riemann": "fp64"}
+        log(f"fp32: {v32:.1f}, fp32 with FP64 Riemann: {v3r:.1f} Mcell-updates/s")
     if args.precision == "fp64" and not args.no_sweep:
         out["sweep"] = run_sweep(args.config, state, args.emf, K, W, out)
     del state

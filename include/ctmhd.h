@@ -64,6 +64,9 @@ extern "C" {
 #define CTMHD_FP64 0           /* everything in float64 */
 #define CTMHD_FP32 1           /* stencil in float32; pressure recovery, dt and
                                   the state / face-b accumulation in float64 */
+#define CTMHD_FP32_R64 2       /* as CTMHD_FP32, with the Riemann solve in float64
+                                  (from the float32 face states); its fluxes,
+                                  wavespeeds and u* are stored in float32 */
 /* dt mode of the batched call */
 #define CTMHD_DT_GLOBAL 0
 #define CTMHD_DT_PER_BOX 1
@@ -84,7 +87,7 @@ typedef struct ctmhd_params {
   int32_t emf_average;   /* CTMHD_AVG_LD04 */
   int32_t fofc;          /* 1: first-order flux correction on, 0: off */
   int32_t flag_criteria; /* OR of CTMHD_FLAG_* */
-  int32_t precision;     /* CTMHD_FP64 or CTMHD_FP32 */
+  int32_t precision;     /* CTMHD_FP64, CTMHD_FP32 or CTMHD_FP32_R64 */
   int32_t tile;          /* launch-shape knob (0 = defaults): bits 0-7 minimum faces per
                             marching chunk of the face pass (default 32), bits 8-15
                             256-element strips per work item of the batched call (default 1),

@@ -171,7 +171,7 @@ int ctmhd_step(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5
   if (nsteps < 0) return fail(CTMHD_EARG, "nsteps must be >= 0");
   if (nsteps == 0) return CTMHD_OK;
   hipStream_t st = (hipStream_t)stream;
-  if (p->precision == CTMHD_FP32)
+  if (p->precision != CTMHD_FP64)
     return step_box_t<float>(p, box, cons, bface, nsteps, dt_fixed, dt_out, diag, workspace,
                              ws_bytes, st);
   return step_box_t<double>(p, box, cons, bface, nsteps, dt_fixed, dt_out, diag, workspace,

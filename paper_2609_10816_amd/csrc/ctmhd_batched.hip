@@ -269,7 +269,7 @@ long long packed_elems(const ctmhd_box* boxes, int nbox) {
 }
 
 size_t batch_ws_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
-  const size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
+  const size_t tb = stencil_bytes(p);
   const size_t e = (size_t)packed_elems(boxes, nbox);
   int kind[kMaxPhases], stage[kMaxPhases], xarg[kMaxPhases], range[3][2];
   const int nphase = plan_phases(p, true, kind, stage, xarg, range);  // the longer list
@@ -480,6 +480,18 @@ int batched_emf(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const L
                 size_t ws_bytes, hipStream_t st) {
 #define CTMHD_BATCH(RI, EM) \
   batched_run<T, RECON, RI, EM>(p, nbox, boxes, L, plan, cons, bface, nsteps, dt_mode, dt_fixed, dt_out, diag, ws, ws_bytes, st)
+  if constexpr (std::is_same<T, float>::value) {
+    if (p->precision == CTMHD_FP32_R64) {
+      if (p->riemann == CTMHD_RIEMANN_HLLD) {
+        if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kHLLD64, kQ26);
+        if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kHLLD64, kB25A);
+        return CTMHD_BATCH(kHLLD64, kFS18);
+      }
+      if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kLLF64, kQ26);
+      if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kLLF64, kB25A);
+      return CTMHD_BATCH(kLLF64, kFS18);
+    }
+  }
   if (p->riemann == CTMHD_RIEMANN_HLLD) {
     if (p->emf_compute == CTMHD_EMF_Q26) return CTMHD_BATCH(kHLLD, kQ26);
     if (p->emf_compute == CTMHD_EMF_B25A) return CTMHD_BATCH(kHLLD, kB25A);
@@ -631,7 +643,7 @@ int step_common(const ctmhd_params* p, int nbox, const ctmhd_box* boxes, const L
   if (nsteps == 0) return CTMHD_OK;
   if (packed_elems(boxes, nbox) * 6 >= (1LL << 31) * 64LL) return fail(CTMHD_EARG, "packed arrays too large");
   hipStream_t st = (hipStream_t)stream;
-  if (p->precision == CTMHD_FP32)
+  if (p->precision != CTMHD_FP64)
     return batched_t<float>(p, nbox, boxes, L, plan, cons, bface, nsteps, dt_mode, dt_fixed,
                             dt_out, diag, workspace, ws_bytes, st);
   return batched_t<double>(p, nbox, boxes, L, plan, cons, bface, nsteps, dt_mode, dt_fixed,
@@ -644,7 +656,7 @@ extern "C" {
 
 size_t ctmhd_workspace_bytes(const ctmhd_params* p, const ctmhd_box* boxes, int nbox) {
   if (check_params(p) || !boxes || nbox < 1) return 0;
-  size_t tb = p->precision == CTMHD_FP32 ? 4 : 8;
+  size_t tb = stencil_bytes(p);
   // one box: enough for either entry point
   if (nbox == 1) {
     const size_t one = box_ws_bytes(boxes[0], tb, p);

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 #include "ctmhd.h"
 #include "ctmhd_math.h"
@@ -419,19 +420,24 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
                                                int stage, const T qL[7], const T qR[7],
                                                double bn_d, double gamma_d, double eta_d) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
-  FState<T> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
-  FState<T> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
-  T bn = (T)bn_d;  // normal field of the face, S.b[a][s]
+  // the solver's arithmetic type: T, or float64 for kHLLD64 / kLLF64
+  using RT = typename std::conditional<(RIEMANN >= kHLLD64), double, T>::type;
+  FState<RT> L{(RT)qL[0], (RT)qL[1], (RT)qL[2], (RT)qL[3], (RT)qL[4], (RT)qL[5], (RT)qL[6]};
+  FState<RT> R{(RT)qR[0], (RT)qR[1], (RT)qR[2], (RT)qR[3], (RT)qR[4], (RT)qR[5], (RT)qR[6]};
+  const RT bn = (RT)bn_d;  // normal field of the face, S.b[a][s]
+  RT Fr[5];
   T F[5], ap, am;
   int fb = 0;
-  if (RIEMANN == kHLLD) {
-    T SL, SR;
-    fb = hlld_flux(L, R, bn, (T)gamma_d, F, SL, SR);
-    ap = tmax(T(0), SR);
-    am = tmax(T(0), -SL);
+  if (RIEMANN == kHLLD || RIEMANN == kHLLD64) {
+    RT SL, SR;
+    fb = hlld_flux(L, R, bn, (RT)gamma_d, Fr, SL, SR);
+    ap = (T)tmax(RT(0), SR);
+    am = (T)tmax(RT(0), -SL);
   } else {
-    ap = am = llf_flux(L, R, bn, (T)gamma_d, F);
+    ap = am = (T)llf_flux(L, R, bn, (RT)gamma_d, Fr);
   }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) F[m] = (T)Fr[m];
   if (eta_d > 0.0) {
     // faces read by the update: [g, g+n] along the normal, [g, g+n) across
     bool in_upd = true;
@@ -449,7 +455,7 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
   __builtin_nontemporal_store(F[4], &W.F[stage][a][4][s]);
   __builtin_nontemporal_store(ap, &W.ap[a][s]);
   __builtin_nontemporal_store(am, &W.am[a][s]);
-  __builtin_nontemporal_store((ap * L.un + am * R.un) / (ap + am), &W.us[a][s]);
+  __builtin_nontemporal_store((ap * (T)L.un + am * (T)R.un) / (ap + am), &W.us[a][s]);
   return fb;
 }
 

@@ -17,6 +17,9 @@ namespace {
 // Host side
 // ---------------------------------------------------------------------------
 
+// Bytes of the stencil type of a precision form: float32 for both FP32 forms.
+inline size_t stencil_bytes(const ctmhd_params* p) { return p->precision == CTMHD_FP64 ? 8 : 4; }
+
 int fail(int code, const char* msg) {
   snprintf(g_err, sizeof(g_err), "%s", msg);
   return code;
@@ -75,7 +78,8 @@ int check_params(const ctmhd_params* p) {
   if (p->riemann < 0 || p->riemann > 1) return fail(CTMHD_EARG, "unknown Riemann solver");
   if (p->emf_compute < 0 || p->emf_compute > 2) return fail(CTMHD_EARG, "unknown EMF scheme");
   if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
-  if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32) return fail(CTMHD_EARG, "unknown precision");
+  if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32 && p->precision != CTMHD_FP32_R64)
+    return fail(CTMHD_EARG, "unknown precision");
   if (p->tile < 0 || (p->tile & ~0x7f19ffff) != 0 || ((p->tile >> 19) & 3) == 3)
     return fail(CTMHD_EARG, "tile knob out of range");
   return CTMHD_OK;
@@ -241,6 +245,18 @@ template <typename T, int RECON>
 int launch_faces(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
                  const FacePlan& FP, int stage, long long* diag) {
   prof_begin(st);
+  if constexpr (std::is_same<T, float>::value) {
+    if (p->precision == CTMHD_FP32_R64) {
+      if (p->riemann == CTMHD_RIEMANN_HLLD)
+        LAUNCH((k_faces<T, RECON, kHLLD64>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta,
+               diag, W.stop);
+      else
+        LAUNCH((k_faces<T, RECON, kLLF64>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta,
+               diag, W.stop);
+      prof_end(st);
+      return CTMHD_OK;
+    }
+  }
   if (p->riemann == CTMHD_RIEMANN_HLLD)
     LAUNCH((k_faces<T, RECON, kHLLD>), FP.total_blocks, S, G, W, FP, stage, p->gamma, p->eta, diag,
            W.stop);

@@ -15,7 +15,9 @@
 namespace ctmhd {
 
 enum : int { kPC = 0, kPLM_MC = 1, kPLM_MM = 2, kPPM = 3 };
-enum : int { kHLLD = 0, kLLF = 1 };
+// Riemann solvers; kHLLD64 / kLLF64 solve in float64 from face states of
+// the stencil type (the FP32 form with a float64 Riemann solve)
+enum : int { kHLLD = 0, kLLF = 1, kHLLD64 = 2, kLLF64 = 3 };
 enum : int { kQ26 = 0, kB25A = 1, kFS18 = 2 };
 
 // Reconstruction half-width r of each method; ghost layers needed = r + 2.

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libctmhd.so")
 RECON = {"pc": 0, "plm": 1, "plm_mc": 1, "plm_minmod": 2, "ppm": 3}
 RIEMANN = {"hlld": 0, "llf": 1}
 EMF = {"q26": 0, "b25a": 1, "fs18": 2}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_r64": 2}
 DT_GLOBAL, DT_PER_BOX = 0, 1
 
 

@@ -87,6 +87,22 @@ def test_bad_box_rejected():
     assert b"workspace" in ctmhd.lib().ctmhd_last_error()
 
 
+def test_precision_forms():
+    b = ctmhd.make_box((8, 8, 8), 3, (0.1,) * 3)
+    for prec in ("fp64", "fp32", "fp32_r64"):
+        assert _call_step(ctmhd.make_params(precision=prec), b) == -1
+        assert b"workspace" in ctmhd.lib().ctmhd_last_error()
+    # both FP32 forms keep their stencil arrays in float32
+    bw = ctmhd.make_box((10, 7, 3), 4, (0.1, 0.2, 0.3))
+    assert (ctmhd.workspace_bytes(ctmhd.make_params(recon="ppm", precision="fp32"), bw) ==
+            ctmhd.workspace_bytes(ctmhd.make_params(recon="ppm", precision="fp32_r64"), bw))
+    p = ctmhd.make_params()
+    for bad in (3, -1):
+        p.precision = bad
+        assert _call_step(p, b) == -1
+        assert b"precision" in ctmhd.lib().ctmhd_last_error()
+
+
 def test_unsupported_averaging():
     p = ctmhd.make_params()
     p.emf_average = 1
@@ -115,7 +131,7 @@ def test_adjoint_configurations_and_workspace_query():
                dict(recon="plm", emf="fs18")):
         p = ctmhd.make_params(fofc=False, **kw)
         assert ctmhd.adjoint_workspace_bytes(p, b) > ctmhd.workspace_bytes(p, b), kw
-    for kw in (dict(precision="fp32"),):
+    for kw in (dict(precision="fp32"), dict(precision="fp32_r64")):
         assert ctmhd.adjoint_workspace_bytes(ctmhd.make_params(**kw), b) == 0, kw
         assert b"adjoint" in ctmhd.lib().ctmhd_last_error()
 

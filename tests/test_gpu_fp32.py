@@ -1,5 +1,6 @@
-"""The FP32 form (stencil arithmetic in float32; pressure recovery, dt and the
-state / face-b accumulation in float64) against the FP64 oracle.
+"""The FP32 forms (stencil arithmetic in float32; pressure recovery, dt and
+the state / face-b accumulation in float64; CTMHD_FP32_R64 also solves the
+Riemann problem in float64) against the FP64 oracle.
 
 Bar: relative L1 error <= 1e-5 per field after 100 steps of the Mach-5
 turbulent box; conservation and discrete div b at FP64 round-off (the FP32
@@ -33,17 +34,18 @@ def _conserved(c0, c1, tol=1e-13):
         assert abs(c1[m].sum() - c0[m].sum()) <= tol * scale, m
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32_r64"])
 @pytest.mark.parametrize("emf", ["q26", "b25a"])
-def test_fp32_vs_oracle_100_steps(emf):
+def test_fp32_vs_oracle_100_steps(emf, precision):
     n = 48
     cons, bf, info = inputs.turbulent_box((n, n, n), mach=5.0, b0=(0.1, 0.0, 0.0), db_rms=0.05,
                                           seed_v=1, seed_a=2)
     dx = info["dx"]
     co, bo, dts, do = oracle.step(dict(recon="ppm", emf=emf), cons, bf, dx, nsteps=100)
-    P = ctmhd.make_params(recon="ppm", emf=emf, precision="fp32")
+    P = ctmhd.make_params(recon="ppm", emf=emf, precision=precision)
     cg, bg, dtg, dg = ctmhd.run(P, cons, bf, dx, 100, dt_fixed=dts)
     errs = _field_errors(cg, bg, co, bo)
-    print(f"[fp32] {n}^3 Mach-5 PPM {emf}, 100 steps vs FP64 oracle: " +
+    print(f"[fp32] {precision} {n}^3 Mach-5 PPM {emf}, 100 steps vs FP64 oracle: " +
           " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
     assert max(errs.values()) <= 1e-5, errs
     _conserved(cons, cg)
@@ -51,17 +53,18 @@ def test_fp32_vs_oracle_100_steps(emf):
     assert int(dg[:, :2].sum()) == int(do[0] + do[1])
 
 
-def test_fp32_one_step_close():
+@pytest.mark.parametrize("precision", ["fp32", "fp32_r64"])
+def test_fp32_one_step_close(precision):
     """One step: FP32 rounding only (~1e-7 relative)."""
     cons, bf, info = inputs.turbulent_box((24, 20, 16), mach=2.0, b0=(1.0, 0.0, 0.0), db_rms=0.5,
                                           seed_v=3, seed_a=4)
     dx = [1 / 24, 1 / 20, 1 / 16]
     co, bo, dts, _ = oracle.step(dict(recon="ppm", eta=1e-3), cons, bf, dx, nsteps=1)
-    P = ctmhd.make_params(recon="ppm", eta=1e-3, precision="fp32")
+    P = ctmhd.make_params(recon="ppm", eta=1e-3, precision=precision)
     cg, bg, dtg, _ = ctmhd.run(P, cons, bf, dx, 1)
     assert dtg[0] == pytest.approx(dts[0], rel=1e-13)  # dt stays FP64
     errs = _field_errors(cg, bg, co, bo)
-    print("[fp32] one step 24x20x16 Mach-2 eta 1e-3: " +
+    print(f"[fp32] {precision} one step 24x20x16 Mach-2 eta 1e-3: " +
           " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
     assert max(errs.values()) <= 1e-6
 
