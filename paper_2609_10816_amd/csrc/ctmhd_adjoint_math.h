@@ -147,7 +147,7 @@ CTMHD_HD void recon_cell_adj5(const T q[5], T lob, T hib, T qb[5]) {
 template <typename T>
 CTMHD_HD void fast_speed_adj(T rho, T p, T bn, T bt1, T bt2, T gamma, T cb, T& rhob, T& pb,
                              T& bnb, T& bt1b, T& bt2b) {
-  const T irho = T(1) / rho;
+  const T irho = trcp(rho);
   const T gp = gamma * p;
   const T tot = gp + bn * bn + bt1 * bt1 + bt2 * bt2;
   const T a = tot * irho;
@@ -311,13 +311,13 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     const T bn2 = bn * bn;
     const T dL = SL - L.un, dR = SR - R.un;
     const T mL = dL * L.rho, mR = dR * R.rho;
-    const T iden = T(1) / (mR - mL);
+    const T iden = trcp(mR - mL);
     const T NS = mR * R.un - mL * L.un - pTR + pTL;
     const T SM = NS * iden;
     const T NP = mR * pTL - mL * pTR + mL * mR * (R.un - L.un);
     const T pTs = NP * iden;
     const T dsL = SL - SM, dsR = SR - SM;
-    const T idsL = T(1) / dsL, idsR = T(1) / dsR;
+    const T idsL = trcp(dsL), idsR = trcp(dsR);
     const T rsL = mL * idsL, rsR = mR * idsR;
     T vsL, wsL, bysL, bzsL, vsR, wsR, bysR, bzsR;
     T qL, iqL, fvL, fbL, qR, iqR, fvR, fbR;
@@ -325,7 +325,7 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     {
       qL = mL * dsL - bn2;
       degL = tabs(qL) <= T(1e-12) * (tabs(mL * dsL) + bn2);
-      iqL = T(1) / qL;
+      iqL = trcp(qL);
       fvL = bn * (SM - L.un) * iqL;
       fbL = (mL * dL - bn2) * iqL;
       vsL = degL ? L.ut1 : L.ut1 - L.bt1 * fvL;
@@ -336,7 +336,7 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     {
       qR = mR * dsR - bn2;
       degR = tabs(qR) <= T(1e-12) * (tabs(mR * dsR) + bn2);
-      iqR = T(1) / qR;
+      iqR = trcp(qR);
       fvR = bn * (SM - R.un) * iqR;
       fbR = (mR * dR - bn2) * iqR;
       vsR = degR ? R.ut1 : R.ut1 - R.bt1 * fvR;
@@ -364,7 +364,7 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
         T UL[5], FL[5], UR[5], FR[5], pd;
         phys_flux(L, bn, gm1inv, UL, FL, pd);
         phys_flux(R, bn, gm1inv, UR, FR, pd);
-        const T iw = T(1) / (SR - SL);
+        const T iw = trcp(SR - SL);
         T ULb[5], FLb[5], URb[5], FRb[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
@@ -387,12 +387,13 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       T Nv = T(0), Nw = T(0), Nby = T(0), Nbz = T(0);
       if (dstar) {
         sg = bn > T(0) ? T(1) : (bn < T(0) ? T(-1) : T(0));
-        sqL = tsqrt(rsL);
-        sqR = tsqrt(rsR);
+        const T yL = trsqrt(rsL), yR = trsqrt(rsR);
+        sqL = rsL * yL;
+        sqR = rsR * yR;
         abn = tabs(bn);
-        SsL = SM - abn / sqL;
-        SsR = SM + abn / sqR;
-        isum = T(1) / (sqL + sqR);
+        SsL = SM - abn * yL;
+        SsR = SM + abn * yR;
+        isum = trcp(sqL + sqR);
         Nv = sqL * vsL + sqR * vsR + (bysR - bysL) * sg;
         Nw = sqL * wsL + sqR * wsR + (bzsR - bzsL) * sg;
         Nby = sqL * bysR + sqR * bysL + sqL * sqR * (vsR - vsL) * sg;
@@ -728,7 +729,7 @@ CTMHD_HD void face_outputs_adj(const FState<T>& L, const FState<T>& R, T bn, T g
                         fast_speed(R.rho, R.p, bn, R.bt1, R.bt2, gamma));
     const T SL = tmin(L.un, R.un) - cmax, SR = tmax(L.un, R.un) + cmax;
     const T ap = tmax(T(0), SR), am = tmax(T(0), -SL);
-    const T isum = T(1) / (ap + am);
+    const T isum = trcp(ap + am);
     const T us = (ap * L.un + am * R.un) * isum;
     apb += usb * (L.un - us) * isum;
     amb += usb * (R.un - us) * isum;

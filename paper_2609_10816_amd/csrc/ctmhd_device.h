@@ -193,7 +193,7 @@ __device__ __forceinline__ void cell_load(const State& S, const Geom& G, int s, 
 __device__ __forceinline__ void raw_prim(const CellRaw& R, double gamma, double& rho, double u[3],
                                          double& p, double bc[3]) {
   rho = R.c[0];
-  double ir = 1.0 / rho;
+  double ir = trcp(rho);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     u[d] = R.c[1 + d] * ir;
@@ -375,6 +375,28 @@ __device__ __forceinline__ T joule(const State& S, const Geom& G, int s, int a, 
   return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
 }
 
+// The same Joule flux at the x_a face between cells lo and hi from values the
+// face pass already holds: each cell's transverse face fields
+// t = {b_b lower, b_b upper, b_c lower, b_c upper} (b, c cyclic after a),
+// the face's normal field bn = b_a, and its four in-plane neighbours
+// nb = {b_a at -x_b, +x_b, -x_c, +x_c}.  Every edge current, cell-averaged
+// field and product is formed as in joule().
+template <typename T>
+__device__ __forceinline__ T joule_pair(const Geom& G, int a, const double lo[4],
+                                        const double hi[4], double bn, const double nb[4], T eta) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  // eta j_b at the edges s and s + x_c, eta j_c at the edges s and s + x_b
+  T eb = T(0.5) * (eta * (T)((bn - nb[2]) * G.idx[c] - (hi[2] - lo[2]) * G.idx[a]) +
+                   eta * (T)((nb[3] - bn) * G.idx[c] - (hi[3] - lo[3]) * G.idx[a]));
+  T ec = T(0.5) * (eta * (T)((hi[0] - lo[0]) * G.idx[a] - (bn - nb[0]) * G.idx[b]) +
+                   eta * (T)((hi[1] - lo[1]) * G.idx[a] - (nb[1] - bn) * G.idx[b]));
+  T bbl = (T)(0.5 * (lo[0] + lo[1]));
+  T bbr = (T)(0.5 * (hi[0] + hi[1]));
+  T bcl = (T)(0.5 * (lo[2] + lo[3]));
+  T bcr = (T)(0.5 * (hi[2] + hi[3]));
+  return eb * (T(0.5) * (bcl + bcr)) - ec * (T(0.5) * (bbl + bbr));
+}
+
 // ---------------------------------------------------------------------------
 // Face pass (Sec. 2.2, eqs. emf:alpha-pm, emf:q26-facevel).
 // ---------------------------------------------------------------------------
@@ -415,10 +437,9 @@ __device__ __forceinline__ void face_local(const State& S, const Geom& G, int s,
 }
 
 template <typename T, int RIEMANN>
-__device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, const Work<T>& W,
-                                               const FacePlan& FP, int s, const int s3[3], int a,
-                                               int stage, const T qL[7], const T qR[7],
-                                               double bn_d, double gamma_d, double eta_d) {
+__device__ __forceinline__ int solve_and_store(const Work<T>& W, int s, int a, int stage,
+                                               const T qL[7], const T qR[7], double bn_d,
+                                               double gamma_d, T jflux) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   // the solver's arithmetic type: T, or float64 for kHLLD64 / kLLF64
   using RT = typename std::conditional<(RIEMANN >= kHLLD64), double, T>::type;
@@ -438,14 +459,7 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
   }
 #pragma unroll
   for (int m = 0; m < 5; ++m) F[m] = (T)Fr[m];
-  if (eta_d > 0.0) {
-    // faces read by the update: [g, g+n] along the normal, [g, g+n) across
-    bool in_upd = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      in_upd = in_upd && s3[d] >= FP.ulo[d] && s3[d] < FP.ulo[d] + FP.ulen[d] + (d == a ? 1 : 0);
-    if (in_upd) F[4] += joule<T>(S, G, s, a, (T)eta_d);
-  }
+  F[4] += jflux;  // Joule energy flux (zero outside the faces the update reads, or eta = 0)
   // Streaming stores: no later access of this kernel reads them, and keeping
   // them out of the L2 leaves it to the state rows the marches re-read.
   __builtin_nontemporal_store(F[0], &W.F[stage][a][0][s]);
@@ -455,8 +469,38 @@ __device__ __forceinline__ int solve_and_store(const State& S, const Geom& G, co
   __builtin_nontemporal_store(F[4], &W.F[stage][a][4][s]);
   __builtin_nontemporal_store(ap, &W.ap[a][s]);
   __builtin_nontemporal_store(am, &W.am[a][s]);
-  __builtin_nontemporal_store((ap * (T)L.un + am * (T)R.un) / (ap + am), &W.us[a][s]);
+  __builtin_nontemporal_store((ap * (T)L.un + am * (T)R.un) * trcp(ap + am), &W.us[a][s]);
   return fb;
+}
+
+// Whether the face pass's x_a face at s3 is one the update reads: [g, g+n]
+// along the normal, [g, g+n) across (the Joule flux is needed only there).
+__device__ __forceinline__ bool face_in_update(const FacePlan& FP, const int s3[3], int a) {
+  bool in_upd = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    in_upd = in_upd && s3[d] >= FP.ulo[d] && s3[d] < FP.ulo[d] + FP.ulen[d] + (d == a ? 1 : 0);
+  return in_upd;
+}
+
+// A cell's transverse face fields for the normal a, as joule_pair takes them.
+__device__ __forceinline__ void cell_tfaces(const CellRaw& R, int a, double t[4]) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  t[0] = R.bl[b];
+  t[1] = R.bh[b];
+  t[2] = R.bl[c];
+  t[3] = R.bh[c];
+}
+
+// The Joule flux of the x_a face at s between cells with transverse fields lo
+// and hi (normal field bn), loading the face's four in-plane neighbours.
+template <typename T>
+__device__ __forceinline__ T joule_face(const State& S, const Geom& G, int s, int a,
+                                        const double lo[4], const double hi[4], double bn, T eta) {
+  const int sb = gstride(G, (a + 1) % 3), sc = gstride(G, (a + 2) % 3);
+  const double* ba = S.b[a];
+  const double nb[4] = {ba[s - sb], ba[s + sb], ba[s - sc], ba[s + sc]};
+  return joule_pair<T>(G, a, lo, hi, bn, nb, eta);
 }
 
 // Value of the neighbouring lane (l - 1 for lane_prev, l + 1 for lane_next)
@@ -541,11 +585,18 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
     T qL[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) qL[k] = lane_prev(qp[k]);
+    // transverse face fields of this lane's cell and of the cell below it
+    double thi[4], tlo[4];
+    cell_tfaces(cur, 0, thi);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tlo[k] = lane_prev(thi[k]);
     const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
     if (face) {
       const int s3[3] = {x, y, z};
-      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, 0, stage, qL, qm, cur.bl[0], gamma,
-                                         eta);
+      T jf = T(0);
+      if (eta > 0.0 && face_in_update(FP, s3, 0))
+        jf = joule_face<T>(S, G, s, 0, tlo, thi, cur.bl[0], (T)eta);
+      nfb += solve_and_store<T, RIEMANN>(W, s, 0, stage, qL, qm, cur.bl[0], gamma, jf);
     }
   }
 }
@@ -578,6 +629,13 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
   CellRaw nxt;
   cell_load(S, G, base + q * sa, nxt);
   double bn_next = 0.0;  // read only for the faces f0 .. f1-1
+  // Joule flux of face q (between cells q-1 and q), formed when cell q
+  // arrives and used r pushes later, when the face is solved: jd[k] holds the
+  // flux of face q-k
+  double tprev[4] = {0.0, 0.0, 0.0, 0.0};
+  T jd[r + 1];
+#pragma unroll
+  for (int k = 0; k <= r; ++k) jd[k] = T(0);
   for (; q <= f1 - 1 + r; ++q) {
     const CellRaw cur = nxt;
     const double bn = bn_next;
@@ -585,6 +643,18 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
       cell_load(S, G, base + (q + 1) * sa, nxt);
       if (q + 1 - r >= f0) bn_next = S.b[A][base + (q + 1 - r) * sa];
     }
+#pragma unroll
+    for (int k = r; k > 0; --k) jd[k] = jd[k - 1];
+    jd[0] = T(0);
+    double tcur[4];
+    cell_tfaces(cur, A, tcur);
+    if (eta > 0.0 && q >= f0 && q < f1) {
+      s3[A] = q;
+      if (face_in_update(FP, s3, A))
+        jd[0] = joule_face<T>(S, G, base + q * sa, A, tprev, tcur, cur.bl[A], (T)eta);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tprev[k] = tcur[k];
     T v[7];
     face_local_raw<T>(cur, A, gamma, v);
     const int cell = q - r;  // completed by this push
@@ -592,9 +662,8 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
 #pragma unroll
     for (int k = 0; k < 7; ++k) rs[k].push(v[k], qm[k], qp[k]);
     if (cell >= f0) {
-      s3[A] = cell;
       const int s = base + cell * sa;
-      nfb += solve_and_store<T, RIEMANN>(S, G, W, FP, s, s3, A, stage, qprev, qm, bn, gamma, eta);
+      nfb += solve_and_store<T, RIEMANN>(W, s, A, stage, qprev, qm, bn, gamma, jd[r]);
     }
 #pragma unroll
     for (int k = 0; k < 7; ++k) qprev[k] = qp[k];

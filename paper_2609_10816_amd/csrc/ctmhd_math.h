@@ -41,6 +41,51 @@ CTMHD_HD float tsqrt(float x) { return __builtin_sqrtf(x); }
 CTMHD_HD bool tfinite(double x) { return __builtin_isfinite(x); }
 CTMHD_HD bool tfinite(float x) { return __builtin_isfinite(x); }
 
+// Reciprocal and reciprocal square root of a finite, normal x (x > 0 for
+// trsqrt), within about one unit in the last place.  On the GPU: the
+// hardware estimates (v_rcp_f64, v_rsq_f64 to about 2^-23; v_rcp_f32,
+// v_rsq_f32 to one unit) refined by Newton steps, two in double and one in
+// float, against about twice the instructions of the correctly rounded
+// division and square root, which also handle denormal and infinite
+// operands.  A zero x gives NaN (the callers reject such a state anyway).  On
+// the host (CPU checks of the derivative code): the plain operations.
+CTMHD_HD double trcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+#else
+  return 1.0 / x;
+#endif
+}
+CTMHD_HD float trcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+#else
+  return 1.0f / x;
+#endif
+}
+CTMHD_HD double trsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // y <- y + y (1/2 - (x/2) y^2)
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+  return __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+#else
+  return 1.0 / __builtin_sqrt(x);
+#endif
+}
+CTMHD_HD float trsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float y = __builtin_amdgcn_rsqf(x);
+  return __builtin_fmaf(y, __builtin_fmaf(-0.5f * x * y, y, 0.5f), y);
+#else
+  return 1.0f / __builtin_sqrtf(x);
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // 1D reconstruction (Sec. 2.2).  q[0..4] centred on q[2]; returns the values
 // at the lower (qm) and upper (qp) face of the centre cell.  PLM uses the
@@ -189,7 +234,7 @@ CTMHD_HD void recon_iface(const T* q, T& lo, T& hi) {
 // ---------------------------------------------------------------------------
 template <typename T>
 CTMHD_HD T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
-  T irho = T(1) / rho;
+  T irho = trcp(rho);
   T gp = gamma * p;
   T a = (gp + bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
   T disc = a * a - T(4) * gp * bn * bn * irho * irho;
@@ -267,11 +312,11 @@ CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
   const T bn2 = bn * bn;
   T dL = SL - L.un, dR = SR - R.un;
   T mL = dL * L.rho, mR = dR * R.rho;  // (S - u) rho
-  T iden = T(1) / (mR - mL);
+  T iden = trcp(mR - mL);
   T SM = (mR * R.un - mL * L.un - pTR + pTL) * iden;
   T pTs = (mR * pTL - mL * pTR + mL * mR * (R.un - L.un)) * iden;
   T dsL = SL - SM, dsR = SR - SM;
-  T idsL = T(1) / dsL, idsR = T(1) / dsR;
+  T idsL = trcp(dsL), idsR = trcp(dsR);
   T rsL = mL * idsL, rsR = mR * idsR;
 
   // star transverse states
@@ -280,7 +325,7 @@ CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
     T q = mL * dsL - bn2;
     T ref = tabs(mL * dsL) + bn2;
     bool deg = tabs(q) <= T(1e-12) * ref;
-    T iq = T(1) / q;
+    T iq = trcp(q);
     T fv = bn * (SM - L.un) * iq;
     T fb = (mL * dL - bn2) * iq;
     vsL = deg ? L.ut1 : L.ut1 - L.bt1 * fv;
@@ -292,7 +337,7 @@ CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
     T q = mR * dsR - bn2;
     T ref = tabs(mR * dsR) + bn2;
     bool deg = tabs(q) <= T(1e-12) * ref;
-    T iq = T(1) / q;
+    T iq = trcp(q);
     T fv = bn * (SM - R.un) * iq;
     T fb = (mR * dR - bn2) * iq;
     vsR = deg ? R.ut1 : R.ut1 - R.bt1 * fv;
@@ -318,7 +363,7 @@ CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
 #pragma unroll
       for (int m = 0; m < 5; ++m) F[m] = FR[m];
     } else {
-      T iw = T(1) / (SR - SL);
+      T iw = trcp(SR - SL);
 #pragma unroll
       for (int m = 0; m < 5; ++m) F[m] = (SR * FL[m] - SL * FR[m] + SL * SR * (UR[m] - UL[m])) * iw;
     }
@@ -336,11 +381,13 @@ CTMHD_HD int hlld_flux(const FState<T>& L, const FState<T>& R, T bn, T gamma,
   }
   if (!(bn2 <= T(1e-12) * pTs)) {
     T sg = bn > T(0) ? T(1) : (bn < T(0) ? T(-1) : T(0));
-    T sqL = tsqrt(rsL), sqR = tsqrt(rsR);
+    // rs > 0 here: sqrt(rs) = rs / sqrt(rs)
+    T yL = trsqrt(rsL), yR = trsqrt(rsR);
+    T sqL = rsL * yL, sqR = rsR * yR;
     T abn = tabs(bn);
-    SsL = SM - abn / sqL;
-    SsR = SM + abn / sqR;
-    T isum = T(1) / (sqL + sqR);
+    SsL = SM - abn * yL;
+    SsR = SM + abn * yR;
+    T isum = trcp(sqL + sqR);
     T vss = (sqL * vsL + sqR * vsR + (bysR - bysL) * sg) * isum;
     T wss = (sqL * wsL + sqR * wsR + (bzsR - bzsL) * sg) * isum;
     T byss = (sqL * bysR + sqR * bysL + sqL * sqR * (vsR - vsL) * sg) * isum;
