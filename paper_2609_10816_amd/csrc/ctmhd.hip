@@ -113,7 +113,8 @@ int step_box(const ctmhd_params* p, const ctmhd_box* box, double* const cons[5],
     if ((rc = run_stage<T, RECON>(st, p, G, W, FP, A, A, H, 0, sres, dg))) return rc;
     if ((rc = run_stage<T, RECON>(st, p, G, W, FP, H, A, B, 1, sres, dg))) return rc;
     // a stopped step leaves the state where it was: carry it to the next buffer
-    LAUNCH(k_copy, nblocks(G.elems), B, A, G.elems, W.stop);
+    // (a capped grid: the launch almost always finds nothing to do)
+    LAUNCH(k_copy, fix_blocks(G.elems), B, A, G.elems, W.stop);
     State tmp = A;
     A = B;
     B = tmp;

@@ -158,14 +158,15 @@ __global__ void k_wrap(State S, Geom G, const int* stop) {
   wrap_at(S, G, gidx());
 }
 
+// Grid-stride copy of a state (any grid size).
 __global__ void k_copy(State dst, State src, int elems, const int* only_if_stop) {
   if (only_if_stop && !*only_if_stop) return;
-  int t = gidx();
-  if (t >= elems) return;
+  for (int t = gidx(); t < elems; t += gridDim.x * blockDim.x) {
 #pragma unroll
-  for (int m = 0; m < 5; ++m) dst.c[m][t] = src.c[m][t];
+    for (int m = 0; m < 5; ++m) dst.c[m][t] = src.c[m][t];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) dst.b[a][t] = src.b[a][t];
+    for (int a = 0; a < 3; ++a) dst.b[a][t] = src.b[a][t];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -492,15 +493,16 @@ __device__ __forceinline__ void cell_tfaces(const CellRaw& R, int a, double t[4]
   t[3] = R.bh[c];
 }
 
-// The Joule flux of the x_a face at s between cells with transverse fields lo
-// and hi (normal field bn), loading the face's four in-plane neighbours.
-template <typename T>
-__device__ __forceinline__ T joule_face(const State& S, const Geom& G, int s, int a,
-                                        const double lo[4], const double hi[4], double bn, T eta) {
+// The four in-plane neighbours of the normal field of the x_a face at s, as
+// joule_pair takes them.
+__device__ __forceinline__ void face_nb(const State& S, const Geom& G, int s, int a,
+                                        double nb[4]) {
   const int sb = gstride(G, (a + 1) % 3), sc = gstride(G, (a + 2) % 3);
   const double* ba = S.b[a];
-  const double nb[4] = {ba[s - sb], ba[s + sb], ba[s - sc], ba[s + sc]};
-  return joule_pair<T>(G, a, lo, hi, bn, nb, eta);
+  nb[0] = ba[s - sb];
+  nb[1] = ba[s + sb];
+  nb[2] = ba[s - sc];
+  nb[3] = ba[s + sc];
 }
 
 // Value of the neighbouring lane (l - 1 for lane_prev, l + 1 for lane_next)
@@ -566,16 +568,32 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
     const int xc = x < 0 ? 0 : (x > G.N[0] - 2 ? G.N[0] - 2 : x);  // loads stay in the box
     return xc + G.st[1] * y + G.st[2] * z;
   };
+  // whether this lane's face of an item needs the Joule flux; if so its
+  // normal-field neighbours are loaded with the item's cell
+  auto joule_nb = [&](int x, int y, int z, int s, double nb[4]) {
+    const int s3[3] = {x, y, z};
+    const bool j = eta > 0.0 && lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] &&
+                   x < FP.lo[0] + FP.nf[0] && face_in_update(FP, s3, 0);
+    if (j) face_nb(S, G, s, 0, nb);
+    return j;
+  };
   int xn, yn, zn;
   int sn = locate(it, xn, yn, zn);
   CellRaw nxt;
   cell_load(S, G, sn, nxt);
+  double nb_nxt[4] = {0.0, 0.0, 0.0, 0.0};
+  bool j_nxt = joule_nb(xn, yn, zn, sn, nb_nxt);
   for (; it < end; ++it) {  // wavefront-uniform trip count (cross-lane shuffles below)
     const CellRaw cur = nxt;
     const int x = xn, y = yn, z = zn, s = sn;
+    double nb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nb[k] = nb_nxt[k];
+    const bool jf_need = j_nxt;
     if (it + 1 < end) {
       sn = locate(it + 1, xn, yn, zn);
       cell_load(S, G, sn, nxt);
+      j_nxt = joule_nb(xn, yn, zn, sn, nb_nxt);
     }
     T v[7];
     face_local_raw<T>(cur, 0, gamma, v);
@@ -592,10 +610,7 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
     for (int k = 0; k < 4; ++k) tlo[k] = lane_prev(thi[k]);
     const bool face = lane >= r + 1 && lane <= 63 - r && x >= FP.lo[0] && x < FP.lo[0] + FP.nf[0];
     if (face) {
-      const int s3[3] = {x, y, z};
-      T jf = T(0);
-      if (eta > 0.0 && face_in_update(FP, s3, 0))
-        jf = joule_face<T>(S, G, s, 0, tlo, thi, cur.bl[0], (T)eta);
+      const T jf = jf_need ? joule_pair<T>(G, 0, tlo, thi, cur.bl[0], nb, (T)eta) : T(0);
       nfb += solve_and_store<T, RIEMANN>(W, s, 0, stage, qL, qm, cur.bl[0], gamma, jf);
     }
   }
@@ -636,23 +651,32 @@ __device__ void faces_march(const State& S, const Geom& G, const Work<T>& W, con
   T jd[r + 1];
 #pragma unroll
   for (int k = 0; k <= r; ++k) jd[k] = T(0);
+  // the normal-field neighbours of face q+1 are loaded with cell q+1 when
+  // that face needs the Joule flux
+  double nb_next[4] = {0.0, 0.0, 0.0, 0.0};
+  bool j_next = false;
   for (; q <= f1 - 1 + r; ++q) {
     const CellRaw cur = nxt;
     const double bn = bn_next;
+    double nb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nb[k] = nb_next[k];
+    const bool jq = j_next;
     if (q < f1 - 1 + r) {
       cell_load(S, G, base + (q + 1) * sa, nxt);
       if (q + 1 - r >= f0) bn_next = S.b[A][base + (q + 1 - r) * sa];
+      j_next = false;
+      if (eta > 0.0 && q + 1 >= f0 && q + 1 < f1) {
+        s3[A] = q + 1;
+        j_next = face_in_update(FP, s3, A);
+        if (j_next) face_nb(S, G, base + (q + 1) * sa, A, nb_next);
+      }
     }
 #pragma unroll
     for (int k = r; k > 0; --k) jd[k] = jd[k - 1];
-    jd[0] = T(0);
     double tcur[4];
     cell_tfaces(cur, A, tcur);
-    if (eta > 0.0 && q >= f0 && q < f1) {
-      s3[A] = q;
-      if (face_in_update(FP, s3, A))
-        jd[0] = joule_face<T>(S, G, base + q * sa, A, tprev, tcur, cur.bl[A], (T)eta);
-    }
+    jd[0] = jq ? joule_pair<T>(G, A, tprev, tcur, cur.bl[A], nb, (T)eta) : T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) tprev[k] = tcur[k];
     T v[7];
