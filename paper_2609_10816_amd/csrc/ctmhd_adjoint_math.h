@@ -267,8 +267,9 @@ CTMHD_HD void llf_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamma
   }
   const bool left = xL >= xR;
   const T xLb = left ? sbar : T(0), xRb = left ? T(0) : sbar;
-  Lb.un += (L.un > T(0) ? T(1) : (L.un < T(0) ? T(-1) : T(0))) * xLb;
-  Rb.un += (R.un > T(0) ? T(1) : (R.un < T(0) ? T(-1) : T(0))) * xRb;
+  // |un|: the derivative of x < 0 ? -x : x (+1 at zero)
+  Lb.un += (L.un < T(0) ? T(-1) : T(1)) * xLb;
+  Rb.un += (R.un < T(0) ? T(-1) : T(1)) * xRb;
   fast_speed_adj(L.rho, L.p, bn, L.bt1, L.bt2, gamma, xLb, Lb.rho, Lb.p, bnb, Lb.bt1, Lb.bt2);
   fast_speed_adj(R.rho, R.p, bn, R.bt1, R.bt2, gamma, xRb, Rb.rho, Rb.p, bnb, Rb.bt1, Rb.bt2);
   phys_flux_adj(L, bn, gm1inv, ULb, FLb, T(0), Lb, bnb);
@@ -695,15 +696,21 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       bnb += T(2) * bn * bn2b;
     }
   }
-  // SL = min(unL, unR) - cmax, SR = max(unL, unR) + cmax
+  // SL = min(unL, unR) - cmax, SR = max(unL, unR) + cmax.  At unL = unR the
+  // minimum and the maximum have no unique derivative; both go to the left
+  // state, the convention of the selections a <= b ? a : b and a >= b ? a : b
+  // (as for cmax and the limiters).  Such ties are not rare: PLM-MC gives
+  // exactly equal face values next to every extremum whose neighbour's slope
+  // is the doubled one-sided difference.
   const T cmaxb = SRbar - SLbar;
-  if (L.un <= R.un) {
+  if (L.un <= R.un)
     Lb.un += SLbar;
-    Rb.un += SRbar;
-  } else {
+  else
     Rb.un += SLbar;
+  if (L.un >= R.un)
     Lb.un += SRbar;
-  }
+  else
+    Rb.un += SRbar;
   if (cfL >= cfR)
     fast_speed_adj(L.rho, L.p, bn, L.bt1, L.bt2, gamma, cmaxb, Lb.rho, Lb.p, bnb, Lb.bt1, Lb.bt2);
   else
