@@ -385,6 +385,9 @@ __device__ __forceinline__ T joule(const State& S, const Geom& G, int s, int a, 
 template <typename T>
 __device__ __forceinline__ T joule_pair(const Geom& G, int a, const double lo[4],
                                         const double hi[4], double bn, const double nb[4], T eta) {
+  // no fused multiply-adds: the single-box and batched face kernels inline
+  // this into different code, and must give the same bits
+#pragma clang fp contract(off)
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   // eta j_b at the edges s and s + x_c, eta j_c at the edges s and s + x_b
   T eb = T(0.5) * (eta * (T)((bn - nb[2]) * G.idx[c] - (hi[2] - lo[2]) * G.idx[a]) +
