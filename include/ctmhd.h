@@ -112,7 +112,10 @@ typedef struct ctmhd_box {
 } ctmhd_box;
 
 /* Ghost layers the scheme needs: reconstruction half-width + 2 (PC 2, PLM 3,
- * PPM 4).  Returns a negative code for bad parameters. */
+ * PPM 4).  Sec. 2.3.1 (last paragraph): the edge EMFs reconstruct face
+ * quantities along the transverse axes, so the Riemann problem is solved in
+ * ghost zones next to the box too, and those faces' reconstructions reach
+ * further out.  Returns a negative code for bad parameters. */
 int ctmhd_required_ghosts(const ctmhd_params* p);
 
 /* Elements (not bytes) of one field array of a box: prod(n_d + 2 ng). */
