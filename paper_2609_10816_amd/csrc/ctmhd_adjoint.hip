@@ -313,30 +313,38 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
   for (int m = 0; m < 5; ++m) Fl[m] = X.fa[a][m][t];
   const double apb = X.fa[a][5][t], amb = X.fa[a][6][t], usb = X.fa[a][7][t];
+  constexpr int r = recon_halfwidth(RECON);
+  const bool inr = s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1;
+  // The stencils of the face-local states, loaded together with the inputs
+  // above so that the thread waits for memory once: the six-point sequence
+  // t - 3 sa .. t + 2 sa of each reconstructed primitive (the offsets fall
+  // back to t where the stencil would leave the box; such faces are skipped).
+  const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+  double w[7][6];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const double* P = X.prim[vmap[q]];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) w[q][m] = stencil_uses<RECON>(m) ? P[inr ? t + (m - 3) * sa : t] : 0.0;
+  }
+  const double bn = S.b[a][t];
+  __builtin_amdgcn_sched_barrier(0);
   FState<double> Lb, Rb;
   fstate_zero(Lb);
   fstate_zero(Rb);
   double bnb = 0.0;
   const bool any = Fl[0] != 0.0 || Fl[1] != 0.0 || Fl[2] != 0.0 || Fl[3] != 0.0 ||
                    Fl[4] != 0.0 || usb != 0.0 || apb != 0.0 || amb != 0.0;
-  constexpr int r = recon_halfwidth(RECON);
-  if (any && s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1) {
-    // face-local states as the forward face kernel forms them
-    const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
+  if (any && inr) {
+    // face-local states as the forward face kernel forms them: the upper
+    // value of cell t - sa and the lower value of cell t (shared slopes for
+    // PPM)
     double qL[7], qR[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      const double* P = X.prim[vmap[q]];
-      // upper value of cell t - sa and lower value of cell t from the
-      // six-point sequence t - 3 sa .. t + 2 sa (shared slopes for PPM)
-      double w[6];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) w[m] = stencil_uses<RECON>(m) ? P[t + (m - 3) * sa] : 0.0;
-      recon_iface<RECON>(w, qL[q], qR[q]);
-    }
+    for (int q = 0; q < 7; ++q) recon_iface<RECON>(w[q], qL[q], qR[q]);
     const FState<double> L{qL[0], qL[1], qL[2], qL[3], qL[4], qL[5], qL[6]};
     const FState<double> R{qR[0], qR[1], qR[2], qR[3], qR[4], qR[5], qR[6]};
-    face_outputs_adj<RIEMANN>(L, R, S.b[a][t], gamma, Fl, apb, amb, usb, Lb, Rb, bnb);
+    face_outputs_adj<RIEMANN>(L, R, bn, gamma, Fl, apb, amb, usb, Lb, Rb, bnb);
   }
   X.fa[a][0][t] = Lb.rho;
   X.fa[a][1][t] = Lb.un;
@@ -363,9 +371,9 @@ __global__ void __launch_bounds__(kBlock)
 // the box.  Each centre's
 // reconstruction is reversed once: along x by the 64 lanes of a wavefront
 // (stencil values and the five contributions by cross-lane shuffles), along y
-// and z by a thread marching through a segment of a line with the values and
-// the open partial sums in registers.  Centres whose stencil leaves the box
-// carry no adjoint.
+// and z by a thread that takes a segment of a line and holds its values, the
+// adjoints of its centres and the partial sums in registers.  Centres whose
+// stencil leaves the box carry no adjoint.
 // ---------------------------------------------------------------------------
 struct LineJob {
   const double* X;
@@ -377,8 +385,12 @@ struct LineJob {
 constexpr int kMaxLineJobs = 8;
 struct LineJobs {
   LineJob j[kMaxLineJobs];
-  int chunk;  // positions per marching thread (y, z)
 };
+// Positions per thread of the y / z gathers.
+#ifndef CTMHD_LINE_CHUNK
+#define CTMHD_LINE_CHUNK 8
+#endif
+constexpr int kLineChunk = CTMHD_LINE_CHUNK;
 
 template <int RECON>
 __global__ void __launch_bounds__(kBlock) k_line_x(Geom G, LineJobs J, const int* stop) {
@@ -422,55 +434,65 @@ template <int RECON, int D>
 __global__ void __launch_bounds__(kBlock) k_line_march(Geom G, LineJobs J, const int* stop) {
   if (*stop) return;
   constexpr int r = recon_halfwidth(RECON);
-  constexpr int W = 2 * r + 1;
+  constexpr int CH = kLineChunk;
+  constexpr int NC = CH + 2 * r;  // centres whose stencil holds a position of the chunk
+  constexpr int NV = CH + 4 * r;  // values the stencils of those centres read
   constexpr int C = D == 1 ? 2 : 1;  // transverse axes: x and C
   const LineJob& L = J.j[blockIdx.z];
   const int lane = blockIdx.x * kBlock + threadIdx.x;
   if (lane >= G.N[0] * G.N[C]) return;
   const int base = lane % G.N[0] + (lane / G.N[0]) * G.st[C];
   const int st = G.st[D], N = G.N[D];
-  const int p0 = blockIdx.y * J.chunk;
-  const int p1 = p0 + J.chunk < N ? p0 + J.chunk : N;
-  // val[j], acc[j]: position c - r + j for the current centre c
-  double val[W], acc[W];
+  const int p0 = blockIdx.y * CH;
+  auto clampN = [N](int p) { return p < 0 ? 0 : (p >= N ? N - 1 : p); };
+  // Every load of the chunk is issued before the first reverse, so that a
+  // thread waits for memory once (indices clamped into the line): val[j] is
+  // position p0 - 2r + j (only centres whose stencil lies in the line read
+  // it), lo[i] / up[i] the adjoints of centre p0 - r + i, old[k] the output
+  // at p0 + k of an accumulating job.
+  double val[NV], lo[NC], up[NC], old[CH];
 #pragma unroll
-  for (int j = 0; j < W - 1; ++j) {
-    const int p = p0 - 2 * r + j;
-    val[j] = p >= 0 && p < N ? L.X[base + p * st] : 0.0;
-    acc[j] = 0.0;
-  }
-  acc[W - 1] = 0.0;
-  for (int c = p0 - r; c <= p1 - 1 + r; ++c) {
-    {
-      const int p = c + r;
-      val[W - 1] = p >= 0 && p < N ? L.X[base + p * st] : 0.0;
-    }
+  for (int j = 0; j < NV; ++j) val[j] = L.X[base + clampN(p0 - 2 * r + j) * st];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const int c = p0 - r + i;
     const bool valid = c - r >= 0 && c + r < N;
-    const double lo = valid ? L.LO[base + c * st] : 0.0;
-    const double up = valid && c + 1 < N ? L.UP[base + (c + 1) * st] : 0.0;
-    if (lo != 0.0 || up != 0.0) {
+    const double l = L.LO[base + clampN(c) * st];
+    const double h = L.UP[base + clampN(c + 1) * st];
+    lo[i] = valid ? l : 0.0;
+    up[i] = valid && c + 1 < N ? h : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < CH; ++k) old[k] = 0.0;
+  if (L.acc) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k) old[k] = L.out[base + clampN(p0 + k) * st];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // centres in increasing order, each adding its stencil's adjoints
+  double acc[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    if (lo[i] != 0.0 || up[i] != 0.0) {
       double q[5], qb[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        q[m] = (m - 2 >= -r && m - 2 <= r) ? val[m - 2 + r] : 0.0;
+        q[m] = (m - 2 >= -r && m - 2 <= r) ? val[i + m - 2 + r] : 0.0;
         qb[m] = 0.0;
       }
-      recon_cell_adj5<RECON>(q, lo, up, qb);
+      recon_cell_adj5<RECON>(q, lo[i], up[i], qb);
 #pragma unroll
-      for (int m = 0; m < 5; ++m)
-        if (m - 2 >= -r && m - 2 <= r) acc[m - 2 + r] += qb[m];
+      for (int m = 0; m < 5; ++m) {
+        const int k = i - r + m - 2;  // chunk position of stencil point m
+        if (m - 2 >= -r && m - 2 <= r && k >= 0 && k < CH) acc[k] += qb[m];
+      }
     }
-    const int p = c - r;  // complete: no later centre reads it
-    if (p >= p0 && p < p1) {
-      double* o = L.out + base + p * st;
-      *o = L.acc ? *o + acc[0] : acc[0];
-    }
+  }
 #pragma unroll
-    for (int j = 0; j < W - 1; ++j) {
-      val[j] = val[j + 1];
-      acc[j] = acc[j + 1];
-    }
-    acc[W - 1] = 0.0;
+  for (int k = 0; k < CH; ++k) {
+    if (p0 + k < N) L.out[base + (p0 + k) * st] = L.acc ? old[k] + acc[k] : acc[k];
   }
 }
 
@@ -486,7 +508,7 @@ int launch_lines(hipStream_t st, const Geom& G, int D, const LineJobs& J, int nj
   } else {
     const int C = D == 1 ? 2 : 1;
     const int blocks = (G.N[0] * G.N[C] + kBlock - 1) / kBlock;
-    const dim3 grid(blocks, (G.N[D] + J.chunk - 1) / J.chunk, njobs);
+    const dim3 grid(blocks, (G.N[D] + kLineChunk - 1) / kLineChunk, njobs);
     if (D == 1)
       hipLaunchKernelGGL((k_line_march<RECON, 1>), grid, dim3(kBlock), 0, st, G, J, stop);
     else
@@ -509,7 +531,6 @@ int face_lines(hipStream_t st, const Geom& G, const State& S, const Work<double>
                const AdjArrays& X, bool ustar, const int* stop) {
   for (int D = 0; D < 3; ++D) {
     LineJobs J{};
-    J.chunk = 16;
     int n = 0;
     for (int a = 0; a < 3; ++a) {
       const int b = (a + 1) % 3, c = (a + 2) % 3;
@@ -541,7 +562,6 @@ int cell_lines(hipStream_t st, const Geom& G, const AdjArrays& X, double* const 
     const int b = (a + 1) % 3, c = (a + 2) % 3;
     const int vmap[7] = {0, 1 + a, 1 + b, 1 + c, 4, 5 + b, 5 + c};
     LineJobs J{};
-    J.chunk = 16;
     for (int q = 0; q < 7; ++q) {
       // the left state of face e is the upper value of cell e - st, the right
       // state the lower value of cell e; axis 0 writes its seven primitives
@@ -633,7 +653,6 @@ int cell_corner_adj(hipStream_t st, const Geom& G, const Work<double>& W, const 
   LAUNCH((k_adj_iface<RECON, EMF>), nb, G, W, X, stop);
   for (int D = 0; D < 3; ++D) {
     LineJobs J{};
-    J.chunk = 16;
     int n = 0;
     for (int c = 0; c < 3; ++c)
       for (int f = 0; f < NF; ++f)
@@ -662,7 +681,6 @@ int cell_corner_adj(hipStream_t st, const Geom& G, const Work<double>& W, const 
         }
     while (np > 0) {  // launches with distinct destinations
       LineJobs J{};
-      J.chunk = 16;
       int n = 0;
       bool used[3] = {false, false, false};
       for (int i = 0; i < np;) {
