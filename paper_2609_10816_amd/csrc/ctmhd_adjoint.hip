@@ -23,9 +23,9 @@
 //   cells  face-local state adjoints gathered through the reverse of the
 //          cell reconstructions (B25a: also the cell-EMF adjoint, gathered
 //          through the reverse of both two-step reconstructions, onto u and
-//          the cell field), then primitive -> conserved (Sec. 2.2,
-//          eq. state:primitive)
-//   fields cell-centred field adjoints onto the two faces of each cell
+//          the cell field) into primitive adjoints
+//   fields primitive -> conserved (Sec. 2.2, eq. state:primitive), and the
+//          cell-centred field adjoints onto the two faces of each cell
 //   fold   every ghost copy's adjoint added to its interior cell or face
 // The forward face arrays (alpha+-, u*) of the state being differentiated come
 // from the forward face kernel.
@@ -39,15 +39,15 @@ struct PrimPtrs {
 };
 
 struct AdjArrays {
-  double* v[8];        // adjoint of D: 5 cell fields, 3 face fields; 0 outside the interior
+  double* v[8];        // adjoint of D: 5 cell fields, 3 face fields (vval)
+  double vs;           // scale of v
+  double* ca[5];       // conserved-field adjoint per cell (k_adj_cons)
   double* prim[8];     // rho, u0, u1, u2, p, bc0, bc1, bc2 of the state
-  double* ea[3][13];   // per edge direction: adjoints of uaB uaT ubL ubR baB baT bbL bbR
-                       // apa ama apb amb and of the edge EMF
+  double* ea[3][12];   // per edge direction: adjoints of uaB uaT ubL ubR baB baT bbL bbR
+                       // apa ama apb amb
   double* fa[3][14];   // per face direction: adjoints of the left and right face states
   double* bn[3];       // face-field adjoint, gathered per face
   double* bj[3];       // face-field adjoint of the Ohmic terms (atomic accumulation)
-  double* ca[5];       // conserved-field adjoint per cell
-  double* cb[3];       // cell-centred field adjoint per cell
   // B25a and FS18 only.  Per edge direction c, the cell fields reconstructed
   // to the corners in two steps: B25a the cell EMF e_c (field 0), FS18 the
   // cell velocities u_a (field 0) and u_b (field 1).  ec[c][8 f + 4 o + q]:
@@ -74,6 +74,22 @@ __device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
   const int q = t / G.N[0];
   s3[1] = q % G.N[1];
   s3[2] = q / G.N[1];
+}
+
+// The adjoint of D at position pos: vs * v on interior positions, 0 on ghost
+// positions (whatever the caller's buffer holds there).
+__device__ __forceinline__ double vval(const AdjArrays& X, int f, int pos, bool inter) {
+  return inter ? X.vs * X.v[f][pos] : 0.0;
+}
+// Whether the cell s3 (shifted by -1 along axis d if d >= 0) is an interior cell.
+__device__ __forceinline__ bool interior_at(const Geom& G, const int s3[3], int d) {
+  bool in = true;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int q = s3[e] - (e == d ? 1 : 0);
+    in = in && q >= G.g && q < G.g + G.n[e];
+  }
+  return in;
 }
 
 // ---------------------------------------------------------------------------
@@ -111,7 +127,8 @@ __device__ __forceinline__ void etaj_adj(double* const bj[3], const Geom& G, int
 }
 
 // ---------------------------------------------------------------------------
-// Edges: EMF adjoint and the reverse of LD04 + Q26 or B25a corners (edge_emf).
+// Edges: EMF adjoint and the reverse of LD04 + Q26, B25a or FS18 corners
+// (edge_emf), one edge direction (blockIdx.y) per thread.
 // ---------------------------------------------------------------------------
 template <int RECON, int EMF>
 __global__ void __launch_bounds__(kBlock)
@@ -125,20 +142,22 @@ __global__ void __launch_bounds__(kBlock)
   bool inside = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) inside = inside && s3[d] >= G.g && s3[d] <= G.g + G.n[d];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  {
+    const int c = (int)blockIdx.y;  // edge direction
     if (!inside || s3[c] >= G.g + G.n[c]) {
 #pragma unroll
-      for (int q = 0; q < 13; ++q) X.ea[c][q][t] = 0.0;
+      for (int q = 0; q < 12; ++q) X.ea[c][q][t] = 0.0;
 #pragma unroll
       for (int q = 0; q < 8 * corner_fields(EMF); ++q) X.ec[c][q][t] = 0.0;
-      continue;
+      return;
     }
     const int a = (c + 1) % 3, b = (c + 2) % 3;
     const int sa = gstride(G, a), sb = gstride(G, b);
     // the EMF enters the new face fields b_a at t, t - sb and b_b at t, t - sa
-    const double Eb = dt * ((X.v[5 + a][t] - X.v[5 + a][t - sb]) * G.idx[b] -
-                            (X.v[5 + b][t] - X.v[5 + b][t - sa]) * G.idx[a]);
+    const bool i0 = interior_at(G, s3, -1), ia = interior_at(G, s3, a),
+               ib = interior_at(G, s3, b);
+    const double Eb = dt * ((vval(X, 5 + a, t, i0) - vval(X, 5 + a, t - sb, ib)) * G.idx[b] -
+                            (vval(X, 5 + b, t, i0) - vval(X, 5 + b, t - sa, ia)) * G.idx[a]);
     double bv[4], al[4];
     iface_along_d<RECON>(S.b[a], t, sb, bv[0], bv[1]);  // baB, baT
     iface_along_d<RECON>(S.b[b], t, sa, bv[2], bv[3]);  // bbL, bbR
@@ -206,7 +225,6 @@ __global__ void __launch_bounds__(kBlock)
       X.ea[c][4 + q][t] = bb[q];
       X.ea[c][8 + q][t] = alb[q];
     }
-    X.ea[c][12][t] = Eb;
     if (eta > 0.0) etaj_adj(X.bj, G, t, c, eta * Eb);
   }
 }
@@ -252,8 +270,10 @@ __global__ void __launch_bounds__(kBlock)
                      s3[b] < G.g + G.n[b] && s3[c] >= G.g && s3[c] < G.g + G.n[c];
     double Fb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (upd) {
+      const bool i0 = interior_at(G, s3, -1), ia = interior_at(G, s3, a);
 #pragma unroll
-      for (int m = 0; m < 5; ++m) Fb[m] = dt * G.idx[a] * (X.v[m][t] - X.v[m][t - sa]);
+      for (int m = 0; m < 5; ++m)
+        Fb[m] = dt * G.idx[a] * (vval(X, m, t, i0) - vval(X, m, t - sa, ia));
     }
     // edges of direction c read this face's arrays along b, those of
     // direction b read them along c
@@ -706,66 +726,70 @@ int cell_corner_adj(hipStream_t st, const Geom& G, const Work<double>& W, const 
   return CTMHD_OK;
 }
 
-__global__ void __launch_bounds__(kBlock)
-    k_adj_cfinish(Geom G, AdjArrays X, PrimPtrs PB, double gamma, const int* stop) {
-  if (*stop) return;
-  const int t = gidx();
-  if (t >= G.elems) return;
-  int s3[3];
-  decode(G, t, s3);
-  const bool valid = s3[0] < G.N[0] - 1 && s3[1] < G.N[1] - 1 && s3[2] < G.N[2] - 1;
+// Primitive -> conserved adjoints of cell w (Sec. 2.2, eq. state:primitive):
+// ca[5] the conserved fields, cb[3] the cell-centred field; 0 on the last
+// layer of each axis, which has no upper face.
+// p = (gamma - 1) (e - rho |u|^2 / 2 - |bc|^2 / 2), u = m / rho
+__device__ __forceinline__ void cell_cons_adj(const AdjArrays& X, const PrimPtrs& PB, double gm1,
+                                              int w, bool valid, double ca[5], double cb[3]) {
   if (!valid) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) X.ca[m][t] = 0.0;
+    for (int m = 0; m < 5; ++m) ca[m] = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) X.cb[d][t] = 0.0;
+    for (int d = 0; d < 3; ++d) cb[d] = 0.0;
     return;
   }
   double pb[8];
 #pragma unroll
-  for (int v = 0; v < 8; ++v) pb[v] = PB.p[v][t];
-  // p = (gamma - 1) (e - rho |u|^2 / 2 - |bc|^2 / 2), u = m / rho
-  const double rho = X.prim[0][t], p_b = pb[4], gm1 = gamma - 1.0;
-  const double u[3] = {X.prim[1][t], X.prim[2][t], X.prim[3][t]};
-  const double bc[3] = {X.prim[5][t], X.prim[6][t], X.prim[7][t]};
+  for (int v = 0; v < 8; ++v) pb[v] = PB.p[v][w];
+  const double rho = X.prim[0][w], p_b = pb[4];
+  const double u[3] = {X.prim[1][w], X.prim[2][w], X.prim[3][w]};
+  const double bc[3] = {X.prim[5][w], X.prim[6][w], X.prim[7][w]};
   double rb = pb[0] + 0.5 * gm1 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * p_b;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     rb -= pb[1 + d] * u[d] / rho;
-    X.ca[1 + d][t] = pb[1 + d] / rho - gm1 * p_b * u[d];
-    X.cb[d][t] = pb[5 + d] - gm1 * p_b * bc[d];
+    ca[1 + d] = pb[1 + d] / rho - gm1 * p_b * u[d];
+    cb[d] = pb[5 + d] - gm1 * p_b * bc[d];
   }
-  X.ca[0][t] = rb;
-  X.ca[4][t] = gm1 * p_b;
+  ca[0] = rb;
+  ca[4] = gm1 * p_b;
 }
 
-// Face-field adjoint: gathered + Ohmic + half of each adjacent cell's
-// cell-centred adjoint (bc_a = (b_a[lower] + b_a[upper]) / 2).
-__global__ void __launch_bounds__(kBlock) k_adj_bsum(Geom G, AdjArrays X, const int* stop) {
+// The cell-centred field adjoint cb[a] of cell w alone (as cell_cons_adj).
+__device__ __forceinline__ double cell_cb_adj(const AdjArrays& X, const PrimPtrs& PB, double gm1,
+                                              int w, int a, bool valid) {
+  return valid ? PB.p[5 + a][w] - gm1 * PB.p[4][w] * X.prim[5 + a][w] : 0.0;
+}
+
+// Per position: the conserved-field adjoints into ca (cell_cons_adj), and
+// the face-field adjoint bn completed with the Ohmic part (ohm != 0) and half
+// of each adjacent cell's cell-centred adjoint (bc_a = (b_a[lower] +
+// b_a[upper]) / 2).
+__global__ void __launch_bounds__(kBlock)
+    k_adj_cons(Geom G, AdjArrays X, PrimPtrs PB, double gamma, int ohm, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
   int s3[3];
   decode(G, t, s3);
+  bool up[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-    X.bn[a][t] += X.bj[a][t] + 0.5 * (X.cb[a][t] + (s3[a] >= 1 ? X.cb[a][t - G.st[a]] : 0.0));
-}
-
-// Load v = scale * g (interior values; 0 on ghost positions).
-__global__ void __launch_bounds__(kBlock)
-    k_adj_load(Geom G, State v, State g, double scale, const int* stop) {
-  const int t = gidx();
-  if (t >= G.elems) return;
-  int s3[3];
-  decode(G, t, s3);
-  bool inter = !*stop;
+  for (int d = 0; d < 3; ++d) up[d] = s3[d] < G.N[d] - 1;
+  const double gm1 = gamma - 1.0;
+  double ca[5], cb[3];
+  cell_cons_adj(X, PB, gm1, t, up[0] && up[1] && up[2], ca, cb);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) inter = inter && s3[d] >= G.g && s3[d] < G.g + G.n[d];
+  for (int m = 0; m < 5; ++m) X.ca[m][t] = ca[m];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) v.c[m][t] = inter ? scale * g.c[m][t] : 0.0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) v.b[a][t] = inter ? scale * g.b[a][t] : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    // the lower neighbour along a lies on the last layer of no axis other
+    // than those t lies on
+    const double cbm =
+        s3[a] >= 1 ? cell_cb_adj(X, PB, gm1, t - G.st[a], a, up[(a + 1) % 3] && up[(a + 2) % 3])
+                   : 0.0;
+    X.bn[a][t] += (ohm ? X.bj[a][t] : 0.0) + 0.5 * (cb[a] + cbm);
+  }
 }
 
 // out = c2 g2 + c1 g1 + (sum over all periodic copies of the interior
@@ -816,6 +840,15 @@ __global__ void __launch_bounds__(kBlock)
   for (int a = 0; a < 3; ++a) out.b[a][t] = vb[a];
 }
 
+// Start of a reverse from a tape: the recorded dt, and the stop flag, set
+// where that dt is not a positive finite number.
+__global__ void k_adj_tape_dt(const double* tdt, double* dt, int* stop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double v = *tdt;
+  *stop = v > 0.0 && __builtin_isfinite(v) ? 0 : 1;
+  *dt = v;
+}
+
 // Copy of the forward face arrays alpha+, alpha-, u* (3 directions each).
 __global__ void __launch_bounds__(kBlock) k_adj_save9(Geom G, Work<double> W, Work<double> D) {
   const int t = gidx();
@@ -829,7 +862,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_save9(Geom G, Work<double> W, Wo
 }
 
 // Clears the Ohmic accumulators, and the u* adjoints when no edge reads u*
-// (B25a), where the face gathers leave them unwritten.
+// (B25a, FS18), where the face gathers leave them unwritten.  Not launched
+// for Q26 without resistivity: nothing then reads either.
 __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X, int zero_us) {
   const int t = gidx();
   if (t >= G.elems) return;
@@ -843,8 +877,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_zero3(Geom G, AdjArrays X, int z
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-// V, G1, prim, ea, fa, bn, bj, ca, cb, saved face arrays of S0
-constexpr int kAdjArrays = 8 + 8 + 8 + 39 + 42 + 3 + 3 + 5 + 3 + 9;
+// G1, prim, ea, fa, bn, bj, ca, saved face arrays of S0
+constexpr int kAdjArrays = 8 + 8 + 36 + 42 + 3 + 3 + 5 + 9;
 // B25a / FS18: per cell field of the corner reconstructions, 24 corner
 // adjoints and 12 + 12 first-step values and adjoints; 3 cell-field adjoints
 constexpr int kAdjArraysPerField = 24 + 12 + 12;
@@ -863,15 +897,24 @@ int check_adjoint(const ctmhd_params* p) {
   return CTMHD_OK;
 }
 
+// The primitive adjoints of vjp_d (in ea[0][0..7] once its face gathers are done).
+PrimPtrs prim_adjoints(const AdjArrays& X) {
+  PrimPtrs PB;
+  for (int v = 0; v < 8; ++v) PB.p[v] = X.ea[0][v];
+  return PB;
+}
+
 // D'(S)^T v into X.ca / X.bn (ghosted), given the forward face arrays of S in W.
 template <int RECON, int RIEMANN, int EMF>
 int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<double>& W,
           const AdjArrays& X) {
   const int nb = nblocks(G.elems);
-  LAUNCH(k_adj_zero3, nb, G, X, EMF != kQ26 ? 1 : 0);
+  if (EMF != kQ26 || p->eta > 0.0) LAUNCH(k_adj_zero3, nb, G, X, EMF != kQ26 ? 1 : 0);
   LAUNCH(k_adj_prim, nb, S, G, X, p->gamma, W.stop);
   if constexpr (EMF != kQ26) LAUNCH((k_prim<double, EMF>), nb, S, G, W, p->gamma, W.stop);
-  LAUNCH((k_adj_edge<RECON, EMF>), nb, S, G, W, X, p->eta, W.stop);
+  hipLaunchKernelGGL((k_adj_edge<RECON, EMF>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X,
+                     p->eta, W.stop);
+  if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint edges");
   if (const int rc = face_lines<RECON>(st, G, S, W, X, EMF == kQ26, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
   hipLaunchKernelGGL(k_adj_fgather, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
@@ -880,13 +923,11 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
                      p->gamma, W.stop);
   if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint faces");
   // the primitive adjoints go to ea[0][0..7], free once the face gathers are done
-  PrimPtrs PB;
-  for (int v = 0; v < 8; ++v) PB.p[v] = X.ea[0][v];
+  const PrimPtrs PB = prim_adjoints(X);
   if (const int rc = cell_lines<RECON>(st, G, X, PB.p, W.stop)) return rc;
   if constexpr (EMF != kQ26)
     if (const int rc = cell_corner_adj<RECON, EMF>(st, G, W, X, PB, W.stop)) return rc;
-  LAUNCH(k_adj_cfinish, nb, G, X, PB, p->gamma, W.stop);
-  LAUNCH(k_adj_bsum, nb, G, X, W.stop);
+  LAUNCH(k_adj_cons, nb, G, X, PB, p->gamma, p->eta > 0.0 ? 1 : 0, W.stop);
   return CTMHD_OK;
 }
 
@@ -894,7 +935,7 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
 struct AdjCtx {
   Work<double> W, W0;  // forward work arrays; W0: W with the face arrays of S0
   State A, H;          // S0 with ghosts, S1 (the recomputing form)
-  State V, G1;         // stage-2 cotangent / g1
+  State G1;            // g1
   AdjArrays X;
 };
 
@@ -907,19 +948,17 @@ int adj_setup(const ctmhd_params* p, const ctmhd_box& box, void* ws, size_t ws_b
   const size_t e = (size_t)G.elems;
   Carve cv{(char*)ws + box_ws_bytes(box, 8, p)};
   AdjArrays& X = C.X;
-  for (int m = 0; m < 5; ++m) C.V.c[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) C.V.b[a] = cv.take<double>(e);
   for (int m = 0; m < 5; ++m) C.G1.c[m] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) C.G1.b[a] = cv.take<double>(e);
   for (int v = 0; v < 8; ++v) X.prim[v] = cv.take<double>(e);
   for (int c = 0; c < 3; ++c)
-    for (int q = 0; q < 13; ++q) X.ea[c][q] = cv.take<double>(e);
+    for (int q = 0; q < 12; ++q) X.ea[c][q] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a)
     for (int q = 0; q < 14; ++q) X.fa[a][q] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) X.bn[a] = cv.take<double>(e);
   for (int a = 0; a < 3; ++a) X.bj[a] = cv.take<double>(e);
   for (int m = 0; m < 5; ++m) X.ca[m] = cv.take<double>(e);
-  for (int a = 0; a < 3; ++a) X.cb[a] = cv.take<double>(e);
+  X.vs = 1.0;
   constexpr int NF = corner_fields(EMF);
   for (int c = 0; c < 3; ++c) {
     for (int q = 0; q < 16; ++q) X.ec[c][q] = q < 8 * NF ? cv.take<double>(e) : nullptr;
@@ -960,15 +999,17 @@ int adj_reverse(hipStream_t st, const ctmhd_params* p, const Geom& G, AdjCtx& C,
   const int nb = nblocks(G.elems);
   AdjArrays& X = C.X;
   int rc;
-  // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2)
-  LAUNCH(k_adj_load, nb, G, C.V, Gin, 0.5, W1.stop);
-  for (int m = 0; m < 5; ++m) X.v[m] = C.V.c[m];
-  for (int a = 0; a < 3; ++a) X.v[5 + a] = C.V.b[a];
+  // stage 2 in reverse at S1: g1 = g2/2 + D'(S1)^T (g2/2), with g2 read in
+  // place (its interior values)
+  for (int m = 0; m < 5; ++m) X.v[m] = Gin.c[m];
+  for (int a = 0; a < 3; ++a) X.v[5 + a] = Gin.b[a];
+  X.vs = 0.5;
   if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, H, G, W1, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, C.G1, Gin, 0.5, Gin, 0.0, X, W1.stop);
   // stage 1 in reverse at S0: g0 = g2/2 + g1 + D'(S0)^T g1
   for (int m = 0; m < 5; ++m) X.v[m] = C.G1.c[m];
   for (int a = 0; a < 3; ++a) X.v[5 + a] = C.G1.b[a];
+  X.vs = 1.0;
   if ((rc = vjp_d<RECON, RIEMANN, EMF>(st, p, A, G, W0, X))) return rc;
   LAUNCH(k_adj_fold, nb, G, Gout, Gin, 0.5, C.G1, 1.0, X, W1.stop);
   return CTMHD_OK;
@@ -1042,15 +1083,14 @@ int adjoint_box(const ctmhd_params* p_in, const ctmhd_box* box, const double* co
     Gin.b[a] = const_cast<double*>(g_bface[a]);
     Gout.b[a] = g_bface_out[a];
   }
-  LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
   if (tape) {
     // everything the reverse needs was recorded by ctmhd_step_record
     const Tape T = carve_tape(const_cast<void*>(tape), G);
-    LAUNCH(k_dt_final, 1, W.smax, W.nflag, p->cfl, T.dt, W.dt, (double*)nullptr, W.stop,
-           (long long*)nullptr);
+    LAUNCH(k_adj_tape_dt, 1, T.dt, W.dt, W.stop);
     return adj_reverse<RECON, RIEMANN, EMF>(st, p, G, C, with_face_arrays(W, T, 1),
                                             with_face_arrays(C.W0, T, 0), T.S0, T.S1, Gin, Gout);
   }
+  LAUNCH(k_init, 1, W.stop, W.smax, W.nflag);
   State S0;
   for (int m = 0; m < 5; ++m) S0.c[m] = const_cast<double*>(cons_n[m]);
   for (int a = 0; a < 3; ++a) S0.b[a] = const_cast<double*>(bface_n[a]);
