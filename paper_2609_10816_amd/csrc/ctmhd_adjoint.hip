@@ -77,9 +77,12 @@ __device__ __forceinline__ void decode(const Geom& G, int t, int s3[3]) {
 }
 
 // The adjoint of D at position pos: vs * v on interior positions, 0 on ghost
-// positions (whatever the caller's buffer holds there).
+// positions (whatever the caller's buffer holds there; pos lies in the box).
 __device__ __forceinline__ double vval(const AdjArrays& X, int f, int pos, bool inter) {
-  return inter ? X.vs * X.v[f][pos] : 0.0;
+  // the product masked bitwise rather than selected, so that the load is not
+  // moved into a branch of its own (where each load would wait alone)
+  const long long keep = inter ? -1ll : 0ll;
+  return __longlong_as_double(__double_as_longlong(X.vs * X.v[f][pos]) & keep);
 }
 // Whether the cell s3 (shifted by -1 along axis d if d >= 0) is an interior cell.
 __device__ __forceinline__ bool interior_at(const Geom& G, const int s3[3], int d) {
@@ -231,96 +234,100 @@ __global__ void __launch_bounds__(kBlock)
 
 // Adjoint of a face value v[f] read as one of the two arguments of an edge
 // speed max(v[e - st], v[e]) at the edges e = f + st and e = f (axis d).
+// Every value is loaded (indices kept in the box) before any is compared.
 __device__ __forceinline__ double gather_max(const double* V, const double* AB, const Geom& G,
                                              const int s3[3], int f, int d) {
   const int st = G.st[d];
+  const bool hi = s3[d] + 1 < G.N[d], lo = s3[d] >= 1;
+  const double g1 = AB[hi ? f + st : f], g0 = AB[f];
+  const double v0 = V[f], vp = V[hi ? f + st : f], vm = V[lo ? f - st : f];
+  // first argument at edge f + st, second argument at edge f (no
+  // short-circuit, so that no load waits inside a branch)
+  const bool first = hi & (g1 != 0.0) & (v0 >= vp), second = lo & (g0 != 0.0) & !(vm >= v0);
   double acc = 0.0;
-  if (s3[d] + 1 < G.N[d]) {
-    const double g = AB[f + st];
-    if (g != 0.0 && V[f] >= V[f + st]) acc += g;  // first argument at edge f + st
-  }
-  if (s3[d] >= 1) {
-    const double g = AB[f];
-    if (g != 0.0 && !(V[f - st] >= V[f])) acc += g;  // second argument at edge f
-  }
+  acc += first ? g1 : 0.0;
+  acc += second ? g0 : 0.0;
   return acc;
 }
 
-// ---------------------------------------------------------------------------
-// Faces, part 1 (direction blockIdx.y): flux adjoint from v (transposed
-// divergence), the alpha adjoints gathered from the edges that read them, and
-// the Joule flux in reverse.  With the u* adjoint that face_lines leaves in
-// fa[a][7], the inputs of the reverse Riemann solve are then in fa[a][0..7]
-// (5 local flux components, alpha+, alpha-, u*).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-    k_adj_fgather(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
-  if (*stop) return;
-  const int t = gidx();
-  if (t >= G.elems) return;
-  const double dt = *W.dt;
-  int s3[3];
-  decode(G, t, s3);
-  {
-    const int a = (int)blockIdx.y;
-    const int b = (a + 1) % 3, c = (a + 2) % 3;
+// The flux adjoint of face t of direction a from v (transposed divergence;
+// faces read by the update: [g, g+n] along the normal, [g, g+n) across),
+// in the face's local order (normal, two transverse momentum components).
+__device__ __forceinline__ bool face_in_update_adj(const Geom& G, const int s3[3], int a) {
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  return s3[a] >= G.g && s3[a] <= G.g + G.n[a] && s3[b] >= G.g && s3[b] < G.g + G.n[b] &&
+         s3[c] >= G.g && s3[c] < G.g + G.n[c];
+}
+__device__ __forceinline__ void face_flux_adj(const Geom& G, const AdjArrays& X, const int s3[3],
+                                              int t, int a, double dt, double Fl[5]) {
+  double Fb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (face_in_update_adj(G, s3, a)) {
     const int sa = G.st[a];
-    // faces read by the update: [g, g+n] along the normal, [g, g+n) across
-    const bool upd = s3[a] >= G.g && s3[a] <= G.g + G.n[a] && s3[b] >= G.g &&
-                     s3[b] < G.g + G.n[b] && s3[c] >= G.g && s3[c] < G.g + G.n[c];
-    double Fb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (upd) {
-      const bool i0 = interior_at(G, s3, -1), ia = interior_at(G, s3, a);
+    const bool i0 = interior_at(G, s3, -1), ia = interior_at(G, s3, a);
 #pragma unroll
-      for (int m = 0; m < 5; ++m)
-        Fb[m] = dt * G.idx[a] * (vval(X, m, t, i0) - vval(X, m, t - sa, ia));
-    }
-    // edges of direction c read this face's arrays along b, those of
-    // direction b read them along c
-    X.fa[a][0][t] = Fb[0];
-    X.fa[a][1][t] = Fb[1 + a];
-    X.fa[a][2][t] = Fb[1 + b];
-    X.fa[a][3][t] = Fb[1 + c];
-    X.fa[a][4][t] = Fb[4];
-    X.fa[a][5][t] = gather_max(W.ap[a], X.ea[c][8], G, s3, t, b) +
-                    gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
-    X.fa[a][6][t] = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
-                    gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
-    if (eta > 0.0 && upd && Fb[4] != 0.0) {
-      // Joule flux (joule): J = eb (bcl + bcr)/2 - ec (bbl + bbr)/2
-      const double Jb = Fb[4];
-      const int sb = G.st[b], sc = G.st[c], l = t - sa;
-      const double eb = 0.5 * (eta_j<double>(S, G, t, b, eta) + eta_j<double>(S, G, t + sc, b, eta));
-      const double ec = 0.5 * (eta_j<double>(S, G, t, c, eta) + eta_j<double>(S, G, t + sb, c, eta));
-      const double bbl = 0.5 * (S.b[b][l] + S.b[b][l + sb]), bbr = 0.5 * (S.b[b][t] + S.b[b][t + sb]);
-      const double bcl = 0.5 * (S.b[c][l] + S.b[c][l + sc]), bcr = 0.5 * (S.b[c][t] + S.b[c][t + sc]);
-      const double ebb = Jb * 0.5 * (bcl + bcr), ecb = -Jb * 0.5 * (bbl + bbr);
-      const double qc = 0.25 * Jb * eb, qb = -0.25 * Jb * ec;
-      atomicAdd(&X.bj[c][l], qc);
-      atomicAdd(&X.bj[c][l + sc], qc);
-      atomicAdd(&X.bj[c][t], qc);
-      atomicAdd(&X.bj[c][t + sc], qc);
-      atomicAdd(&X.bj[b][l], qb);
-      atomicAdd(&X.bj[b][l + sb], qb);
-      atomicAdd(&X.bj[b][t], qb);
-      atomicAdd(&X.bj[b][t + sb], qb);
-      etaj_adj(X.bj, G, t, b, eta * 0.5 * ebb);
-      etaj_adj(X.bj, G, t + sc, b, eta * 0.5 * ebb);
-      etaj_adj(X.bj, G, t, c, eta * 0.5 * ecb);
-      etaj_adj(X.bj, G, t + sb, c, eta * 0.5 * ecb);
-    }
+    for (int m = 0; m < 5; ++m)
+      Fb[m] = dt * G.idx[a] * (vval(X, m, t, i0) - vval(X, m, t - sa, ia));
   }
+  Fl[0] = Fb[0];
+  Fl[1] = Fb[1 + a];
+  Fl[2] = Fb[1 + (a + 1) % 3];
+  Fl[3] = Fb[1 + (a + 2) % 3];
+  Fl[4] = Fb[4];
 }
 
 // ---------------------------------------------------------------------------
-// Faces, part 2: the Riemann solver in reverse, one face of direction
-// blockIdx.y per thread.  Reads its inputs from fa[a][0..7], writes the
-// adjoints of the left and right face-local states to fa[a][0..13] and adds
-// the normal-field adjoint to bn.
+// Joule flux in reverse (eta > 0), face direction blockIdx.y: the energy
+// flux adjoint onto the face fields of the Ohmic terms (atomic accumulation
+// into bj).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+    k_adj_joule(State S, Geom G, Work<double> W, AdjArrays X, double eta, const int* stop) {
+  if (*stop) return;
+  const int t = gidx();
+  if (t >= G.elems) return;
+  int s3[3];
+  decode(G, t, s3);
+  const int a = (int)blockIdx.y;
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  if (!face_in_update_adj(G, s3, a)) return;
+  double Fl[5];
+  face_flux_adj(G, X, s3, t, a, *W.dt, Fl);
+  if (Fl[4] == 0.0) return;
+  // J = eb (bcl + bcr)/2 - ec (bbl + bbr)/2 (joule)
+  const double Jb = Fl[4];
+  const int sa = G.st[a], sb = G.st[b], sc = G.st[c], l = t - sa;
+  const double eb = 0.5 * (eta_j<double>(S, G, t, b, eta) + eta_j<double>(S, G, t + sc, b, eta));
+  const double ec = 0.5 * (eta_j<double>(S, G, t, c, eta) + eta_j<double>(S, G, t + sb, c, eta));
+  const double bbl = 0.5 * (S.b[b][l] + S.b[b][l + sb]), bbr = 0.5 * (S.b[b][t] + S.b[b][t + sb]);
+  const double bcl = 0.5 * (S.b[c][l] + S.b[c][l + sc]), bcr = 0.5 * (S.b[c][t] + S.b[c][t + sc]);
+  const double ebb = Jb * 0.5 * (bcl + bcr), ecb = -Jb * 0.5 * (bbl + bbr);
+  const double qc = 0.25 * Jb * eb, qb = -0.25 * Jb * ec;
+  atomicAdd(&X.bj[c][l], qc);
+  atomicAdd(&X.bj[c][l + sc], qc);
+  atomicAdd(&X.bj[c][t], qc);
+  atomicAdd(&X.bj[c][t + sc], qc);
+  atomicAdd(&X.bj[b][l], qb);
+  atomicAdd(&X.bj[b][l + sb], qb);
+  atomicAdd(&X.bj[b][t], qb);
+  atomicAdd(&X.bj[b][t + sb], qb);
+  etaj_adj(X.bj, G, t, b, eta * 0.5 * ebb);
+  etaj_adj(X.bj, G, t + sc, b, eta * 0.5 * ebb);
+  etaj_adj(X.bj, G, t, c, eta * 0.5 * ecb);
+  etaj_adj(X.bj, G, t + sb, c, eta * 0.5 * ecb);
+}
+
+// ---------------------------------------------------------------------------
+// Faces: the Riemann solver in reverse, one face of direction blockIdx.y per
+// thread.  Its output adjoints: the flux adjoint from v (face_flux_adj), the
+// alpha adjoints gathered from the edges that read alpha (edges of direction
+// c read this face's arrays along b, those of direction b along c), and the
+// u* adjoint that face_lines leaves in fa[a][7].  Writes the adjoints of the
+// left and right face-local states to fa[a][0..13] and adds the normal-field
+// adjoint to bn.
 // ---------------------------------------------------------------------------
 template <int RECON, int RIEMANN>
 __global__ void __launch_bounds__(kBlock)
-    k_adj_friemann(State S, Geom G, AdjArrays X, double gamma, const int* stop) {
+    k_adj_friemann(State S, Geom G, Work<double> W, AdjArrays X, double gamma, const int* stop) {
   if (*stop) return;
   const int t = gidx();
   if (t >= G.elems) return;
@@ -330,9 +337,12 @@ __global__ void __launch_bounds__(kBlock)
   int s3[3];
   decode(G, t, s3);
   double Fl[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) Fl[m] = X.fa[a][m][t];
-  const double apb = X.fa[a][5][t], amb = X.fa[a][6][t], usb = X.fa[a][7][t];
+  face_flux_adj(G, X, s3, t, a, *W.dt, Fl);
+  const double apb = gather_max(W.ap[a], X.ea[c][8], G, s3, t, b) +
+                     gather_max(W.ap[a], X.ea[b][10], G, s3, t, c);
+  const double amb = gather_max(W.am[a], X.ea[c][9], G, s3, t, b) +
+                     gather_max(W.am[a], X.ea[b][11], G, s3, t, c);
+  const double usb = X.fa[a][7][t];
   constexpr int r = recon_halfwidth(RECON);
   const bool inr = s3[a] >= r + 1 && s3[a] + r < G.N[a] - 1;
   // The stencils of the face-local states, loaded together with the inputs
@@ -917,10 +927,10 @@ int vjp_d(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const W
   if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint edges");
   if (const int rc = face_lines<RECON>(st, G, S, W, X, EMF == kQ26, W.stop)) return rc;
   // both face kernels take the direction from blockIdx.y
-  hipLaunchKernelGGL(k_adj_fgather, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta,
-                     W.stop);
-  hipLaunchKernelGGL((k_adj_friemann<RECON, RIEMANN>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, X,
-                     p->gamma, W.stop);
+  if (p->eta > 0.0)
+    hipLaunchKernelGGL(k_adj_joule, dim3(nb, 3), dim3(kBlock), 0, st, S, G, W, X, p->eta, W.stop);
+  hipLaunchKernelGGL((k_adj_friemann<RECON, RIEMANN>), dim3(nb, 3), dim3(kBlock), 0, st, S, G, W,
+                     X, p->gamma, W.stop);
   if (hipGetLastError() != hipSuccess) return fail(CTMHD_EHIP, "kernel launch failed: adjoint faces");
   // the primitive adjoints go to ea[0][0..7], free once the face gathers are done
   const PrimPtrs PB = prim_adjoints(X);
