@@ -241,6 +241,18 @@ CTMHD_HD void fstate_zero(FState<T>& s) {
   s.rho = s.un = s.ut1 = s.ut2 = s.p = s.bt1 = s.bt2 = T(0);
 }
 
+// d = s where c (per lane), d unchanged elsewhere.
+template <typename T>
+CTMHD_HD void fstate_select(bool c, const FState<T>& s, FState<T>& d) {
+  d.rho = c ? s.rho : d.rho;
+  d.un = c ? s.un : d.un;
+  d.ut1 = c ? s.ut1 : d.ut1;
+  d.ut2 = c ? s.ut2 : d.ut2;
+  d.p = c ? s.p : d.p;
+  d.bt1 = c ? s.bt1 : d.bt1;
+  d.bt2 = c ? s.bt2 : d.bt2;
+}
+
 // ---------------------------------------------------------------------------
 // LLF flux (llf_flux): adjoint of F[5] and of the returned signal speed s.
 // ---------------------------------------------------------------------------
@@ -276,6 +288,38 @@ CTMHD_HD void llf_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamma
   phys_flux_adj(R, bn, gm1inv, URb, FRb, T(0), Rb, bnb);
 }
 
+// Adds the adjoint of the ideal-MHD flux F of side K (K = L where left, R
+// elsewhere; one path, chosen per lane) onto that side's state adjoint.
+template <typename T>
+CTMHD_HD void side_flux_adj(bool left, const FState<T>& L, const FState<T>& R, T bn, T gm1inv,
+                            const T Ub[5], const T Fb[5], FState<T>& Lb, FState<T>& Rb, T& bnb) {
+  const FState<T> K{left ? L.rho : R.rho, left ? L.un : R.un,   left ? L.ut1 : R.ut1,
+                    left ? L.ut2 : R.ut2, left ? L.p : R.p,     left ? L.bt1 : R.bt1,
+                    left ? L.bt2 : R.bt2};
+  FState<T> Kb{left ? Lb.rho : Rb.rho, left ? Lb.un : Rb.un,   left ? Lb.ut1 : Rb.ut1,
+               left ? Lb.ut2 : Rb.ut2, left ? Lb.p : Rb.p,     left ? Lb.bt1 : Rb.bt1,
+               left ? Lb.bt2 : Rb.bt2};
+  phys_flux_adj(K, bn, gm1inv, Ub, Fb, T(0), Kb, bnb);
+  fstate_select(left, Kb, Lb);
+  fstate_select(!left, Kb, Rb);
+}
+
+// x unchanged, as a value the compiler cannot trace to its computation: a
+// forward value formed again from such copies is not merged with the first
+// computation (whose register would then stay live until this use).
+template <typename T>
+CTMHD_HD T opaque(T x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+template <typename T>
+CTMHD_HD FState<T> opaque(const FState<T>& s) {
+  return FState<T>{opaque(s.rho), opaque(s.un), opaque(s.ut1), opaque(s.ut2),
+                   opaque(s.p),   opaque(s.bt1), opaque(s.bt2)};
+}
+
 // ---------------------------------------------------------------------------
 // HLLD flux (hlld_flux): adjoint of F[5] and of the outer speeds SL, SR.
 // ---------------------------------------------------------------------------
@@ -303,10 +347,8 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
   T pTLb = T(0), pTRb = T(0), eLb = T(0), eRb = T(0);
   const T zero5[5] = {T(0), T(0), T(0), T(0), T(0)};
 
-  if (SL > T(0)) {
-    phys_flux_adj(L, bn, gm1inv, zero5, Fb, T(0), Lb, bnb);
-  } else if (SR < T(0)) {
-    phys_flux_adj(R, bn, gm1inv, zero5, Fb, T(0), Rb, bnb);
+  if (SL > T(0) || SR < T(0)) {
+    side_flux_adj(SL > T(0), L, R, bn, gm1inv, zero5, Fb, Lb, Rb, bnb);
   } else {
     // ---- forward of the fan (same operations as hlld_flux) ----
     const T bn2 = bn * bn;
@@ -356,10 +398,8 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
                      !(SM < SR) || !tfinite(SM) || !tfinite(vsL + wsL + bysL + bzsL + esL) ||
                      !tfinite(vsR + wsR + bysR + bzsR + esR);
     if (bad) {
-      if (SL >= T(0)) {
-        phys_flux_adj(L, bn, gm1inv, zero5, Fb, T(0), Lb, bnb);
-      } else if (SR <= T(0)) {
-        phys_flux_adj(R, bn, gm1inv, zero5, Fb, T(0), Rb, bnb);
+      if (SL >= T(0) || SR <= T(0)) {
+        side_flux_adj(SL >= T(0), L, R, bn, gm1inv, zero5, Fb, Lb, Rb, bnb);
       } else {
         // F = (SR FL - SL FR + SL SR (UR - UL)) / (SR - SL)
         T UL[5], FL[5], UR[5], FR[5], pd;
@@ -429,11 +469,10 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
           Uss[3] = rs * wss;
           Uss[4] = LEFT ? esL - sqL * (vbsL - vbss) * sg : esR + sqR * (vbsR - vbss) * sg;
         }
-        T UKb[5], SKbar = T(0), SsKb = T(0);
+        T SKbar = T(0), SsKb = T(0);
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
           SKbar += Fb[m] * (Us[m] - UK[m]);
-          UKb[m] = -Fb[m] * SK;
           if (inner) {
             (LEFT ? UsLb : UsRb)[m] += Fb[m] * (SK - SsK);
             SsKb += Fb[m] * (Uss[m] - Us[m]);
@@ -449,8 +488,10 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
           SRbar += SKbar;
           SsRb += SsKb;
         }
-        phys_flux_adj(K, bn, gm1inv, UKb, Fb, T(0), LEFT ? Lb : Rb, bnb);
       };
+      // the side whose flux and conserved state F takes (FK - SK UK); their
+      // adjoints go onto that side's state at the end of the reverse
+      const bool left = SsL >= T(0) || SM >= T(0);
       if (SsL >= T(0))
         side(std::integral_constant<bool, true>(), false);
       else if (SM >= T(0))
@@ -549,6 +590,38 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       vsRb += UsRb[2] * rsR;
       wsRb += UsRb[3] * rsR;
       esRb += UsRb[4];
+      // The forward values of the fan that the rest of the reverse reads are
+      // formed again here (the same operations on the same values), from
+      // copies the compiler cannot trace, instead of being held in registers
+      // across the reverse.
+      const FState<T> Lo = opaque(L), Ro = opaque(R);
+      const T bno = opaque(bn), SLo = opaque(SL), SRo = opaque(SR), SMo = opaque(SM);
+      T pTL, pTR, eL, eR;
+      {
+        T U[5], F[5];
+        phys_flux(Lo, bno, gm1inv, U, F, pTL);
+        eL = U[4];
+        phys_flux(Ro, bno, gm1inv, U, F, pTR);
+        eR = U[4];
+      }
+      const T bn2r = bno * bno;
+      const T dL = SLo - Lo.un, dR = SRo - Ro.un;
+      const T mL = dL * Lo.rho, mR = dR * Ro.rho;
+      const T iden = trcp(mR - mL);
+      const T NS = mR * Ro.un - mL * Lo.un - pTR + pTL;
+      const T NP = mR * pTL - mL * pTR + mL * mR * (Ro.un - Lo.un);
+      const T pTs = NP * iden;
+      const T dsL = SLo - SMo, dsR = SRo - SMo;
+      const T idsL = trcp(dsL), idsR = trcp(dsR);
+      const T iqL = trcp(mL * dsL - bn2r), iqR = trcp(mR * dsR - bn2r);
+      const T fvL = bno * (SMo - Lo.un) * iqL, fbL = (mL * dL - bn2r) * iqL;
+      const T fvR = bno * (SMo - Ro.un) * iqR, fbR = (mR * dR - bn2r) * iqR;
+      const T vbL = Lo.un * bno + Lo.ut1 * Lo.bt1 + Lo.ut2 * Lo.bt2;
+      const T vbR = Ro.un * bno + Ro.ut1 * Ro.bt1 + Ro.ut2 * Ro.bt2;
+      const T vbsL = SMo * bno + opaque(vsL) * opaque(bysL) + opaque(wsL) * opaque(bzsL);
+      const T vbsR = SMo * bno + opaque(vsR) * opaque(bysR) + opaque(wsR) * opaque(bzsR);
+      const T NeL = dL * eL - pTL * Lo.un + pTs * SMo + bno * (vbL - vbsL);
+      const T NeR = dR * eR - pTR * Ro.un + pTs * SMo + bno * (vbR - vbsR);
       // esL = NeL idsL, NeL = dL UL4 - pTL unL + pTs SM + bn (vbL - vbsL)
       T dLb = T(0), dRb = T(0), pTsb = T(0), idsLb = T(0), idsRb = T(0), vbLb = T(0), vbRb = T(0);
       {
@@ -694,6 +767,14 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
       SRbar += dRb;
       Rb.un -= dRb;
       bnb += T(2) * bn * bn2b;
+      {
+        // F = FK - SK UK + ...: the adjoints of FK and UK onto side K
+        const T SK = left ? SL : SR;
+        T UKb[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) UKb[m] = -Fb[m] * SK;
+        side_flux_adj(left, L, R, bn, gm1inv, UKb, Fb, Lb, Rb, bnb);
+      }
     }
   }
   // SL = min(unL, unR) - cmax, SR = max(unL, unR) + cmax.  At unL = unR the
@@ -711,10 +792,22 @@ CTMHD_HD void hlld_flux_adj(const FState<T>& L, const FState<T>& R, T bn, T gamm
     Lb.un += SRbar;
   else
     Rb.un += SRbar;
-  if (cfL >= cfR)
-    fast_speed_adj(L.rho, L.p, bn, L.bt1, L.bt2, gamma, cmaxb, Lb.rho, Lb.p, bnb, Lb.bt1, Lb.bt2);
-  else
-    fast_speed_adj(R.rho, R.p, bn, R.bt1, R.bt2, gamma, cmaxb, Rb.rho, Rb.p, bnb, Rb.bt1, Rb.bt2);
+  {
+    // cmax = max(cfL, cfR): onto the side that gives it (one path, chosen per lane)
+    const bool cl = cfL >= cfR;
+    T rb = cl ? Lb.rho : Rb.rho, pb = cl ? Lb.p : Rb.p, b1 = cl ? Lb.bt1 : Rb.bt1,
+      b2 = cl ? Lb.bt2 : Rb.bt2;
+    fast_speed_adj(cl ? L.rho : R.rho, cl ? L.p : R.p, bn, cl ? L.bt1 : R.bt1, cl ? L.bt2 : R.bt2,
+                   gamma, cmaxb, rb, pb, bnb, b1, b2);
+    Lb.rho = cl ? rb : Lb.rho;
+    Lb.p = cl ? pb : Lb.p;
+    Lb.bt1 = cl ? b1 : Lb.bt1;
+    Lb.bt2 = cl ? b2 : Lb.bt2;
+    Rb.rho = cl ? Rb.rho : rb;
+    Rb.p = cl ? Rb.p : pb;
+    Rb.bt1 = cl ? Rb.bt1 : b1;
+    Rb.bt2 = cl ? Rb.bt2 : b2;
+  }
   // the energies and total pressures the fan read
   const T eLv[5] = {T(0), T(0), T(0), T(0), eLb}, eRv[5] = {T(0), T(0), T(0), T(0), eRb};
   phys_flux_adj(L, bn, gm1inv, eLv, zero5, pTLb, Lb, bnb);
