@@ -588,7 +588,7 @@ __device__ void faces_x(const State& S, const Geom& G, const Work<T>& W, const F
   bool j_nxt = joule_nb(xn, yn, zn, sn, nb_nxt);
   for (; it < end; ++it) {  // wavefront-uniform trip count (cross-lane shuffles below)
     const CellRaw cur = nxt;
-    const int x = xn, y = yn, z = zn, s = sn;
+    const int x = xn, s = sn;
     double nb[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) nb[k] = nb_nxt[k];
@@ -985,11 +985,13 @@ struct UpdateCfg {
 // fixup = 0: main update (flags, and for stage 1 the CFL maximum into slot 0)
 // fixup = 1: after first-order replacement; runs only if this stage flagged
 //            cells; stage 1 recomputes the CFL maximum into slot 1.
-template <typename T>
-__device__ __forceinline__ void update_item(const State& base, const State& half, const State& out,
-                                            const Geom& G, const Work<T>& W, int stage, int fixup,
-                                            const UpdateCfg& U, long long* diag, int vb, int strips,
-                                            unsigned long long* slots, int slot) {
+// stage and fixup as constants: each form of the update is straight-line
+// code, so that every load of a cell can be issued before the first wait.
+template <typename T, int stage, int fixup>
+__device__ __forceinline__ void update_item_s(const State& base, const State& half,
+                                              const State& out, const Geom& G, const Work<T>& W,
+                                              const UpdateCfg& U, long long* diag, int vb,
+                                              int strips, unsigned long long* slots, int slot) {
   // no fused multiply-adds: the update is memory-bound, and without them its
   // results cannot depend on how a calling kernel is specialised (the main
   // and fix-up calls, the single-box and batched kernels give the same bits)
@@ -1021,6 +1023,16 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) bl[a] = new_face(base, half, G, W, stage, fixup, s, a, dt);
+    // upper faces of this cell, recomputed with the same arithmetic as the
+    // neighbour that owns them (for the flags and the CFL signal); formed
+    // before the stores below, which the compiler cannot move loads across
+    const bool need_state = (U.fofc && !fixup) || stage == 1;
+    double bu[3] = {0.0, 0.0, 0.0};
+    if (need_state) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        bu[a] = new_face(base, half, G, W, stage, fixup, s + gstride(G, a), a, dt);
+    }
     // periodic images: every storage position congruent to this cell
     int mlo[3], mhi[3];
 #pragma unroll
@@ -1038,14 +1050,7 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
 #pragma unroll
           for (int a = 0; a < 3; ++a) out.b[a][sw] = bl[a];
         }
-    const bool need_state = (U.fofc && !fixup) || stage == 1;
     if (need_state) {
-      // upper faces of this cell, recomputed with the same arithmetic as
-      // the neighbour that owns them
-      double bu[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        bu[a] = new_face(base, half, G, W, stage, fixup, s + gstride(G, a), a, dt);
       const double rho = c[0];
       double u[3], bc[3];
       bool nonfin = false;
@@ -1082,6 +1087,24 @@ __device__ __forceinline__ void update_item(const State& base, const State& half
   if (stage == 1) {
     if (fixup && threadIdx.x == 0) W.nflag[2] = 1;
     block_max_to_slots(sigmax, slots, slot);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void update_item(const State& base, const State& half, const State& out,
+                                            const Geom& G, const Work<T>& W, int stage, int fixup,
+                                            const UpdateCfg& U, long long* diag, int vb, int strips,
+                                            unsigned long long* slots, int slot) {
+  if (stage == 0) {
+    if (fixup)
+      update_item_s<T, 0, 1>(base, half, out, G, W, U, diag, vb, strips, slots, slot);
+    else
+      update_item_s<T, 0, 0>(base, half, out, G, W, U, diag, vb, strips, slots, slot);
+  } else {
+    if (fixup)
+      update_item_s<T, 1, 1>(base, half, out, G, W, U, diag, vb, strips, slots, slot);
+    else
+      update_item_s<T, 1, 0>(base, half, out, G, W, U, diag, vb, strips, slots, slot);
   }
 }
 
