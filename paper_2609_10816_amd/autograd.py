@@ -14,8 +14,14 @@ along the FP32-form trajectory, whose states differ from the FP64 ones at the
 FP32 form's error level.  The forward keeps a copy of the state every
 `every` steps; the backward pass restores each checkpoint, recomputes the
 states of that segment and applies the adjoint step by step, newest first.
-Memory: nsteps / every + every states; work: one forward, one forward
-recomputation of all but the checkpointed states, and nsteps adjoint steps.
+In the FP64 form the backward records the steps of each segment again
+(ctmhd_step_record, bitwise the forward's steps) and reverses them from
+their tapes (ctmhd_step_adjoint_tape), so that no adjoint step recomputes
+its first stage.  Memory: nsteps / every states plus the tapes of one
+segment (every x 34 arrays); work: one forward, one recorded recomputation
+of every step, and nsteps tape adjoints.  In the FP32 form the segment's
+states are recomputed in that form and each is reversed by
+ctmhd_step_adjoint.
 
 With `tape=True` (FP64 form) every forward step is a recorded step
 (ctmhd_step_record): it keeps S^n, the first-stage state and the face arrays
@@ -164,11 +170,23 @@ class _Rollout(torch.autograd.Function):
             return box.reverse_tapes(ctx.tapes, gc, gb) + (None,) * 6
         dts, every = ctx.dts, ctx.every
         nseg = len(ctx.checkpoints)
+        fp64 = box.params.precision == ctmhd.PRECISION["fp64"]
         for s in range(nseg - 1, -1, -1):
             first = s * every
             last = min(first + every, ctx.nsteps)
-            # states first .. last-1 of this segment, recomputed from its checkpoint
             box.restore(ctx.checkpoints[s])
+            if fp64:
+                # the segment recomputed as recorded steps (bitwise the steps
+                # of the forward), then reversed from their tapes: no adjoint
+                # step recomputes its first stage
+                tapes = []
+                for i in range(first, last):
+                    tapes.append(box.new_tape())
+                    box.record(dts[i:i + 1], tapes[-1])
+                gc, gb = box.reverse_tapes(tapes, gc, gb)
+                continue
+            # FP32 form: states first .. last-1 of this segment, recomputed in
+            # that form from its checkpoint, each reversed by the FP64 adjoint
             states = [box.snapshot()]
             for i in range(first, last - 1):
                 box.step(dts[i:i + 1], None)
