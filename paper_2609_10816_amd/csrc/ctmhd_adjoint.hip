@@ -250,14 +250,15 @@ __device__ __forceinline__ double gather_max(const double* V, const double* AB, 
   return acc;
 }
 
-// The flux adjoint of face t of direction a from v (transposed divergence;
-// faces read by the update: [g, g+n] along the normal, [g, g+n) across),
-// in the face's local order (normal, two transverse momentum components).
+// Whether the update reads face s3 of direction a: [g, g+n] along the
+// normal, [g, g+n) across.
 __device__ __forceinline__ bool face_in_update_adj(const Geom& G, const int s3[3], int a) {
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   return s3[a] >= G.g && s3[a] <= G.g + G.n[a] && s3[b] >= G.g && s3[b] < G.g + G.n[b] &&
          s3[c] >= G.g && s3[c] < G.g + G.n[c];
 }
+// The flux adjoint of face t of direction a from v (transposed divergence),
+// in the face's local order (normal, two transverse momentum components).
 __device__ __forceinline__ void face_flux_adj(const Geom& G, const AdjArrays& X, const int s3[3],
                                               int t, int a, double dt, double Fl[5]) {
   double Fb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -416,11 +417,9 @@ constexpr int kMaxLineJobs = 8;
 struct LineJobs {
   LineJob j[kMaxLineJobs];
 };
-// Positions per thread of the y / z gathers.
-#ifndef CTMHD_LINE_CHUNK
-#define CTMHD_LINE_CHUNK 8
-#endif
-constexpr int kLineChunk = CTMHD_LINE_CHUNK;
+// Positions per thread of the y / z gathers (4 was slower at 64^3, 16 no
+// faster).
+constexpr int kLineChunk = 8;
 
 template <int RECON>
 __global__ void __launch_bounds__(kBlock) k_line_x(Geom G, LineJobs J, const int* stop) {
