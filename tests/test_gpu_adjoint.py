@@ -553,3 +553,48 @@ def test_rollout_with_tapes_equals_checkpoints(recon):
         ad.kinetic_energy(c, dx).backward()
         grads.append((u.grad.clone(), b.grad.clone()))
     assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+@pytest.mark.parametrize("recon,riemann,eta,emf", TAPE_CONFIGS)
+def test_adjoint_ignores_cotangent_ghosts(recon, riemann, eta, emf):
+    """The adjoint reads only the interior of the caller's cotangent (the ABI
+    says ghosts are ignored): NaN in every ghost position of dL/dS^{n+1}
+    gives the result of zero ghosts, for ctmhd_step_adjoint and for the tape
+    variant (bitwise without resistivity; with it the Ohmic terms accumulate
+    with atomics in no fixed order)."""
+    import torch
+    P, cons, bf, dx, dt, S, tape, ws = _tape_setup(recon, riemann, eta, emf)
+    rng = np.random.default_rng(11)
+    gc = rng.standard_normal(cons.shape)
+    gb = rng.standard_normal(bf.shape)
+    dtt = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    aws = torch.empty(ctmhd.adjoint_workspace_bytes(P, S.box), dtype=torch.uint8, device="cuda")
+    ctmhd.ctmhd_step_record(P, S.box, S.cons, S.bface, dtt, tape, ws)
+    S0 = ctmhd.BoxState.from_numpy(cons, bf, S.ng, dx)
+    results = []
+    for garbage in (False, True):
+        G = ctmhd.BoxState.from_numpy(gc, gb, S.ng, dx)
+        if garbage:
+            sl = G.interior()
+            for t in G.cons + G.bface:
+                keep = t[sl].clone()
+                t.fill_(float("nan"))
+                t[sl] = keep
+        for use_tape in (False, True):
+            O = ctmhd.BoxState(S.n, S.ng, dx)
+            if use_tape:
+                ctmhd.ctmhd_step_adjoint_tape(P, S.box, tape, G.cons, G.bface, O.cons, O.bface,
+                                              aws)
+            else:
+                ctmhd.ctmhd_step_adjoint(P, S0.box, S0.cons, S0.bface, dtt, G.cons, G.bface,
+                                         O.cons, O.bface, aws)
+            torch.cuda.synchronize()
+            results.append(O.to_numpy())
+    for clean, dirty in zip(results[:2], results[2:]):
+        assert np.all(np.isfinite(dirty[0])) and np.all(np.isfinite(dirty[1]))
+        if eta == 0.0:
+            assert np.array_equal(clean[0], dirty[0]) and np.array_equal(clean[1], dirty[1])
+        else:
+            scale = max(np.abs(clean[0]).max(), np.abs(clean[1]).max())
+            err = max(np.abs(clean[0] - dirty[0]).max(), np.abs(clean[1] - dirty[1]).max())
+            assert err <= 1e-12 * scale
