@@ -77,6 +77,26 @@ CTMHD_HD double trsqrt(double x) {
   return 1.0 / __builtin_sqrt(x);
 #endif
 }
+// Square root of the wave-speed terms.  On the GPU for double: the hardware
+// reciprocal square root estimate refined by one Newton step, times x, then
+// one correction by the residual x - s^2 (Markstein's form), within about one
+// unit in the last place for x >= 2^-900; |x| below that gives 0 and x < 0
+// NaN.  The library square root adds the range scaling of denormal operands
+// and the special cases of zero and infinity.  Float and the host: the
+// library square root.
+CTMHD_HD double twsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+  double s = x * y;
+  s = __builtin_fma(0.5 * y, __builtin_fma(-s, s, x), s);
+  return __builtin_fabs(x) < 0x1p-900 ? 0.0 : s;
+#else
+  return __builtin_sqrt(x);
+#endif
+}
+CTMHD_HD float twsqrt(float x) { return __builtin_sqrtf(x); }
 CTMHD_HD float trsqrt(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   const float y = __builtin_amdgcn_rsqf(x);
@@ -239,7 +259,7 @@ CTMHD_HD T fast_speed(T rho, T p, T bn, T bt1, T bt2, T gamma) {
   T a = (gp + bn * bn + bt1 * bt1 + bt2 * bt2) * irho;
   T disc = a * a - T(4) * gp * bn * bn * irho * irho;
   disc = disc > T(0) ? disc : T(0);
-  return tsqrt(T(0.5) * (a + tsqrt(disc)));
+  return twsqrt(T(0.5) * (a + twsqrt(disc)));
 }
 
 // Face-local primitive state: normal velocity un, transverse ut1/ut2 and the
