@@ -91,11 +91,13 @@ typedef struct ctmhd_params {
   int32_t tile;          /* launch-shape knob (0 = defaults): bits 0-7 minimum faces per
                             marching chunk of the face pass (default 32), bits 8-15
                             256-element strips per work item of the batched call (default 1),
-                            bits 16-23 schedule of the batched call (0 one launch per phase,
+                            bit 16 schedule of the batched call (0 one launch per phase,
                             1 one persistent launch per step), bits 19-20 XCD mapping of
                             the edge and update passes of ctmhd_step (0 automatic, 1 each
                             XCD a contiguous range of tiles, 2 all XCDs on bands of one
-                            plane), bits 24-30 x-face row
+                            plane), bits 21-22 Q26 edge kernel of ctmhd_step (0 automatic,
+                            1 one thread per edge position, 2 one thread per column of
+                            edges marching along z; the same values), bits 24-30 x-face row
                             segments per wavefront of the face pass (default 4); other
                             values are rejected with CTMHD_EARG */
   /* Test hook: NULL, or a DEVICE mask of 2 * n0*n1*n2 bytes (stage-1 mask then
@@ -151,8 +153,8 @@ int ctmhd_batch_plan(const ctmhd_params* p, const ctmhd_box* boxes, int nbox, vo
 
 /* Advance `nbox` independent periodic boxes of different sizes by `nsteps`
  * steps.  The work of a step is a list of (phase, box, tile) items in
- * phase-major order, described by the plan.  Two schedules (tile bits
- * 16-23), with bitwise the same result:
+ * phase-major order, described by the plan.  Two schedules (tile bit 16),
+ * with bitwise the same result:
  *   0: one launch per phase over all boxes, workgroup r runs item r; the
  *      launch boundaries order the phases (about 10-14 launches per step);
  *   1: one persistent launch per step whose workgroups claim items from a

@@ -11,8 +11,10 @@
 //                normal with a register window, so that every cell is loaded
 //                and reconstructed once per direction; primitives are formed
 //                on the fly (pressure recovery in FP64)
-//   k_emf3       edge EMFs of the three edge directions (Q26 / B25a / FS18),
-//                LD04 averaging and eta j
+//   k_emf_march  Q26 edge EMFs of the three edge directions with LD04
+//                averaging and eta j, one thread per column of edges marching
+//                up z (the z reconstructions streamed through registers)
+//   k_emf3       the same for B25a / FS18, one thread per edge position
 //   k_update     flux divergence and CT curl, RK combination, periodic ghost
 //                images, invalid-state flags and (second stage) the CFL
 //                maximum of the new state for the next step

@@ -840,6 +840,24 @@ __device__ __forceinline__ T q26_ld04(T uaB, T uaT, T ubL, T ubR, T baB, T baT, 
   return ld04(e0, e1, e2, e3, apa, ama, apb, amb, baB, baT, bbL, bbR);
 }
 
+// The Q26 EMF of the c edge at s from its edge-reconstructed face fields and
+// face velocities: edge wave speeds (eq. emf:alpha-edge), Q26 corners with
+// LD04, plus eta j.
+template <typename T>
+__device__ __forceinline__ T q26_edge(const State& S, const Geom& G, const Work<T>& W, int s, int c,
+                                      T baB, T baT, T bbL, T bbR, T uaB, T uaT, T ubL, T ubR,
+                                      double eta_d) {
+  const int a = (c + 1) % 3, b = (c + 2) % 3;
+  const int sa = gstride(G, a), sb = gstride(G, b);
+  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
+  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
+  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
+  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
+  T eps = q26_ld04(uaB, uaT, ubL, ubR, baB, baT, bbL, bbR, apa, ama, apb, amb);
+  if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
+  return eps;
+}
+
 template <typename T, int RECON, int EMF>
 __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<T>& W, int s, int c,
                                       double eta_d) {
@@ -848,18 +866,16 @@ __device__ __forceinline__ T edge_emf(const State& S, const Geom& G, const Work<
   T baB, baT, bbL, bbR;
   iface_along_d<RECON>(S.b[a], s, sb, baB, baT);
   iface_along_d<RECON>(S.b[b], s, sa, bbL, bbR);
-  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
-  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
-  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
-  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
   if (EMF == kQ26) {
     T uaB, uaT, ubL, ubR;
     iface_along<RECON>(W.us[a], s, sb, uaB, uaT);
     iface_along<RECON>(W.us[b], s, sa, ubL, ubR);
-    T eps = q26_ld04(uaB, uaT, ubL, ubR, baB, baT, bbL, bbR, apa, ama, apb, amb);
-    if (eta_d > 0.0) eps += eta_j<T>(S, G, s, c, (T)eta_d);
-    return eps;
+    return q26_edge<T>(S, G, W, s, c, baB, baT, bbL, bbR, uaB, uaT, ubL, ubR, eta_d);
   }
+  T apa = tmax(W.ap[a][s - sb], W.ap[a][s]);
+  T ama = tmax(W.am[a][s - sb], W.am[a][s]);
+  T apb = tmax(W.ap[b][s - sa], W.ap[b][s]);
+  T amb = tmax(W.am[b][s - sa], W.am[b][s]);
   T e[4];  // LB, RB, LT, RT
   if (EMF == kB25A) {
     T ab[4], ba[4];  // [x_a x_b]: index sa_side + 2 sb_side; [x_b x_a]: sb_side + 2 sa_side
@@ -922,6 +938,73 @@ __global__ void __launch_bounds__(kBlock)
     k_emf3(State S, Geom G, Work<T> W, int stage, double eta_d, int band, const int* stop) {
   if (*stop) return;
   emf_at<T, RECON, EMF>(S, G, W, stage, eta_d, xcd_band_tile(band) * kBlock + (int)threadIdx.x);
+}
+
+// Q26 EMFs of one column of edge positions (x and y fixed, z in [z0, z1)),
+// marching up z.  The four reconstructions along z -- B_y and u*_y at the x
+// edges, B_x and u*_x at the y edges -- run as streams that take one cell
+// and complete one per position, as in the face marches, instead of loading
+// and limiting six cells per edge; the other reconstructions, the wave speeds
+// and eta j are those of edge_emf.  The streamed values are the same
+// arithmetic on the same cells, so the EMFs equal emf_at's.
+template <typename T, int RECON>
+__device__ __forceinline__ void emf_march_q26(const State& S, const Geom& G, const Work<T>& W,
+                                              int stage, double eta_d, int col, int z0, int z1) {
+  constexpr int r = recon_halfwidth(RECON);
+  const int L0 = G.n[0] + 1;
+  const int x = G.g + col % L0, y = G.g + col / L0;
+  const int sy = G.st[1], sz = G.st[2];
+  const bool xe = x < G.g + G.n[0], ye = y < G.g + G.n[1];  // x / y edges exist here
+  const int base = x + sy * y;
+  ReconStream<RECON, T> rs[4];  // B_y, u*_y (x edges), B_x, u*_x (y edges)
+  T lo[4];                      // upper values of the cell below the next position
+  // cells z0-1-r .. z1-1+r; the pushes before cell z0-1+r only fill the
+  // pipelines (their streams' cells lie in the ghost layers)
+  for (int q = z0 - 1 - r; q <= z1 - 1 + r; ++q) {
+    const int sq = base + q * sz;
+    const T v[4] = {(T)S.b[1][sq], W.us[1][sq], (T)S.b[0][sq], W.us[0][sq]};
+    T qm[4], qp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rs[k].push(v[k], qm[k], qp[k]);
+    const int z = q - r;  // the cell completed by this push
+    if (z >= z0) {
+      const int s = base + z * sz;
+      if (xe) {  // a = y (streamed along z), b = z (along y)
+        T bbL, bbR, ubL, ubR;
+        iface_along_d<RECON>(S.b[2], s, sy, bbL, bbR);
+        iface_along<RECON>(W.us[2], s, sy, ubL, ubR);
+        W.E[stage][0][s] =
+            q26_edge<T>(S, G, W, s, 0, lo[0], qm[0], bbL, bbR, lo[1], qm[1], ubL, ubR, eta_d);
+      }
+      if (ye) {  // a = z (along x), b = x (streamed along z)
+        T baB, baT, uaB, uaT;
+        iface_along_d<RECON>(S.b[2], s, 1, baB, baT);
+        iface_along<RECON>(W.us[2], s, 1, uaB, uaT);
+        W.E[stage][1][s] =
+            q26_edge<T>(S, G, W, s, 1, baB, baT, lo[2], qm[2], uaB, uaT, lo[3], qm[3], eta_d);
+      }
+      if (z < G.g + G.n[2]) W.E[stage][2][s] = edge_emf<T, RECON, kQ26>(S, G, W, s, 2, eta_d);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lo[k] = qp[k];
+  }
+}
+
+// Q26 edge pass as z marches: workgroup tile = chunk * ctiles + column tile
+// (columns x fastest, kBlock per tile), z chunks of zc positions.  Through
+// xcd_tile each XCD takes a contiguous run of tiles: a slab of z chunks over
+// a band of rows, so the y neighbours a column reads share its XCD's L2.
+template <typename T, int RECON>
+__global__ void __launch_bounds__(kBlock)
+    k_emf_march(State S, Geom G, Work<T> W, int stage, double eta_d, int ctiles, int zc,
+                const int* stop) {
+  if (*stop) return;
+  const int tile = xcd_tile();
+  const int col = (tile % ctiles) * kBlock + (int)threadIdx.x;
+  if (col >= (G.n[0] + 1) * (G.n[1] + 1)) return;
+  const int z0 = G.g + (tile / ctiles) * zc;
+  const int zend = G.g + G.n[2] + 1;
+  emf_march_q26<T, RECON>(S, G, W, stage, eta_d, col, z0, z0 + zc < zend ? z0 + zc : zend);
 }
 
 // ---------------------------------------------------------------------------

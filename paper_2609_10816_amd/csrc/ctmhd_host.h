@@ -29,8 +29,9 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tuning knobs in ctmhd_params.tile: bits 0-7 minimum faces per marching
 // chunk (default 32), bits 8-15 256-element strips per batched work item
-// (default 1), bits 16-23 batched schedule (0 per phase, 1 persistent),
-// bits 24-30 x-face row segments per wavefront (default 4).
+// (default 1), bit 16 batched schedule (0 per phase, 1 persistent), bits
+// 19-20 XCD mapping, bits 21-22 Q26 edge kernel, bits 24-30 x-face row
+// segments per wavefront (default 4).
 int tile_chunk(const ctmhd_params* p) {
   int c = p->tile & 0xff;
   return c > 0 ? c : 32;
@@ -39,12 +40,15 @@ int tile_strips(const ctmhd_params* p) {
   int s = (p->tile >> 8) & 0xff;
   return s > 0 ? s : 1;
 }
-// bits 16-23: batched schedule, 0 one launch per phase, 1 persistent queue
-int tile_sched(const ctmhd_params* p) { return (p->tile >> 16) & 0xff; }
+// bit 16: batched schedule, 0 one launch per phase, 1 persistent queue
+int tile_sched(const ctmhd_params* p) { return (p->tile >> 16) & 1; }
 // bits 19-20: XCD mapping of the edge and update passes of the single-box
 // call: 0 automatic, 1 each XCD a contiguous range of tiles, 2 all XCDs on
 // bands of the same plane
 int tile_xcd_map(const ctmhd_params* p) { return (p->tile >> 19) & 3; }
+// bits 21-22: Q26 edge kernel of the single-box call: 0 automatic, 1 one
+// thread per edge position, 2 z marches (the same values)
+int tile_emf(const ctmhd_params* p) { return (p->tile >> 21) & 3; }
 
 // Tiles per XCD and chunk of the banded mapping (0: the contiguous mapping)
 // for a pass whose tiles of kBlock positions run over planes of
@@ -80,7 +84,8 @@ int check_params(const ctmhd_params* p) {
   if (p->emf_average != CTMHD_AVG_LD04) return fail(CTMHD_EUNSUPPORTED, "only LD04 averaging is built");
   if (p->precision != CTMHD_FP64 && p->precision != CTMHD_FP32 && p->precision != CTMHD_FP32_R64)
     return fail(CTMHD_EARG, "unknown precision");
-  if (p->tile < 0 || (p->tile & ~0x7f19ffff) != 0 || ((p->tile >> 19) & 3) == 3)
+  if (p->tile < 0 || (p->tile & ~0x7f79ffff) != 0 || ((p->tile >> 19) & 3) == 3 ||
+      ((p->tile >> 21) & 3) == 3)
     return fail(CTMHD_EARG, "tile knob out of range");
   return CTMHD_OK;
 }
@@ -267,14 +272,53 @@ int launch_faces(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, 
   return CTMHD_OK;
 }
 
+// Q26 edge pass: the number of workgroups aimed at (many times the number
+// that run at once, so that the last, partial round of these equally long
+// marches is a small part of the launch) and the shortest z chunk
+constexpr int kEmfTiles = 32768;
+constexpr int kEmfMinChunk = 8;
+
+// Workgroups of the z-marching edge kernel that the device holds at once (0 if
+// the runtime cannot say).  Queried once per instantiation.
+template <typename T, int RECON>
+int emf_march_resident() {
+  static const int n = [] {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_emf_march<T, RECON>, kBlock, 0) !=
+        hipSuccess)
+      return 0;
+    return ncu * per;
+  }();
+  return n;
+}
+
 template <typename T, int RECON>
 int launch_emf(hipStream_t st, const ctmhd_params* p, State S, const Geom& G, const Work<T>& W,
                int stage) {
   const int cnt = (G.n[0] + 1) * (G.n[1] + 1) * (G.n[2] + 1);
   const int band = xcd_band(p, (long long)(G.n[0] + 1) * (G.n[1] + 1), cnt);
-  if (p->emf_compute == CTMHD_EMF_Q26)
-    LAUNCH((k_emf3<T, RECON, kQ26>), nblocks(cnt), S, G, W, stage, p->eta, band, W.stop);
-  else if (p->emf_compute == CTMHD_EMF_B25A)
+  if (p->emf_compute == CTMHD_EMF_Q26) {
+    // z marches: enough chunks for about kEmfTiles workgroups, at least
+    // kEmfMinChunk positions each (the pipelines take 2r + 1 pushes to fill)
+    const int ctiles = nblocks((G.n[0] + 1) * (G.n[1] + 1));
+    const int L2 = G.n[2] + 1;
+    int nch = (kEmfTiles + ctiles - 1) / ctiles;
+    if (nch > L2 / kEmfMinChunk) nch = L2 / kEmfMinChunk;
+    if (nch < 1) nch = 1;
+    const int zc = (L2 + nch - 1) / nch;
+    nch = (L2 + zc - 1) / zc;
+    // automatic: a small box gives the marches less than about one round of
+    // the chip, where the per-edge kernel's many short workgroups fill it
+    // better (the two give the same values)
+    const int m = tile_emf(p);
+    if (m == 2 || (m == 0 && 4LL * ctiles * nch >= 3LL * emf_march_resident<T, RECON>()))
+      LAUNCH((k_emf_march<T, RECON>), ctiles * nch, S, G, W, stage, p->eta, ctiles, zc, W.stop);
+    else
+      LAUNCH((k_emf3<T, RECON, kQ26>), nblocks(cnt), S, G, W, stage, p->eta, band, W.stop);
+  } else if (p->emf_compute == CTMHD_EMF_B25A)
     LAUNCH((k_emf3<T, RECON, kB25A>), nblocks(cnt), S, G, W, stage, p->eta, band, W.stop);
   else
     LAUNCH((k_emf3<T, RECON, kFS18>), nblocks(cnt), S, G, W, stage, p->eta, band, W.stop);

@@ -131,17 +131,21 @@ def make_params(gamma=5.0 / 3.0, eta=0.0, cfl=0.3, recon="plm", riemann="hlld", 
 
 
 XCD_MAP = {"auto": 0, "contiguous": 1, "banded": 2}
+EMF_KERNEL = {"auto": 0, "edge": 1, "march": 2}
 
 
-def make_tile(chunk=0, strips=0, persistent=False, xrows=0, xcd_map="auto"):
+def make_tile(chunk=0, strips=0, persistent=False, xrows=0, xcd_map="auto", emf_kernel="auto"):
     """The ctmhd_params.tile knob: minimum marching chunk, batched strips per
     work item, the batched schedule (per-phase launches or one persistent
     launch per step), the XCD mapping of the single-box edge and update
     passes ("auto", "contiguous": each XCD a contiguous range of tiles,
-    "banded": all XCDs on bands of the same plane) and the x-face row
-    segments per wavefront (0: defaults)."""
+    "banded": all XCDs on bands of the same plane), the single-box Q26 edge
+    kernel ("auto", "edge": one thread per edge position, "march": one thread
+    per column of edges marching along z) and the x-face row segments per
+    wavefront (0: defaults)."""
     return ((int(chunk) & 0xFF) | ((int(strips) & 0xFF) << 8) | ((1 if persistent else 0) << 16)
-            | (XCD_MAP[xcd_map] << 19) | ((int(xrows) & 0x7F) << 24))
+            | (XCD_MAP[xcd_map] << 19) | (EMF_KERNEL[emf_kernel] << 21)
+            | ((int(xrows) & 0x7F) << 24))
 
 
 def make_box(n, ng, dx, offset=0) -> Box:

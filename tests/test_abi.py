@@ -117,7 +117,10 @@ def test_tile_knob_validation():
     for m in ("contiguous", "banded"):
         p = ctmhd.make_params(tile=ctmhd.make_tile(xcd_map=m))
         assert _call_step(p, b) == -1 and b"workspace" in ctmhd.lib().ctmhd_last_error()
-    for bad in (1 << 17, 3 << 19, 1 << 21, -1):
+    for k in ("edge", "march"):
+        p = ctmhd.make_params(tile=ctmhd.make_tile(emf_kernel=k, persistent=True))
+        assert _call_step(p, b) == -1 and b"workspace" in ctmhd.lib().ctmhd_last_error()
+    for bad in (1 << 17, 1 << 18, 3 << 19, 3 << 21, 1 << 23, -1):
         p = ctmhd.make_params(tile=bad)
         assert _call_step(p, b) == -1
         assert b"tile" in ctmhd.lib().ctmhd_last_error()
