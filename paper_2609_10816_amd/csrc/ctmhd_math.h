@@ -77,13 +77,13 @@ CTMHD_HD double trsqrt(double x) {
   return 1.0 / __builtin_sqrt(x);
 #endif
 }
-// Square root of the wave-speed terms.  On the GPU for double: the hardware
-// reciprocal square root estimate refined by one Newton step, times x, then
-// one correction by the residual x - s^2 (Markstein's form), within about one
-// unit in the last place for x >= 2^-900; |x| below that gives 0 and x < 0
-// NaN.  The library square root adds the range scaling of denormal operands
-// and the special cases of zero and infinity.  Float and the host: the
-// library square root.
+// Square root of the wave-speed terms.  On the GPU: the hardware reciprocal
+// square root estimate (refined by one Newton step in double; one unit in the
+// last place in float) times x, then one correction by the residual x - s^2
+// (Markstein's form), within about one unit in the last place for x >= 2^-900
+// (double) or 2^-100 (float); |x| below that gives 0 and x < 0 NaN.  The
+// library square root adds the range scaling of denormal operands and the
+// special cases of zero and infinity.  On the host: the library square root.
 CTMHD_HD double twsqrt(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double y = __builtin_amdgcn_rsq(x);
@@ -96,7 +96,16 @@ CTMHD_HD double twsqrt(double x) {
   return __builtin_sqrt(x);
 #endif
 }
-CTMHD_HD float twsqrt(float x) { return __builtin_sqrtf(x); }
+CTMHD_HD float twsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float y = __builtin_amdgcn_rsqf(x);
+  float s = x * y;
+  s = __builtin_fmaf(0.5f * y, __builtin_fmaf(-s, s, x), s);
+  return __builtin_fabsf(x) < 0x1p-100f ? 0.0f : s;
+#else
+  return __builtin_sqrtf(x);
+#endif
+}
 CTMHD_HD float trsqrt(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   const float y = __builtin_amdgcn_rsqf(x);
