@@ -1,7 +1,7 @@
 """Parity at full size, one step in the launch configuration the benchmark
 times: the 256^3 and 512^3 Mach-2, beta-1, eta = 1e-3 turbulent boxes (PPM +
-HLLD + Q26/B25a + LD04, FP64) and the 128^3 Mach-5 box of the headline
-figure.
+HLLD + Q26/B25a + LD04, FP64; the 512^3 Q26 box is the headline workload)
+and the 128^3 Mach-5 box.
 
 The oracle cannot step 16.7 M cells quickly, but one step only couples a cell
 to its neighbours within a bounded distance (reconstruction half-width 2, the
@@ -45,7 +45,7 @@ def test_full_size_mach2_sampled(emf, n):
 
 
 def test_full_size_128_headline_sampled():
-    """The benchmark's own workload: 128^3 Mach-5 turbulent box, PPM + HLLD +
+    """The 128^3 Mach-5 turbulent box of the benchmark's sweep, PPM + HLLD +
     Q26 + LD04, FP64, flux correction on, CFL 0.3."""
     n = 128
     cons, bf, info = inputs.turbulent_mach5(n)
