@@ -93,7 +93,8 @@ typedef struct ctmhd_params {
                             256-element strips per work item of the batched call (default 1),
                             bit 16 schedule of the batched call (0 one launch per phase,
                             1 one persistent launch per step), bits 19-20 XCD mapping of
-                            the edge and update passes of ctmhd_step (0 automatic, 1 each
+                            the per-position edge and update passes of ctmhd_step (the
+                            z-marching edge pass maps its own tiles; 0 automatic, 1 each
                             XCD a contiguous range of tiles, 2 all XCDs on bands of one
                             plane), bits 21-22 Q26 edge kernel of ctmhd_step (0 automatic,
                             1 one thread per edge position, 2 one thread per column of
